@@ -1,0 +1,169 @@
+/*
+ * dg.h -- C ABI of libdg: matrix-free, sum-factorised application of the
+ * symmetric weighted interior-penalty (SWIPDG) operator for
+ * -div(K grad u) = f on structured hexahedral meshes of the unit cube, with a
+ * tensor-product Q_k Lagrange basis on Gauss-Lobatto nodes, on one AMD
+ * Instinct MI355X (gfx950).
+ *
+ * The operator is the bilinear form of Sec. 4.1 ("Continuous problem and
+ * discretization": element integrals of K grad u . grad v plus the face forms
+ * b_h^e of SWIPDG), with these readings: minus signs on both consistency
+ * terms, jump [w] = w^- - w^+ with the normal from T^- (lower index along the
+ * face normal) to T^+, weighted average and penalty with the harmonic mean
+ * gamma_e = 2 K^- K^+ / (K^- + K^+), penalty sigma_e = penalty_hat / h_d with
+ * h_d = 1/n_d, weak Dirichlet u = 0 on boundary faces (-K grad u.n v -
+ * K grad v.n u + sigma K u v) or periodic wrap in all directions, and
+ * (k+1)-point Gauss quadrature per direction on volumes and faces.
+ *
+ * Vectors use the element-blocked ("DG codepath") layout of Sec. 3.3: the
+ * (k+1)^3 values of element e = ex + nx (ey + ny ez) are contiguous, local
+ * index i1 + n (i2 + n i3) with i1 along x fastest; the kernels read and
+ * write the caller's global vectors in place, without gather/scatter copies.
+ *
+ * Conventions for every call:
+ *   - Pointers named device are device pointers (e.g. from a contiguous
+ *     torch tensor on the GPU); they are borrowed for the call only.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Calls enqueue
+ *     work on it and return without synchronising, except dg_setup and
+ *     dg_cg_solve, which synchronise `stream` before returning.
+ *   - Return values: DG_OK (0), solver outcomes > 0, errors < 0.  Errors
+ *     leave outputs untouched where the arguments were rejected; the message
+ *     is available from dg_last_error.  Nothing throws across the ABI.
+ *   - A context is used by one host thread at a time.
+ *   - The library allocates no device memory: everything it keeps lives in
+ *     the caller's workspace (dg_query_workspace), which must outlive the
+ *     context.
+ */
+#ifndef DG_H
+#define DG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dg_ctx dg_ctx;
+
+enum dg_status {
+  DG_OK = 0,
+  DG_NOT_CONVERGED = 1, /* dg_cg_solve hit maxit; the last iterate is in x            */
+  DG_BREAKDOWN = 2,     /* dg_cg_solve met a non-positive or non-finite CG scalar     */
+  DG_ERR_ARG = -1,      /* null / misaligned / aliased pointer, bad size or option    */
+  DG_ERR_UNSUPPORTED = -2, /* degree or precision not built into the library        */
+  DG_ERR_DEVICE = -3    /* a HIP call failed                                          */
+};
+
+enum dg_precision {
+  DG_F64 = 0,  /* x: double, y: double; FP64 arithmetic                              */
+  DG_F32 = 1,  /* x: float,  y: float;  FP32 arithmetic, FP32 tables and K          */
+  DG_BF16 = 2  /* x: bfloat16 (uint16_t bit patterns), y: float; FP32 accumulation   */
+};
+
+enum dg_bc { DG_BC_DIRICHLET0 = 0, DG_BC_PERIODIC = 1 };
+enum dg_preconditioner { DG_PC_NONE = 0, DG_PC_JACOBI = 1 };
+
+typedef struct {
+  int32_t nx, ny, nz;        /* elements per direction, >= 1                              */
+  int32_t degree;            /* k, 1 <= k <= 7                                             */
+  int32_t bc;                /* enum dg_bc                                                 */
+  int32_t reserved;          /* must be 0                                                  */
+  double penalty_hat;        /* sigma_e * h_d; <= 0 selects 2 (k+1)^2                     */
+  const double* vertices;    /* device, (nx+1)(ny+1)(nz+1) x 3 doubles, x-index fastest:   *
+                              * trilinear elements; NULL = uniform grid (affine elements).  *
+                              * Copied at setup.                                            */
+  const double* theta;       /* device, nx*ny*nz doubles, K_T = exp(theta_T); NULL: K = 1.   *
+                              * Copied at setup.                                            */
+  void* workspace;           /* device, >= dg_query_workspace bytes, 256-byte aligned       */
+  size_t workspace_bytes;
+} dg_mesh_desc;
+
+/* Bytes of device workspace the context for this mesh needs (pointers in the
+ * descriptor are not read).  DG_ERR_ARG / DG_ERR_UNSUPPORTED on bad sizes. */
+int dg_query_workspace(const dg_mesh_desc* mesh, size_t* bytes);
+
+/* Build a context: 1D tables (Gauss-Lobatto nodes, Gauss points, basis values
+ * and derivatives) in FP64 on the host, K = exp(theta) in FP64 and FP32,
+ * geometry, Jacobi diagonal.  Synchronises `stream`.  *out receives the
+ * context (host memory owned by the library until dg_destroy). */
+int dg_setup(const dg_mesh_desc* mesh, dg_ctx** out, void* stream);
+
+/* Replace the coefficient: K_T = exp(theta_T) (device, nx*ny*nz doubles), and
+ * recompute the Jacobi diagonal.  Asynchronous on `stream`. */
+int dg_set_theta(dg_ctx* ctx, const double* theta, void* stream);
+
+/* y = A x (Sec. 3.3 operator application; form of Sec. 4.1).  x and y are
+ * device vectors of N_dof = nx*ny*nz*(k+1)^3 entries of the types given by
+ * `prec` (enum dg_precision); x == y is rejected (DG_ERR_ARG). */
+int dg_apply(dg_ctx* ctx, int prec, const void* x, void* y, void* stream);
+
+/* y = A^T x, evaluated from the transposed 1D operators (equal to A x up to
+ * rounding since the form is symmetric). */
+int dg_apply_transpose(dg_ctx* ctx, int prec, const void* x, void* y, void* stream);
+
+/* g_T = u^T (dA / dtheta_T) v for every element T (device: u, v N_dof
+ * doubles, g nx*ny*nz doubles): the volume form with K_T and each face form
+ * of T with d gamma_e / d theta_T = gamma_e K_other / (K^- + K^+) (boundary:
+ * K_T).  FP64.  Affine meshes only (DG_ERR_UNSUPPORTED on trilinear ones). */
+int dg_dA_dtheta(dg_ctx* ctx, const double* u, const double* v, double* g, void* stream);
+
+/* d = diag(A) (device, N_dof doubles), FP64. */
+int dg_diagonal(dg_ctx* ctx, double* d, void* stream);
+
+/* Physical coordinates of the (k+1)^3 volume Gauss points of every element
+ * (device, N_dof x 3 doubles, element-blocked, point index q1 + n(q2 + n q3)). */
+int dg_quadrature_points(dg_ctx* ctx, double* xq, void* stream);
+
+/* Load vector b_i = int f phi_i by (k+1)-point Gauss quadrature from the
+ * values of f at the points of dg_quadrature_points (device, N_dof doubles). */
+int dg_load_vector(dg_ctx* ctx, const double* fq, double* b, void* stream);
+
+typedef struct {
+  int prec_inner;     /* DG_F64: FP64 PCG.  DG_F32 / DG_BF16: FP64 defect correction  *
+                       * whose inner PCG runs on FP32 vectors with that apply          */
+  int precond;        /* enum dg_preconditioner                                       */
+  int transpose;      /* 1: solve A^T x = b                                            */
+  double rtol;        /* stop when ||b - A x||_2 <= rtol ||b||_2 (true FP64 residual)  */
+  double inner_rtol;  /* inner PCG reduction for prec_inner != DG_F64; <= 0: default   */
+  int maxit;          /* total (inner) CG iterations allowed                          */
+  int max_outer;      /* outer corrections allowed (mixed precision)                  */
+  int check_every;    /* host looks at the device convergence flag every this many     *
+                       * iterations (>= 1; <= 0: default 8)                            */
+  int reserved;
+} dg_cg_opts;
+
+typedef struct {
+  int status;               /* DG_OK, DG_NOT_CONVERGED or DG_BREAKDOWN                  */
+  int iters;                /* CG iterations performed (inner iterations in total)     */
+  int outer_iters;          /* defect-correction steps (0 for FP64 PCG)                */
+  int restarts;             /* FP64 PCG restarts after a failed true-residual check    */
+  double rel_true_residual; /* ||b - A x|| / ||b|| in FP64 at return                   */
+  double seconds;           /* wall time of the call                                  */
+} dg_cg_info;
+
+/* Solve A x = b (or A^T x = b) with Alg. "PCG" of Sec. 2.4 (Jacobi or no
+ * preconditioner; the norm check merged into the <z, r> reduction, so two
+ * reductions per iteration) in FP64, or with FP64 defect correction around
+ * an FP32-vector PCG (prec_inner DG_F32 / DG_BF16).  b and x are device FP64
+ * vectors; x holds x0 on entry and the result on exit.  Synchronises
+ * `stream`; info is always filled when the arguments are accepted. */
+int dg_cg_solve(dg_ctx* ctx, const dg_cg_opts* opts, const double* b, double* x, dg_cg_info* info,
+                void* stream);
+
+/* N_dof, element count and nodes per direction of a context. */
+int64_t dg_num_dofs(const dg_ctx* ctx);
+int64_t dg_num_elements(const dg_ctx* ctx);
+int dg_nodes_per_dir(const dg_ctx* ctx);
+
+/* Release the context's host memory (the caller frees the workspace). */
+void dg_destroy(dg_ctx* ctx);
+
+/* Message of the last failed call on ctx (or of the last failed dg_setup /
+ * dg_query_workspace when ctx is NULL).  Valid until the next call. */
+const char* dg_last_error(const dg_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DG_H */

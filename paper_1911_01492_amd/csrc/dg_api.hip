@@ -1,0 +1,675 @@
+// dg_api.hip -- host side of libdg: the C ABI declared in include/dg.h.
+//
+// Holds the context (mesh, 1D tables, pointers into the caller's workspace),
+// validates arguments, dispatches kernels by (geometry, n, precision) and
+// drives the Krylov solvers: Alg. "PCG" of Sec. 2.4 in FP64 and an FP64
+// defect correction around an FP32-vector PCG.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/dg.h"
+#include "dg_internal.hpp"
+#include "dg_kernels.hpp"
+
+using namespace dg;
+
+struct dg_ctx {
+  dg_mesh_desc desc;
+  int n;                 // nodes per direction
+  int64_t E, ndof;
+  bool trilinear;
+  // workspace regions
+  Tables<double>* tab64;
+  Tables<float>* tab32;
+  double* K64;
+  float* K32;
+  double* vert64;
+  float* vert32;
+  double* dinv64;
+  float* dinv32;
+  double *r64, *p64, *q64;
+  float *r32, *d32, *p32, *q32;
+  uint16_t* p16;
+  double* partials;
+  CgState* st;           // [0]: outer / FP64 solve, [1]: inner solve
+  std::string err;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(dg_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  else g_err = msg;
+  return code;
+}
+
+#define HIP_TRY(c, expr)                                                                    \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess)                                                                   \
+      return fail((c), DG_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));   \
+  } while (0)
+
+// ------------------------------------------------------------------ 1D tables
+// Gauss-Legendre points by the Golub-Welsch method (eigenvalues of the
+// symmetric tridiagonal Jacobi matrix of the Legendre recurrence, weights from
+// the first eigenvector components), and the interior Gauss-Lobatto nodes as
+// the Gauss points of the Jacobi weight (1-x^2) (roots of P^(1,1)_{n-2}, i.e.
+// of P'_{n-1}).  Eigen-decomposition: implicit QL with Wilkinson shifts.
+
+// diag d[0..m), off-diagonal e[1..m) (e[0] unused); on exit d = eigenvalues,
+// z[0..m) = first components of the normalised eigenvectors.
+bool tridiag_ql(std::vector<double>& d, std::vector<double> e, std::vector<double>& z0) {
+  const int m = (int)d.size();
+  std::vector<double> Z((size_t)m * m, 0.0);
+  for (int i = 0; i < m; ++i) Z[(size_t)i * m + i] = 1.0;
+  for (int i = 1; i < m; ++i) e[i - 1] = e[i];
+  if (m > 0) e[m - 1] = 0.0;
+  for (int l = 0; l < m; ++l) {
+    int iter = 0, mm;
+    do {
+      for (mm = l; mm < m - 1; ++mm) {
+        const double dd = std::fabs(d[mm]) + std::fabs(d[mm + 1]);
+        if (std::fabs(e[mm]) <= 1e-17 * dd) break;
+      }
+      if (mm != l) {
+        if (++iter > 60) return false;
+        double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
+        double r = std::hypot(g, 1.0);
+        g = d[mm] - d[l] + e[l] / (g + (g >= 0 ? std::fabs(r) : -std::fabs(r)));
+        double s = 1.0, c = 1.0, p = 0.0;
+        int i;
+        for (i = mm - 1; i >= l; --i) {
+          double f = s * e[i], b = c * e[i];
+          r = std::hypot(f, g);
+          e[i + 1] = r;
+          if (r == 0.0) {
+            d[i + 1] -= p;
+            e[mm] = 0.0;
+            break;
+          }
+          s = f / r;
+          c = g / r;
+          g = d[i + 1] - p;
+          r = (d[i] - g) * s + 2.0 * c * b;
+          p = s * r;
+          d[i + 1] = g + p;
+          g = c * r - b;
+          for (int k = 0; k < m; ++k) {
+            f = Z[(size_t)k * m + i + 1];
+            Z[(size_t)k * m + i + 1] = s * Z[(size_t)k * m + i] + c * f;
+            Z[(size_t)k * m + i] = c * Z[(size_t)k * m + i] - s * f;
+          }
+        }
+        if (r == 0.0 && i >= l) continue;
+        d[l] -= p;
+        e[l] = g;
+        e[mm] = 0.0;
+      }
+    } while (mm != l);
+  }
+  z0.assign(m, 0.0);
+  for (int j = 0; j < m; ++j) z0[j] = Z[j];  // row 0 of the eigenvector matrix
+  return true;
+}
+
+// q-point Gauss-Legendre on [0,1], ascending
+bool gauss01(int q, std::vector<double>& x, std::vector<double>& w) {
+  std::vector<double> d(q, 0.0), e(q, 0.0), z;
+  for (int k = 1; k < q; ++k) e[k] = k / std::sqrt(4.0 * k * k - 1.0);
+  if (!tridiag_ql(d, e, z)) return false;
+  std::vector<int> idx(q);
+  for (int i = 0; i < q; ++i) idx[i] = i;
+  std::sort(idx.begin(), idx.end(), [&](int a, int b) { return d[a] < d[b]; });
+  x.resize(q);
+  w.resize(q);
+  for (int i = 0; i < q; ++i) {
+    x[i] = 0.5 * (d[idx[i]] + 1.0);
+    w[i] = z[idx[i]] * z[idx[i]];  // 2 z^2 on [-1,1], halved on [0,1]
+  }
+  return true;
+}
+
+// n Gauss-Lobatto nodes on [0,1]: 0, the n-2 roots of P^(1,1)_{n-2}, 1
+bool lobatto01(int n, std::vector<double>& x) {
+  const int m = n - 2;
+  x.assign(n, 0.0);
+  x[n - 1] = 1.0;
+  if (m <= 0) return true;
+  std::vector<double> d(m, 0.0), e(m, 0.0), z;
+  for (int k = 1; k < m; ++k) e[k] = std::sqrt((double)k * (k + 2) / ((2.0 * k + 1) * (2.0 * k + 3)));
+  if (!tridiag_ql(d, e, z)) return false;
+  std::sort(d.begin(), d.end());
+  for (int i = 0; i < m; ++i) x[i + 1] = 0.5 * (d[i] + 1.0);
+  return true;
+}
+
+// Lagrange basis on nodes xs, barycentric form: values at points, and the
+// differentiation matrix at the nodes Dn[k][i] = l_i'(xs_k).
+struct Bary {
+  std::vector<double> xs, w;
+  explicit Bary(const std::vector<double>& nodes) : xs(nodes), w(nodes.size(), 1.0) {
+    for (size_t i = 0; i < xs.size(); ++i)
+      for (size_t j = 0; j < xs.size(); ++j)
+        if (i != j) w[i] /= (xs[i] - xs[j]);
+  }
+  void values(double x, std::vector<double>& l) const {
+    const size_t n = xs.size();
+    l.assign(n, 0.0);
+    for (size_t i = 0; i < n; ++i)
+      if (x == xs[i]) {
+        l[i] = 1.0;
+        return;
+      }
+    double den = 0.0;
+    for (size_t i = 0; i < n; ++i) den += w[i] / (x - xs[i]);
+    for (size_t i = 0; i < n; ++i) l[i] = (w[i] / (x - xs[i])) / den;
+  }
+  void diff_matrix(std::vector<double>& Dn) const {
+    const size_t n = xs.size();
+    Dn.assign(n * n, 0.0);
+    for (size_t k = 0; k < n; ++k) {
+      double s = 0.0;
+      for (size_t i = 0; i < n; ++i)
+        if (i != k) {
+          Dn[k * n + i] = (w[i] / w[k]) / (xs[k] - xs[i]);
+          s += Dn[k * n + i];
+        }
+      Dn[k * n + k] = -s;
+    }
+  }
+};
+
+bool build_tables(int n, Tables<double>& T) {
+  std::memset(&T, 0, sizeof(T));
+  std::vector<double> gll, gx, gw;
+  if (!lobatto01(n, gll) || !gauss01(n, gx, gw)) return false;
+  Bary L(gll), G(gx);
+  std::vector<double> Dn, Dg, l;
+  L.diff_matrix(Dn);  // Dn[k][i] = l_i'(gll_k)
+  G.diff_matrix(Dg);  // Gauss-point collocation derivative
+  // B[q][i] = l_i(x_q), D[q][i] = l_i'(x_q) = sum_k l_k(x_q) Dn[k][i]
+  std::vector<double> B((size_t)n * n), D((size_t)n * n, 0.0);
+  for (int q = 0; q < n; ++q) {
+    L.values(gx[q], l);
+    for (int i = 0; i < n; ++i) {
+      B[q * n + i] = l[i];
+      for (int k = 0; k < n; ++k) D[q * n + i] += l[k] * Dn[k * n + i];
+    }
+  }
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      double m = 0.0, s = 0.0;
+      for (int q = 0; q < n; ++q) {
+        m += gw[q] * B[q * n + i] * B[q * n + j];
+        s += gw[q] * D[q * n + i] * D[q * n + j];
+      }
+      T.M[i * kMaxN + j] = m;
+      T.S[i * kMaxN + j] = s;
+      T.B[i * kMaxN + j] = B[i * n + j];
+      T.Dg[i * kMaxN + j] = Dg[i * n + j];
+    }
+  for (int i = 0; i < n; ++i) {
+    T.d0[i] = Dn[0 * n + i];
+    T.d1[i] = Dn[(size_t)(n - 1) * n + i];
+    T.gw[i] = gw[i];
+    T.gx[i] = gx[i];
+  }
+  return true;
+}
+
+void tables_to_f32(const Tables<double>& a, Tables<float>& b) {
+  for (int i = 0; i < kMaxN * kMaxN; ++i) {
+    b.M[i] = (float)a.M[i];
+    b.S[i] = (float)a.S[i];
+    b.B[i] = (float)a.B[i];
+    b.Dg[i] = (float)a.Dg[i];
+  }
+  for (int i = 0; i < kMaxN; ++i) {
+    b.d0[i] = (float)a.d0[i];
+    b.d1[i] = (float)a.d1[i];
+    b.gw[i] = (float)a.gw[i];
+    b.gx[i] = (float)a.gx[i];
+  }
+}
+
+// ------------------------------------------------------------------ workspace
+struct Layout {
+  size_t tab64, tab32, K64, K32, vert64, vert32, dinv64, dinv32, r64, p64, q64, r32, d32, p32, q32, p16,
+      partials, st, total;
+};
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+int check_desc(const dg_mesh_desc* m, dg_ctx* c) {
+  if (!m) return fail(c, DG_ERR_ARG, "mesh descriptor is NULL");
+  if (m->nx < 1 || m->ny < 1 || m->nz < 1) return fail(c, DG_ERR_ARG, "element counts must be >= 1");
+  if (m->degree < 1 || m->degree > kMaxN - 1)
+    return fail(c, DG_ERR_UNSUPPORTED, "degree must be in 1..7");
+  if (m->bc != DG_BC_DIRICHLET0 && m->bc != DG_BC_PERIODIC) return fail(c, DG_ERR_ARG, "unknown bc");
+  if (m->reserved != 0) return fail(c, DG_ERR_ARG, "reserved field must be 0");
+  const double E = (double)m->nx * m->ny * m->nz;
+  const double n3 = std::pow(m->degree + 1.0, 3);
+  if (E * n3 > 4.0e9) return fail(c, DG_ERR_ARG, "mesh too large (N_dof > 4e9)");
+  if ((double)m->nx * m->ny * m->nz > 2.0e9) return fail(c, DG_ERR_ARG, "too many elements");
+  return DG_OK;
+}
+
+Layout layout(const dg_mesh_desc* m) {
+  const int n = m->degree + 1;
+  const int64_t E = (int64_t)m->nx * m->ny * m->nz;
+  const int64_t nd = E * n * n * n;
+  const int64_t nv = (int64_t)(m->nx + 1) * (m->ny + 1) * (m->nz + 1);
+  const bool tri = m->vertices != nullptr;
+  Layout L{};
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o = align256(o + bytes);
+    return at;
+  };
+  L.tab64 = take(sizeof(Tables<double>));
+  L.tab32 = take(sizeof(Tables<float>));
+  L.K64 = take(E * sizeof(double));
+  L.K32 = take(E * sizeof(float));
+  L.vert64 = take(tri ? nv * 3 * sizeof(double) : 0);
+  L.vert32 = take(tri ? nv * 3 * sizeof(float) : 0);
+  L.dinv64 = take(nd * sizeof(double));
+  L.dinv32 = take(nd * sizeof(float));
+  L.r64 = take(nd * sizeof(double));
+  L.p64 = take(nd * sizeof(double));
+  L.q64 = take(nd * sizeof(double));
+  L.r32 = take(nd * sizeof(float));
+  L.d32 = take(nd * sizeof(float));
+  L.p32 = take(nd * sizeof(float));
+  L.q32 = take(nd * sizeof(float));
+  L.p16 = take(nd * sizeof(uint16_t));
+  const int64_t nb = std::max<int64_t>(element_blocks(n, E), kMaxVecBlocks);
+  L.partials = take((size_t)nb * 3 * sizeof(double));
+  L.st = take(2 * sizeof(CgState));
+  L.total = o;
+  return L;
+}
+
+MeshArgs<double> args64(const dg_ctx* c) {
+  MeshArgs<double> m;
+  m.nx = c->desc.nx;
+  m.ny = c->desc.ny;
+  m.nz = c->desc.nz;
+  m.periodic = c->desc.bc == DG_BC_PERIODIC;
+  m.E = c->E;
+  m.hx = 1.0 / c->desc.nx;
+  m.hy = 1.0 / c->desc.ny;
+  m.hz = 1.0 / c->desc.nz;
+  m.sig_hat = c->desc.penalty_hat > 0 ? c->desc.penalty_hat : 2.0 * c->n * c->n;
+  m.K = c->K64;
+  m.vert = c->vert64;
+  m.tab = c->tab64;
+  return m;
+}
+MeshArgs<float> args32(const dg_ctx* c) {
+  MeshArgs<float> m;
+  m.nx = c->desc.nx;
+  m.ny = c->desc.ny;
+  m.nz = c->desc.nz;
+  m.periodic = c->desc.bc == DG_BC_PERIODIC;
+  m.E = c->E;
+  m.hx = (float)(1.0 / c->desc.nx);
+  m.hy = (float)(1.0 / c->desc.ny);
+  m.hz = (float)(1.0 / c->desc.nz);
+  m.sig_hat = (float)(c->desc.penalty_hat > 0 ? c->desc.penalty_hat : 2.0 * c->n * c->n);
+  m.K = c->K32;
+  m.vert = c->vert32;
+  m.tab = c->tab32;
+  return m;
+}
+
+hipError_t apply_any(dg_ctx* c, int prec, int trans, int dot, const void* x, void* y, double* dot_out,
+                     const int* skip, hipStream_t s) {
+  const MeshArgs<double> m64 = args64(c);
+  const MeshArgs<float> m32 = args32(c);
+  unsigned* counter = &c->st[0].counter;
+  if (c->trilinear)
+    return launch_apply_trilinear(c->n, prec, trans, dot, m64, m32, x, y, c->partials, counter, dot_out,
+                                  skip, s);
+  return launch_apply_affine(c->n, prec, trans, dot, m64, m32, x, y, c->partials, counter, dot_out, skip, s);
+}
+
+hipError_t compute_dinv(dg_ctx* c, hipStream_t s) {
+  const MeshArgs<double> m64 = args64(c);
+  hipError_t e = c->trilinear ? launch_diag_trilinear(c->n, m64, c->r64, s)
+                              : launch_diag_affine(c->n, m64, c->r64, s);
+  if (e != hipSuccess) return e;
+  return launch_inv_diag(c->ndof, c->r64, c->dinv64, c->dinv32, s);
+}
+
+bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+}  // namespace
+
+// ====================================================================== C ABI
+extern "C" {
+
+int dg_query_workspace(const dg_mesh_desc* mesh, size_t* bytes) {
+  int rc = check_desc(mesh, nullptr);
+  if (rc != DG_OK) return rc;
+  if (!bytes) return fail(nullptr, DG_ERR_ARG, "bytes is NULL");
+  *bytes = layout(mesh).total;
+  return DG_OK;
+}
+
+int dg_setup(const dg_mesh_desc* mesh, dg_ctx** out, void* stream) {
+  if (!out) return fail(nullptr, DG_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  int rc = check_desc(mesh, nullptr);
+  if (rc != DG_OK) return rc;
+  const Layout L = layout(mesh);
+  if (!mesh->workspace) return fail(nullptr, DG_ERR_ARG, "workspace is NULL");
+  if (!aligned(mesh->workspace, 256)) return fail(nullptr, DG_ERR_ARG, "workspace must be 256-byte aligned");
+  if (mesh->workspace_bytes < L.total)
+    return fail(nullptr, DG_ERR_ARG, "workspace too small: need " + std::to_string(L.total) + " bytes");
+  dg_ctx* c = new (std::nothrow) dg_ctx();
+  if (!c) return fail(nullptr, DG_ERR_ARG, "out of host memory");
+  c->desc = *mesh;
+  c->n = mesh->degree + 1;
+  c->E = (int64_t)mesh->nx * mesh->ny * mesh->nz;
+  c->ndof = c->E * c->n * c->n * c->n;
+  c->trilinear = mesh->vertices != nullptr;
+  char* w = (char*)mesh->workspace;
+  c->tab64 = (Tables<double>*)(w + L.tab64);
+  c->tab32 = (Tables<float>*)(w + L.tab32);
+  c->K64 = (double*)(w + L.K64);
+  c->K32 = (float*)(w + L.K32);
+  c->vert64 = c->trilinear ? (double*)(w + L.vert64) : nullptr;
+  c->vert32 = c->trilinear ? (float*)(w + L.vert32) : nullptr;
+  c->dinv64 = (double*)(w + L.dinv64);
+  c->dinv32 = (float*)(w + L.dinv32);
+  c->r64 = (double*)(w + L.r64);
+  c->p64 = (double*)(w + L.p64);
+  c->q64 = (double*)(w + L.q64);
+  c->r32 = (float*)(w + L.r32);
+  c->d32 = (float*)(w + L.d32);
+  c->p32 = (float*)(w + L.p32);
+  c->q32 = (float*)(w + L.q32);
+  c->p16 = (uint16_t*)(w + L.p16);
+  c->partials = (double*)(w + L.partials);
+  c->st = (CgState*)(w + L.st);
+  hipStream_t s = (hipStream_t)stream;
+  auto bail = [&](int code, const std::string& msg) {
+    g_err = msg;
+    delete c;
+    return code;
+  };
+  Tables<double> t64;
+  Tables<float> t32;
+  if (!build_tables(c->n, t64)) return bail(DG_ERR_ARG, "1D table construction failed");
+  tables_to_f32(t64, t32);
+  hipError_t e;
+#define SETUP_TRY(expr)                                                                   \
+  do {                                                                                    \
+    e = (expr);                                                                           \
+    if (e != hipSuccess) return bail(DG_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e)); \
+  } while (0)
+  SETUP_TRY(hipMemcpyAsync(c->tab64, &t64, sizeof(t64), hipMemcpyHostToDevice, s));
+  SETUP_TRY(hipMemcpyAsync(c->tab32, &t32, sizeof(t32), hipMemcpyHostToDevice, s));
+  SETUP_TRY(hipMemsetAsync(c->st, 0, 2 * sizeof(CgState), s));
+  SETUP_TRY(launch_exp(c->E, mesh->theta, c->K64, c->K32, s));
+  if (c->trilinear) {
+    const int64_t nv3 = (int64_t)(mesh->nx + 1) * (mesh->ny + 1) * (mesh->nz + 1) * 3;
+    SETUP_TRY(hipMemcpyAsync(c->vert64, mesh->vertices, nv3 * sizeof(double), hipMemcpyDeviceToDevice, s));
+    SETUP_TRY(launch_to_f32(nv3, c->vert64, c->vert32, s));
+  }
+  SETUP_TRY(compute_dinv(c, s));
+  SETUP_TRY(hipStreamSynchronize(s));
+#undef SETUP_TRY
+  c->desc.vertices = nullptr;  // copied
+  c->desc.theta = nullptr;
+  *out = c;
+  return DG_OK;
+}
+
+int dg_set_theta(dg_ctx* c, const double* theta, void* stream) {
+  if (!c) return fail(nullptr, DG_ERR_ARG, "ctx is NULL");
+  if (!theta) return fail(c, DG_ERR_ARG, "theta is NULL");
+  hipStream_t s = (hipStream_t)stream;
+  HIP_TRY(c, launch_exp(c->E, theta, c->K64, c->K32, s));
+  HIP_TRY(c, compute_dinv(c, s));
+  return DG_OK;
+}
+
+static int apply_common(dg_ctx* c, int prec, int trans, const void* x, void* y, void* stream) {
+  if (!c) return fail(nullptr, DG_ERR_ARG, "ctx is NULL");
+  if (!x || !y) return fail(c, DG_ERR_ARG, "x or y is NULL");
+  if (x == y) return fail(c, DG_ERR_ARG, "x and y must not alias");
+  if (prec != DG_F64 && prec != DG_F32 && prec != DG_BF16)
+    return fail(c, DG_ERR_UNSUPPORTED, "unknown precision");
+  const size_t ein = prec == DG_F64 ? 8 : (prec == DG_F32 ? 4 : 2);
+  const size_t eout = prec == DG_F64 ? 8 : 4;
+  if (!aligned(x, ein) || !aligned(y, eout)) return fail(c, DG_ERR_ARG, "misaligned x or y");
+  // overlap of the two ranges is aliasing too
+  const char* xb = (const char*)x;
+  const char* yb = (const char*)y;
+  if (xb < yb + c->ndof * eout && yb < xb + c->ndof * ein) return fail(c, DG_ERR_ARG, "x and y overlap");
+  HIP_TRY(c, apply_any(c, prec, trans, 0, x, y, nullptr, nullptr, (hipStream_t)stream));
+  return DG_OK;
+}
+
+int dg_apply(dg_ctx* c, int prec, const void* x, void* y, void* stream) {
+  return apply_common(c, prec, 0, x, y, stream);
+}
+int dg_apply_transpose(dg_ctx* c, int prec, const void* x, void* y, void* stream) {
+  return apply_common(c, prec, 1, x, y, stream);
+}
+
+int dg_dA_dtheta(dg_ctx* c, const double* u, const double* v, double* g, void* stream) {
+  if (!c) return fail(nullptr, DG_ERR_ARG, "ctx is NULL");
+  if (!u || !v || !g) return fail(c, DG_ERR_ARG, "u, v or g is NULL");
+  if (c->trilinear) return fail(c, DG_ERR_UNSUPPORTED, "dA/dtheta is implemented for affine meshes only");
+  HIP_TRY(c, launch_dA_affine(c->n, args64(c), u, v, g, (hipStream_t)stream));
+  return DG_OK;
+}
+
+int dg_diagonal(dg_ctx* c, double* d, void* stream) {
+  if (!c) return fail(nullptr, DG_ERR_ARG, "ctx is NULL");
+  if (!d) return fail(c, DG_ERR_ARG, "d is NULL");
+  const MeshArgs<double> m64 = args64(c);
+  hipStream_t s = (hipStream_t)stream;
+  HIP_TRY(c, c->trilinear ? launch_diag_trilinear(c->n, m64, d, s) : launch_diag_affine(c->n, m64, d, s));
+  return DG_OK;
+}
+
+int dg_quadrature_points(dg_ctx* c, double* xq, void* stream) {
+  if (!c) return fail(nullptr, DG_ERR_ARG, "ctx is NULL");
+  if (!xq) return fail(c, DG_ERR_ARG, "xq is NULL");
+  HIP_TRY(c, launch_quad_points(c->n, args64(c), xq, (hipStream_t)stream));
+  return DG_OK;
+}
+
+int dg_load_vector(dg_ctx* c, const double* fq, double* b, void* stream) {
+  if (!c) return fail(nullptr, DG_ERR_ARG, "ctx is NULL");
+  if (!fq || !b) return fail(c, DG_ERR_ARG, "fq or b is NULL");
+  if (fq == b) return fail(c, DG_ERR_ARG, "fq and b must not alias");
+  HIP_TRY(c, launch_load_vector(c->n, args64(c), fq, b, (hipStream_t)stream));
+  return DG_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ solvers
+namespace {
+
+struct HostState {
+  int done, breakdown, iters;
+  double rr, bb;
+};
+
+int read_state(dg_ctx* c, int which, CgState& hs, hipStream_t s) {
+  HIP_TRY(c, hipMemcpyAsync(&hs, &c->st[which], sizeof(CgState), hipMemcpyDeviceToHost, s));
+  HIP_TRY(c, hipStreamSynchronize(s));
+  return DG_OK;
+}
+
+// FP64 PCG (Alg. PCG) on x; returns iterations and sets breakdown.
+int pcg64(dg_ctx* c, const dg_cg_opts* o, const double* b, double* x, int maxit, int& iters, bool& broke,
+          hipStream_t s) {
+  const int64_t n = c->ndof;
+  const double* dinv = o->precond == DG_PC_JACOBI ? c->dinv64 : nullptr;
+  CgState* st = &c->st[0];
+  const int check = o->check_every > 0 ? o->check_every : 8;
+  HIP_TRY(c, apply_any(c, DG_F64, o->transpose, 0, x, c->q64, nullptr, nullptr, s));
+  HIP_TRY(c, (launch_cg_init<double, double, double, double>(n, b, c->q64, c->r64, c->p64, dinv, o->rtol, st,
+                                                            c->partials, s)));
+  CgState hs;
+  int rc = read_state(c, 0, hs, s);
+  if (rc != DG_OK) return rc;
+  int it = 0;
+  while (!hs.done && it < maxit) {
+    const int chunk = std::min(check, maxit - it);
+    for (int j = 0; j < chunk; ++j, ++it) {
+      const int par = it & 1;
+      HIP_TRY(c, apply_any(c, DG_F64, o->transpose, 1, c->p64, c->q64, &st->pq, &st->done, s));
+      HIP_TRY(c, (launch_cg_update<double, double, double, double>(n, x, c->r64, c->p64, c->q64, dinv, par, st,
+                                                                  c->partials, s)));
+      HIP_TRY(c, (launch_cg_pupdate<double, double, double>(n, c->r64, c->p64, dinv, par, st, s)));
+    }
+    rc = read_state(c, 0, hs, s);
+    if (rc != DG_OK) return rc;
+  }
+  iters = hs.iters;
+  broke = hs.breakdown != 0;
+  return DG_OK;
+}
+
+int true_residual(dg_ctx* c, int transpose, const double* b, const double* x, double& rel, hipStream_t s) {
+  HIP_TRY(c, apply_any(c, DG_F64, transpose, 0, x, c->q64, nullptr, nullptr, s));
+  HIP_TRY(c, launch_resid_norm(c->ndof, b, c->q64, &c->st[0], c->partials, s));
+  CgState hs;
+  int rc = read_state(c, 0, hs, s);
+  if (rc != DG_OK) return rc;
+  rel = hs.true_bb > 0 ? std::sqrt(hs.true_rr / hs.true_bb) : std::sqrt(hs.true_rr);
+  return DG_OK;
+}
+
+// inner PCG on FP32 vectors: A_lo d = r32 to inner_rtol; TP = float or bf16
+template <typename TP>
+int pcg_inner(dg_ctx* c, const dg_cg_opts* o, int prec, double inner_rtol, int maxit, int& iters, bool& broke,
+              hipStream_t s) {
+  const int64_t n = c->ndof;
+  const float* dinv = o->precond == DG_PC_JACOBI ? c->dinv32 : nullptr;
+  CgState* st = &c->st[1];
+  TP* p = prec == DG_BF16 ? (TP*)c->p16 : (TP*)c->p32;
+  const int check = o->check_every > 0 ? o->check_every : 8;
+  HIP_TRY(c, (launch_cg_init_inner<float, TP, float>(n, c->r32, c->d32, p, dinv, inner_rtol, st, c->partials,
+                                                     s)));
+  CgState hs;
+  int rc = read_state(c, 1, hs, s);
+  if (rc != DG_OK) return rc;
+  int it = 0;
+  while (!hs.done && it < maxit) {
+    const int chunk = std::min(check, maxit - it);
+    for (int j = 0; j < chunk; ++j, ++it) {
+      const int par = it & 1;
+      HIP_TRY(c, apply_any(c, prec, o->transpose, 1, p, c->q32, &st->pq, &st->done, s));
+      HIP_TRY(c, (launch_cg_update<float, float, TP, float>(n, c->d32, c->r32, p, c->q32, dinv, par, st,
+                                                            c->partials, s)));
+      HIP_TRY(c, (launch_cg_pupdate<float, TP, float>(n, c->r32, p, dinv, par, st, s)));
+    }
+    rc = read_state(c, 1, hs, s);
+    if (rc != DG_OK) return rc;
+  }
+  iters = hs.iters;
+  broke = hs.breakdown != 0;
+  return DG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dg_cg_solve(dg_ctx* c, const dg_cg_opts* o, const double* b, double* x, dg_cg_info* info, void* stream) {
+  if (!c) return fail(nullptr, DG_ERR_ARG, "ctx is NULL");
+  if (!o || !b || !x || !info) return fail(c, DG_ERR_ARG, "opts, b, x or info is NULL");
+  if (b == x) return fail(c, DG_ERR_ARG, "b and x must not alias");
+  if (o->prec_inner != DG_F64 && o->prec_inner != DG_F32 && o->prec_inner != DG_BF16)
+    return fail(c, DG_ERR_UNSUPPORTED, "unknown inner precision");
+  if (o->precond != DG_PC_NONE && o->precond != DG_PC_JACOBI) return fail(c, DG_ERR_ARG, "unknown preconditioner");
+  if (!(o->rtol > 0) || o->maxit < 1) return fail(c, DG_ERR_ARG, "rtol must be > 0 and maxit >= 1");
+  if (!aligned(b, 8) || !aligned(x, 8)) return fail(c, DG_ERR_ARG, "misaligned b or x");
+  hipStream_t s = (hipStream_t)stream;
+  const auto t0 = std::chrono::steady_clock::now();
+  std::memset(info, 0, sizeof(*info));
+  int total = 0;
+  bool broke = false;
+  double rel = 0.0;
+  int rc;
+  if (o->prec_inner == DG_F64) {
+    // PCG to the recursive criterion, confirmed by the true FP64 residual;
+    // restarted from the current iterate if the check fails
+    for (int attempt = 0;; ++attempt) {
+      int its = 0;
+      rc = pcg64(c, o, b, x, o->maxit - total, its, broke, s);
+      if (rc != DG_OK) return rc;
+      total += its;
+      rc = true_residual(c, o->transpose, b, x, rel, s);
+      if (rc != DG_OK) return rc;
+      if (rel <= o->rtol || broke || total >= o->maxit || attempt >= 10) break;
+      info->restarts++;
+    }
+  } else {
+    const double tin = o->inner_rtol > 0 ? o->inner_rtol : (o->prec_inner == DG_F32 ? 1e-5 : 1e-2);
+    const int max_outer = o->max_outer > 0 ? o->max_outer : 30;
+    int outer = 0;
+    for (;;) {
+      HIP_TRY(c, apply_any(c, DG_F64, o->transpose, 0, x, c->q64, nullptr, nullptr, s));
+      HIP_TRY(c, launch_dc_residual(c->ndof, b, c->q64, c->r32, &c->st[0], c->partials, s));
+      CgState hs;
+      rc = read_state(c, 0, hs, s);
+      if (rc != DG_OK) return rc;
+      rel = hs.bb > 0 ? std::sqrt(hs.rr / hs.bb) : std::sqrt(hs.rr);
+      if (!(rel == rel)) {
+        broke = true;
+        break;
+      }
+      if (rel <= o->rtol || outer >= max_outer || total >= o->maxit) break;
+      int its = 0;
+      bool ib = false;
+      if (o->prec_inner == DG_F32)
+        rc = pcg_inner<float>(c, o, DG_F32, tin, o->maxit - total, its, ib, s);
+      else
+        rc = pcg_inner<uint16_t>(c, o, DG_BF16, tin, o->maxit - total, its, ib, s);
+      if (rc != DG_OK) return rc;
+      total += its;
+      HIP_TRY(c, launch_dc_update(c->ndof, x, c->d32, s));
+      ++outer;
+      if (ib && its == 0) {
+        broke = true;
+        break;
+      }
+    }
+    info->outer_iters = outer;
+  }
+  HIP_TRY(c, hipStreamSynchronize(s));
+  info->iters = total;
+  info->rel_true_residual = rel;
+  info->status = rel <= o->rtol ? DG_OK : (broke ? DG_BREAKDOWN : DG_NOT_CONVERGED);
+  info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return info->status;
+}
+
+int64_t dg_num_dofs(const dg_ctx* c) { return c ? c->ndof : -1; }
+int64_t dg_num_elements(const dg_ctx* c) { return c ? c->E : -1; }
+int dg_nodes_per_dir(const dg_ctx* c) { return c ? c->n : -1; }
+
+void dg_destroy(dg_ctx* c) { delete c; }
+
+const char* dg_last_error(const dg_ctx* c) { return c ? c->err.c_str() : g_err.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,150 @@
+// dg_internal.hpp -- shared definitions of the libdg HIP sources (gfx950).
+//
+// Everything here belongs to the GPU library; nothing is shared with the CPU
+// oracle.  Notation: n = k+1 nodes per direction, N3 = n^3 values per element,
+// element-blocked vectors (Sec. 3.3, DG codepath), local index
+// i1 + n (i2 + n i3) with i1 along x.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dg {
+
+constexpr int kMaxN = 8;  // k <= 7
+
+// 1D reference operators on [0,1] (n GLL nodes, n Gauss points).
+template <typename T>
+struct Tables {
+  T M[kMaxN * kMaxN];   // mass       M_ij = sum_q w_q l_i(x_q) l_j(x_q)
+  T S[kMaxN * kMaxN];   // stiffness  S_ij = sum_q w_q l_i'(x_q) l_j'(x_q)
+  T B[kMaxN * kMaxN];   // interpolation GLL -> Gauss, B_qi = l_i(x_q)
+  T Dg[kMaxN * kMaxN];  // collocation derivative on the Gauss points (Dg B = D)
+  T d0[kMaxN];          // l_i'(0)
+  T d1[kMaxN];          // l_i'(1)
+  T gw[kMaxN];          // Gauss weights on [0,1]
+  T gx[kMaxN];          // Gauss points on [0,1]
+};
+
+// Mesh data passed by value to the kernels.
+template <typename T>
+struct MeshArgs {
+  int nx, ny, nz;
+  int periodic;         // 1: periodic wrap, 0: weak Dirichlet
+  int64_t E;            // elements
+  T hx, hy, hz;         // 1/nx, 1/ny, 1/nz
+  T sig_hat;            // penalty_hat (sigma_e = sig_hat / h_d)
+  const T* K;           // E coefficients K_T = exp(theta_T)
+  const T* vert;        // trilinear meshes: (nx+1)(ny+1)(nz+1) x 3 vertex coordinates
+  const Tables<T>* tab; // 1D tables
+};
+
+// Block -> logical tile: consecutive logical tiles go to the same XCD (the
+// hardware deals workgroups round-robin over the 8 XCDs), so each XCD works on
+// a contiguous slab of elements and its L2 catches the neighbour re-reads.
+__device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t nb) {
+  const int64_t full = (nb / 8) * 8;
+  if (b >= full) return b;
+  return (b % 8) * (full / 8) + b / 8;
+}
+
+// bfloat16 (uint16 storage) <-> float
+__device__ __forceinline__ float bf16_to_f32(uint16_t v) {
+  return __uint_as_float(((uint32_t)v) << 16);
+}
+__device__ __forceinline__ uint16_t f32_to_bf16(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)0x7fc0;  // NaN
+  u += 0x7fffu + ((u >> 16) & 1u);                                // round to nearest even
+  return (uint16_t)(u >> 16);
+}
+
+template <typename TC, typename TIN>
+__device__ __forceinline__ TC load_as(const TIN* p) {
+  return (TC)(*p);
+}
+template <>
+__device__ __forceinline__ float load_as<float, uint16_t>(const uint16_t* p) {
+  return bf16_to_f32(*p);
+}
+template <>
+__device__ __forceinline__ double load_as<double, uint16_t>(const uint16_t* p) {
+  return (double)bf16_to_f32(*p);
+}
+
+// Threads per block of the element kernels (always a multiple of the wave
+// size) and elements per block for n nodes per direction (n^2 line threads
+// per element; the remaining threads of the block idle).
+constexpr int kBlock = 256;
+__host__ __device__ constexpr int elems_per_block(int n) { return kBlock / (n * n); }
+
+// wave64 sum of a double (all 64 lanes must be present)
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Deterministic block reduction of one double: every thread passes its value;
+// thread 0 gets the sum (fixed order: wave sums, then waves in index order).
+template <int BLOCK>
+__device__ double block_sum(double v, double* red /* BLOCK/64 entries */) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) red[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) {
+    for (int i = 0; i < (BLOCK + 63) / 64; ++i) s += red[i];
+  }
+  __syncthreads();
+  return s;
+}
+
+// Grid-level finish of a set of per-block partial sums: the last block to
+// arrive sums the partials in block order (deterministic), calls fin(totals)
+// with thread 0, and resets the arrival counter.  NV values per block.
+template <int NV, int BLOCK, typename Fin>
+__device__ void grid_finish(const double (&mine)[NV], double* partials, unsigned* counter,
+                            int64_t nblocks, int64_t myblock, Fin fin) {
+  __shared__ bool last;
+  __shared__ double red[NV][BLOCK / 64 + 1];
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) partials[myblock * NV + v] = mine[v];
+    __threadfence();
+    unsigned prev = atomicAdd(counter, 1u);
+    last = (prev == (unsigned)(nblocks - 1));
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  double acc[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+  // fixed assignment of partials to threads, then fixed-order tree
+  for (int64_t b = threadIdx.x; b < nblocks; b += BLOCK) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[v] += partials[b * NV + v];
+  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    double s = wave_sum(acc[v]);
+    if (lane == 0) red[v][w] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double tot[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      tot[v] = 0.0;
+      for (int i = 0; i < (BLOCK + 63) / 64; ++i) tot[v] += red[v][i];
+    }
+    fin(tot);
+    *counter = 0u;
+    __threadfence();
+  }
+}
+
+}  // namespace dg

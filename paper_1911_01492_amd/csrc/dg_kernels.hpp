@@ -1,0 +1,74 @@
+// dg_kernels.hpp -- host-side launchers of the libdg kernels.
+#pragma once
+
+#include "dg_internal.hpp"
+
+namespace dg {
+
+// Scalars of one running CG solve, kept in device memory.
+struct CgState {
+  double rho[2];    // <z, r> of the current and of the next iteration (by parity)
+  double pq;        // <p, A p>
+  double rr;        // <r, r>
+  double rr0;       // <r0, r0>
+  double bb;        // <b, b>
+  double tol2;      // squared absolute tolerance on <r, r>
+  double true_rr;   // ||b - A x||^2 of the last true-residual check
+  double true_bb;   // ||b||^2
+  int done;         // 1 once converged or broken down: later kernels of the loop return at once
+  int breakdown;    // 1 on a non-positive / non-finite CG scalar
+  int iters;        // iterations completed
+  int pad0;
+  unsigned counter; // arrival counter of the grid reductions (reset by the last block)
+  unsigned pad1[3];
+};
+
+constexpr int kMaxVecBlocks = 2048;
+
+// grid size of the per-element kernels
+int64_t element_blocks(int n, int64_t E);
+
+// y = A x (trans: A^T x) on affine meshes; prec: 0 f64, 1 f32, 2 bf16 in / f32 out.
+// dot != 0: <x, y> -> *dot_out (deterministic grid reduction through partials/counter).
+// skip: device flag; when nonzero the kernel does nothing.
+hipError_t launch_apply_affine(int n, int prec, int trans, int dot, const MeshArgs<double>& m64,
+                               const MeshArgs<float>& m32, const void* x, void* y, double* partials,
+                               unsigned* counter, double* dot_out, const int* skip, hipStream_t s);
+hipError_t launch_diag_affine(int n, const MeshArgs<double>& m, double* d, hipStream_t s);
+hipError_t launch_dA_affine(int n, const MeshArgs<double>& m, const double* u, const double* v, double* g,
+                            hipStream_t s);
+
+// trilinear meshes
+hipError_t launch_apply_trilinear(int n, int prec, int trans, int dot, const MeshArgs<double>& m64,
+                                  const MeshArgs<float>& m32, const void* x, void* y, double* partials,
+                                  unsigned* counter, double* dot_out, const int* skip, hipStream_t s);
+hipError_t launch_diag_trilinear(int n, const MeshArgs<double>& m, double* d, hipStream_t s);
+
+// geometry / load vector (any mesh)
+hipError_t launch_quad_points(int n, const MeshArgs<double>& m, double* xq, hipStream_t s);
+hipError_t launch_load_vector(int n, const MeshArgs<double>& m, const double* fq, double* b,
+                              hipStream_t s);
+
+// Krylov vector kernels
+template <typename TB, typename TV, typename TP, typename TD>
+hipError_t launch_cg_init(int64_t n, const TB* b, const TV* q, TV* r, TP* p, const TD* dinv, double rtol,
+                          CgState* st, double* partials, hipStream_t s);
+template <typename TV, typename TP, typename TD>
+hipError_t launch_cg_init_inner(int64_t n, const TV* r, TV* d, TP* p, const TD* dinv, double rtol,
+                                CgState* st, double* partials, hipStream_t s);
+template <typename TX, typename TV, typename TP, typename TD>
+hipError_t launch_cg_update(int64_t n, TX* x, TV* r, const TP* p, const TV* q, const TD* dinv, int par,
+                            CgState* st, double* partials, hipStream_t s);
+template <typename TV, typename TP, typename TD>
+hipError_t launch_cg_pupdate(int64_t n, const TV* r, TP* p, const TD* dinv, int par, const CgState* st,
+                             hipStream_t s);
+hipError_t launch_dc_residual(int64_t n, const double* b, const double* q, float* r32, CgState* st,
+                              double* partials, hipStream_t s);
+hipError_t launch_dc_update(int64_t n, double* x, const float* d, hipStream_t s);
+hipError_t launch_resid_norm(int64_t n, const double* b, const double* q, CgState* st, double* partials,
+                             hipStream_t s);
+hipError_t launch_exp(int64_t n, const double* th, double* K64, float* K32, hipStream_t s);
+hipError_t launch_inv_diag(int64_t n, const double* d, double* i64, float* i32, hipStream_t s);
+hipError_t launch_to_f32(int64_t n, const double* a, float* b, hipStream_t s);
+
+}  // namespace dg

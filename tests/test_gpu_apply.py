@@ -1,0 +1,167 @@
+"""GPU parity of the sum-factorised apply (affine elements) against the CPU
+oracle: element by element on the same seeded inputs.  FP64 bar: relative
+l2 error <= 1e-12 (the stated target); FP32 / BF16 errors against the FP64
+oracle are checked against bounds derived from the unit roundoff."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from oracle import oracle as O  # noqa: E402
+from paper_1911_01492_amd import inputs as I  # noqa: E402
+from paper_1911_01492_amd.dg import DGError, DGOperator  # noqa: E402
+from tests.gpu_util import banner, bf16_dev, dev, host, rel_l2  # noqa: E402
+
+BCS = {"dirichlet": O.DIRICHLET, "periodic": O.PERIODIC}
+
+
+def _case(nx, ny, nz, k, bc, seed=0, lognormal=True):
+    E = nx * ny * nz
+    theta = I.theta(E, seed=seed + 1) if lognormal else None
+    m = O.Mesh(nx, ny, nz, k, bc=BCS[bc], theta=theta)
+    op = DGOperator(nx, ny, nz, k, bc, theta=None if theta is None else dev(theta))
+    x = I.uniform_vector(m.ndof, seed=seed)
+    return m, op, x
+
+
+def test_periodic_q2_4_workload():
+    """4^3 periodic Q2, K = 1: full-matrix parity and A 1 = 0."""
+    banner("apply periodic_q2_4")
+    m, op, x = _case(4, 4, 4, 2, "periodic", lognormal=False)
+    A = O.assemble(m)
+    y = host(op.apply(dev(x)))
+    assert rel_l2(y, A @ x) <= 1e-12
+    one = host(op.apply(dev(np.ones(m.ndof))))
+    assert np.abs(one).max() <= 1e-12 * np.abs(A).max()
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5, 6, 7])
+@pytest.mark.parametrize("bc", ["dirichlet", "periodic"])
+def test_small_meshes_all_degrees(k, bc):
+    for mesh in [(1, 1, 1), (2, 1, 1), (2, 2, 1), (2, 2, 2)]:
+        if k >= 6 and mesh == (2, 2, 2):
+            continue
+        banner(f"apply {mesh} k={k} {bc}")
+        m, op, x = _case(*mesh, k, bc, seed=k)
+        A = O.assemble(m)
+        y = host(op.apply(dev(x)))
+        assert rel_l2(y, A @ x) <= 1e-12, (mesh, k, bc)
+
+
+@pytest.mark.parametrize("shape,k", [((7, 5, 3), 3), ((6, 6, 5), 4), ((9, 4, 3), 2), ((5, 3, 4), 1),
+                                     ((3, 4, 3), 5), ((3, 2, 3), 6), ((2, 3, 2), 7)])
+@pytest.mark.parametrize("bc", ["dirichlet", "periodic"])
+def test_ragged_meshes(shape, k, bc):
+    """Several element tiles per launch with a ragged last tile."""
+    banner(f"apply ragged {shape} k={k} {bc}")
+    m, op, x = _case(*shape, k, bc, seed=3)
+    A = O.assemble(m)
+    y = host(op.apply(dev(x)))
+    assert rel_l2(y, A @ x) <= 1e-12
+
+
+def _sample_elements(N, extra_seed=0):
+    E = N ** 3
+    corners = [0, N - 1, N * (N - 1), N * N - 1, E - N * N, E - 1, E // 2 + N // 2]
+    rnd = np.random.default_rng(100 + extra_seed).choice(E, 9, replace=False)
+    return np.unique(np.r_[corners, rnd]).astype(np.int64)
+
+
+@pytest.mark.parametrize("wl", ["dirichlet_q3_32", "mixed_q4_64"])
+def test_full_size_sampled_rows(wl):
+    """Full-size workloads (the benchmark's launch configuration): sampled element
+    rows computed by the oracle one by one."""
+    cfg = I.WORKLOADS[wl]
+    N, k = cfg["N"], cfg["k"]
+    banner(f"apply full {wl}")
+    theta = I.theta(N ** 3)
+    m = O.Mesh(N, N, N, k, theta=theta)
+    op = DGOperator(N, N, N, k, "dirichlet", theta=dev(theta))
+    x = I.uniform_vector(m.ndof)
+    y = host(op.apply(dev(x)))
+    el = _sample_elements(N)
+    ref = O.apply_rows(m, x, el)
+    got = y.reshape(-1, m.n3)[el]
+    assert rel_l2(got, ref) <= 1e-12
+
+
+def test_low_precision_errors():
+    """FP32 and BF16 (FP32 accumulation) applies against the FP64 oracle.
+    FP32: relative error a modest multiple of 2^-24 times the operator's
+    cancellation; BF16: arithmetic error against A x_hat (x_hat = rounded input)
+    like FP32, total error against A x dominated by the input rounding 2^-9."""
+    banner("apply low precision")
+    N, k = 6, 4
+    theta = I.theta(N ** 3)
+    m = O.Mesh(N, N, N, k, theta=theta)
+    op = DGOperator(N, N, N, k, "dirichlet", theta=dev(theta))
+    A = O.assemble(m)
+    x = I.uniform_vector(m.ndof)
+    y_ref = A @ x
+    y32 = host(op.apply(dev(I.to_f32(x), torch.float32), prec="f32"))
+    e32 = rel_l2(y32, y_ref)
+    bits = I.to_bf16_bits(x)
+    xh = I.bf16_bits_to_f64(bits)
+    y16 = host(op.apply(bf16_dev(bits), prec="bf16"))
+    e16_arith = rel_l2(y16, A @ xh)
+    e16_total = rel_l2(y16, y_ref)
+    print(f"fp32 err {e32:.3e}  bf16 arithmetic err {e16_arith:.3e}  bf16 total err {e16_total:.3e}")
+    assert e32 <= 2e-5
+    assert e16_arith <= 2e-5
+    assert e16_total <= 2e-2
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
+def test_transpose(prec):
+    """A^T x equals A x up to rounding (symmetric form), and <y, A x> = <A^T y, x>."""
+    banner(f"transpose {prec}")
+    N, k = 5, 3
+    theta = I.theta(N ** 3)
+    op = DGOperator(N, N, N, k, "dirichlet", theta=dev(theta))
+    nd = op.ndof
+    x = I.uniform_vector(nd, seed=1)
+    yv = I.uniform_vector(nd, seed=2)
+    if prec == "f64":
+        X, Y = dev(x), dev(yv)
+    elif prec == "f32":
+        X, Y = dev(x, torch.float32), dev(yv, torch.float32)
+    else:
+        X, Y = bf16_dev(I.to_bf16_bits(x)), bf16_dev(I.to_bf16_bits(yv))
+    Ax = host(op.apply(X, prec=prec))
+    ATx = host(op.apply(X, prec=prec, transpose=True))
+    ATy = host(op.apply(Y, prec=prec, transpose=True))
+    tol = 1e-14 if prec == "f64" else 1e-6
+    assert rel_l2(ATx, Ax) <= tol
+    xs, ys = host(X), host(Y)
+    lhs, rhs = ys @ Ax, ATy @ xs
+    assert abs(lhs - rhs) <= (1e-13 if prec == "f64" else 1e-5) * np.linalg.norm(ys) * np.linalg.norm(Ax)
+
+
+def test_determinism_and_errors():
+    banner("determinism and argument errors")
+    N, k = 8, 3
+    theta = I.theta(N ** 3)
+    op = DGOperator(N, N, N, k, "dirichlet", theta=dev(theta))
+    x = dev(I.uniform_vector(op.ndof))
+    y1 = op.apply(x).clone()
+    y2 = op.apply(x).clone()
+    assert torch.equal(y1, y2)
+    with pytest.raises(DGError):
+        op.apply(x, out=x)                       # aliasing
+    with pytest.raises(ValueError):
+        op.apply(x[:-1])                          # wrong size
+    with pytest.raises(DGError):
+        DGOperator(2, 2, 2, 8)                    # unsupported degree
+    torch.cuda.synchronize()
+
+
+def test_diagonal():
+    banner("diagonal")
+    for (shape, k, bc) in [((3, 2, 2), 3, "dirichlet"), ((1, 2, 3), 2, "periodic"), ((4, 4, 4), 4, "dirichlet")]:
+        theta = I.theta(int(np.prod(shape)), seed=9)
+        m = O.Mesh(*shape, k, bc=BCS[bc], theta=theta)
+        op = DGOperator(*shape, k, bc, theta=dev(theta))
+        d = host(op.diagonal())
+        assert rel_l2(d, O.assemble(m).diagonal()) <= 1e-13
