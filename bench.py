@@ -1,0 +1,300 @@
+#!/usr/bin/env python3
+"""Benchmark of the matrix-free SWIPDG operator application on one MI355X.
+
+Headline: GDOF/s of the FP64 sum-factorised apply y = A x on the 32^3-element
+Q3 Dirichlet workload with a lognormal coefficient per element (2.10M DOF),
+inputs resident in device memory, K timed back-to-back launches bracketed by
+device synchronisation and HIP events on the launch stream.
+
+The same JSON line also carries the other rows of the hot path, each run once
+(or timed over a few repetitions): FP32 / BF16 applies on the 64^3 Q4
+workload, FP64 PCG and FP64 defect-correction CG (FP32 and BF16 inner solves)
+times to a true relative residual of 1e-10, the adjoint gradient, the
+trilinear Q7 apply, plus the roofline of the dominant kernel and the CPU
+oracle timed on a bounded sample (``cpu_baseline``).
+
+    python bench.py [--gpus 1] [--steps 50] [--warmup 10] [--no-extras] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0        # MI355X HBM3E
+FP64_PEAK_TFS = 78.6         # MI355X FP64 vector / MFMA (dense)
+FP32_PEAK_TFS = 157.3
+
+
+def log(msg: str):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def alg_bytes_per_dof(n: int, in_b: int, out_b: int, k_b: int) -> float:
+    """Algorithmic HBM bytes per DOF of one apply: read x once, write y once,
+    read the element coefficient once (per element = per n^3 DOFs)."""
+    return in_b + out_b + k_b / n ** 3
+
+
+def time_apply(op, x, prec, steps, warmup, torch):
+    y = op.apply(x, prec=prec)
+    for _ in range(warmup):
+        op.apply(x, prec=prec, out=y)
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(steps):
+        op.apply(x, prec=prec, out=y)
+    e1.record(s)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / 1e3, y
+
+
+def cold_apply(op, x, prec, reps, torch):
+    """Per-launch time with the 256 MB last-level cache flushed between launches."""
+    flush = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+    y = op.apply(x, prec=prec)
+    ts = []
+    for _ in range(reps):
+        flush.add_(1.0)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        op.apply(x, prec=prec, out=y)
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1) / 1e3)
+    return float(np.median(ts))
+
+
+def cpu_baseline(seconds: float = 12.0):
+    """The CPU oracle (CSR assembled by brute-force quadrature, OpenMP SpMV in
+    FP64), timed on this host on a bounded sample of the headline workload:
+    the same Q3 / lognormal-K Dirichlet problem on 16^3 elements (1/8 of it)."""
+    from oracle import oracle as O
+    from paper_1911_01492_amd import inputs as I
+    N, k = 16, 3
+    m = O.Mesh(N, N, N, k, theta=I.theta(N ** 3))
+    t0 = time.perf_counter()
+    A = O.assemble(m)
+    t_asm = time.perf_counter() - t0
+    x = I.uniform_vector(m.ndof)
+    O.spmv(A, x)
+    reps, t = 0, 0.0
+    t0 = time.perf_counter()
+    while t < seconds and reps < 1000:
+        O.spmv(A, x)
+        reps += 1
+        t = time.perf_counter() - t0
+    per = t / reps
+    return {"value": m.ndof / per / 1e9, "unit": "GDOF/s", "cores": O.num_threads(), "kind": "oracle",
+            "sample": f"CSR SpMV of the Q3 lognormal-K Dirichlet operator on 16^3 elements "
+                      f"({m.ndof} DOF, {A.nnz} stored entries), {reps} products in {t:.1f} s; "
+                      f"CSR assembly took {t_asm:.1f} s",
+            "assembly_s": t_asm}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only", default="", help="comma list of extras to run (default: all)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the sharding design is described in DESIGN.md).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1911_01492_amd import inputs as I
+    from paper_1911_01492_amd.dg import DGOperator
+
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    dev = lambda a, dt=torch.float64: torch.as_tensor(np.ascontiguousarray(a)).to("cuda", dt)  # noqa: E731
+
+    # ------------------------------------------------------------ headline
+    wl = "dirichlet_q3_32"
+    cfg = I.WORKLOADS[wl]
+    N, k = cfg["N"], cfg["k"]
+    n = k + 1
+    theta = I.theta(N ** 3)
+    op = DGOperator(N, N, N, k, "dirichlet", theta=dev(theta))
+    x = dev(I.uniform_vector(op.ndof))
+    log(f"headline {wl}: {op.ndof} DOF, warmup {args.warmup}, steps {args.steps}")
+    t, y = time_apply(op, x, "f64", args.steps, args.warmup, torch)
+    per = t / args.steps
+    gdofs = op.ndof * args.steps / t / 1e9
+    bpd = alg_bytes_per_dof(n, 8, 8, 8)
+    achieved = bpd * op.ndof / per / 1e9
+    t_cold = cold_apply(op, x, "f64", 10, torch)
+    result = {
+        "metric": "GDOF/s of SIPG apply (fp64 vs fp32/bf16) + CG time-to-1e-10 residual",
+        "value": round(gdofs, 3),
+        "unit": "GDOF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(per * 1e3, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": wl, "elements": f"{N}^3", "degree": k, "ndof": op.ndof,
+                   "bc": "weak Dirichlet", "coefficient": "K=exp(g), g~N(0,1) per element, seed 1",
+                   "x": "U(-1,1), seed 0", "step": "one FP64 operator application y = A x"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "k_apply_affine<4,double,double,double,false,false>",
+                     "alg_bytes_per_dof": round(bpd, 4), "avg_launch_us": round(per * 1e6, 3),
+                     "cold_launch_us": round(t_cold * 1e6, 3),
+                     "cold_achieved": round(bpd * op.ndof / t_cold / 1e9, 1)},
+        "paper_context": {"note": "Table 'Full operator application' (Sec. 3.3), matrix-free problem A, "
+                                  "p=3, 2x Xeon E5-2698v3 (32 cores), problem size not stated",
+                          "dofs_per_s": 5.3775e8},
+    }
+    extras = {}
+    only = set(filter(None, args.only.split(",")))
+
+    def want(name):
+        return not args.no_extras and (not only or name in only)
+
+    # ------------------------------------------------------------ CG on the headline workload
+    if want("cg_q3_32"):
+        xq = op.quadrature_points()
+        fq = 3 * math.pi ** 2 * torch.sin(math.pi * xq[:, 0]) * torch.sin(math.pi * xq[:, 1]) * \
+            torch.sin(math.pi * xq[:, 2])
+        b = op.load_vector(fq.contiguous())
+        for prec in ("f64", "f32", "bf16"):
+            op.cg_solve(b, prec_inner=prec, rtol=1e-10)  # warm
+            u, info = op.cg_solve(b, prec_inner=prec, rtol=1e-10)
+            extras[f"cg_{prec}_q3_32"] = info
+            log(f"cg {prec} q3_32: {info}")
+        del u, b, fq, xq
+    del op, x, y
+    torch.cuda.empty_cache()
+
+    # ------------------------------------------------------------ mixed precision workload (64^3 Q4)
+    if want("mixed_q4_64"):
+        wl3 = "mixed_q4_64"
+        c3 = I.WORKLOADS[wl3]
+        N3_, k3 = c3["N"], c3["k"]
+        n3 = k3 + 1
+        th3 = I.theta(N3_ ** 3)
+        op3 = DGOperator(N3_, N3_, N3_, k3, "dirichlet", theta=dev(th3))
+        xh = I.uniform_vector(op3.ndof)
+        bits = I.to_bf16_bits(xh)
+        X = {"f64": dev(xh), "f32": dev(I.to_f32(xh), torch.float32),
+             "bf16": torch.from_numpy(bits.astype(np.int16)).view(torch.bfloat16).cuda()}
+        del bits
+        ref = None
+        for prec, (ib, ob) in (("f64", (8, 8)), ("f32", (4, 4)), ("bf16", (2, 4))):
+            tt, yy = time_apply(op3, X[prec], prec, 20, 5, torch)
+            per3 = tt / 20
+            kb = 8 if prec == "f64" else 4
+            bpd3 = alg_bytes_per_dof(n3, ib, ob, kb)
+            ent = {"gdofs": round(op3.ndof / per3 / 1e9, 3), "ms": round(per3 * 1e3, 4),
+                   "achieved_GBs": round(bpd3 * op3.ndof / per3 / 1e9, 1),
+                   "frac_hbm": round(bpd3 * op3.ndof / per3 / 1e9 / HBM_PEAK_GBS, 4)}
+            if prec == "f64":
+                ref = yy.clone()
+            else:
+                ent["rel_err_vs_gpu_f64"] = float(torch.linalg.norm(yy.double() - ref) / torch.linalg.norm(ref))
+            extras[f"apply_{prec}_{wl3}"] = ent
+            log(f"apply {prec} {wl3}: {ent}")
+            del yy
+        del X, ref
+        torch.cuda.empty_cache()
+        b3 = dev(I.uniform_vector(op3.ndof, seed=I.S_B))
+        for prec in ("f64", "f32", "bf16"):
+            u3, info = op3.cg_solve(b3, prec_inner=prec, rtol=1e-10)
+            extras[f"cg_{prec}_{wl3}"] = info
+            log(f"cg {prec} {wl3}: {info}")
+            if prec == "f64":
+                u64 = u3
+            else:
+                extras[f"cg_{prec}_{wl3}"]["rel_diff_vs_f64_solution"] = float(
+                    torch.linalg.norm(u3 - u64) / torch.linalg.norm(u64))
+        del op3, b3, u3, u64
+        torch.cuda.empty_cache()
+
+    # ------------------------------------------------------------ adjoint gradient (32^3 Q3)
+    if want("adjoint_q3_32"):
+        from paper_1911_01492_amd.dg import DGSolve
+        c4 = I.WORKLOADS["adjoint_q3_32"]
+        N4, k4 = c4["N"], c4["k"]
+        op4 = DGOperator(N4, N4, N4, k4, "dirichlet", theta=dev(I.theta(N4 ** 3)))
+        xq = op4.quadrature_points()
+        fq = 3 * math.pi ** 2 * torch.sin(math.pi * xq[:, 0]) * torch.sin(math.pi * xq[:, 1]) * \
+            torch.sin(math.pi * xq[:, 2])
+        b4 = op4.load_vector(fq.contiguous())
+        opts = {"rtol": 1e-12}
+        th_obs = dev(I.theta(N4 ** 3, seed=I.S_OBS))
+        u_obs = DGSolve.apply(th_obs, b4, op4, opts) + dev(I.noise(op4.ndof))
+        theta4 = dev(I.theta(N4 ** 3)).requires_grad_(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        u = DGSolve.apply(theta4, b4, op4, opts)
+        loss = 0.5 * torch.sum((u - u_obs) ** 2)
+        loss.backward()
+        torch.cuda.synchronize()
+        tg = time.perf_counter() - t0
+        lam = torch.ones_like(u)
+        tt = time.perf_counter()
+        for _ in range(10):
+            op4.dA_dtheta(lam, u)
+        torch.cuda.synchronize()
+        tda = (time.perf_counter() - tt) / 10
+        extras["adjoint_q3_32"] = {"loss": float(loss), "grad_norm": float(theta4.grad.norm()),
+                                   "forward_plus_gradient_s": round(tg, 4), "dA_dtheta_ms": round(tda * 1e3, 4),
+                                   "dA_dtheta_gdofs": round(op4.ndof / tda / 1e9, 3)}
+        log(f"adjoint: {extras['adjoint_q3_32']}")
+        del op4
+        torch.cuda.empty_cache()
+
+    # ------------------------------------------------------------ trilinear Q7 (48^3)
+    if want("trilinear_q7_48"):
+        c5 = I.WORKLOADS["trilinear_q7_48"]
+        N5, k5 = c5["N"], c5["k"]
+        try:
+            op5 = DGOperator(N5, N5, N5, k5, "dirichlet", theta=dev(I.theta(N5 ** 3)),
+                             vertices=dev(I.perturbed_vertices(N5)))
+            x5 = I.uniform_vector(op5.ndof)
+            for prec, X5 in (("f64", dev(x5)), ("f32", dev(I.to_f32(x5), torch.float32))):
+                tt, yy = time_apply(op5, X5, prec, 10, 3, torch)
+                extras[f"apply_{prec}_trilinear_q7_48"] = {"gdofs": round(op5.ndof * 10 / tt / 1e9, 3),
+                                                           "ms": round(tt / 10 * 1e3, 4)}
+                log(f"trilinear {prec}: {extras[f'apply_{prec}_trilinear_q7_48']}")
+                del yy
+            del op5
+        except Exception as ex:  # reported, not hidden
+            extras["trilinear_q7_48"] = {"error": str(ex)}
+            log(f"trilinear: {ex}")
+        torch.cuda.empty_cache()
+
+    if extras:
+        result["extras"] = extras
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        result["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

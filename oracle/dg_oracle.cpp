@@ -787,12 +787,29 @@ double oracle_l2_error(const oracle_mesh* m, const double* uh, int fkind, const 
  * replaced by dK_T/dtheta_T = K_T, each face matrix of T with gamma_e replaced
  * by d gamma_e / d theta_T = gamma_e K_other / (K^- + K^+) (interior) or
  * d K_T / d theta_T = K_T (boundary). */
+int oracle_dA_dtheta_elems(const oracle_mesh* m, const double* u, const double* vv, int64_t nsel,
+                           const int64_t* elems, double* gout);
+
 int oracle_dA_dtheta(const oracle_mesh* m, const double* u, const double* vv, double* gout) {
+  if (!valid(m)) return -1;
+  const int64_t E = (int64_t)m->nx * m->ny * m->nz;
+  std::vector<int64_t> all(E);
+  for (int64_t i = 0; i < E; ++i) all[i] = i;
+  return oracle_dA_dtheta_elems(m, u, vv, E, all.data(), gout);
+}
+
+/* The same for the listed elements only: gout[s] = g_{elems[s]}. */
+int oracle_dA_dtheta_elems(const oracle_mesh* m, const double* u, const double* vv, int64_t nsel,
+                           const int64_t* elems, double* gout) {
   if (!valid(m)) return -1;
   Mesh M = make_mesh(m);
   const int n3 = M.n3;
+  for (int64_t s = 0; s < nsel; ++s)
+    if (elems[s] < 0 || elems[s] >= M.E) return -1;
 #pragma omp parallel for schedule(dynamic, 1)
-  for (int64_t id = 0; id < M.E; ++id) {
+  for (int64_t sel = 0; sel < nsel; ++sel) {
+    const int64_t id = elems[sel];
+
     int e[3];
     elem_coords(M, id, e);
     Geo g;
@@ -835,10 +852,11 @@ int oracle_dA_dtheta(const oracle_mesh* m, const double* u, const double* vv, do
           }
         }
       }
-    gout[id] = acc;
+    gout[sel] = acc;
   }
   return 0;
 }
+
 
 /* The same gradient by the complex-step derivative: theta_T -> theta_T + i h,
  * h = 1e-30, and g_T = Im(u^T A(theta + i h e_T) v) / h over the local

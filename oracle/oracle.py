@@ -82,6 +82,7 @@ def _load():
     lib.oracle_l2_error.restype = _c_dbl
     lib.oracle_dA_dtheta.argtypes = [P(_CMesh), _c_vp, _c_vp, _c_vp]
     lib.oracle_dA_dtheta_cs.argtypes = [P(_CMesh), _c_vp, _c_vp, _c_vp]
+    lib.oracle_dA_dtheta_elems.argtypes = [P(_CMesh), _c_vp, _c_vp, _c_i64, _c_vp, _c_vp]
     _lib = lib
     return lib
 
@@ -245,6 +246,19 @@ def dA_dtheta(mesh: Mesh, u: np.ndarray, v: np.ndarray, complex_step: bool = Fal
     fn = lib.oracle_dA_dtheta_cs if complex_step else lib.oracle_dA_dtheta
     if fn(ctypes.byref(cm), _ptr(u), _ptr(v), _ptr(g)) != 0:
         raise ValueError("invalid mesh")
+    return g
+
+
+def dA_dtheta_elems(mesh: Mesh, u: np.ndarray, v: np.ndarray, elems) -> np.ndarray:
+    """g_T = u^T (dA/dtheta_T) v for the listed elements only."""
+    lib = _load()
+    cm = mesh.c()
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    el = np.ascontiguousarray(np.asarray(elems, dtype=np.int64))
+    g = np.zeros(el.size)
+    if lib.oracle_dA_dtheta_elems(ctypes.byref(cm), _ptr(u), _ptr(v), el.size, _ptr(el), _ptr(g)) != 0:
+        raise ValueError("invalid mesh or element index")
     return g
 
 

@@ -215,6 +215,7 @@ bool build_tables(int n, Tables<double>& T) {
       T.M[i * kMaxN + j] = m;
       T.S[i * kMaxN + j] = s;
       T.B[i * kMaxN + j] = B[i * n + j];
+      T.D[i * kMaxN + j] = D[i * n + j];
       T.Dg[i * kMaxN + j] = Dg[i * n + j];
     }
   for (int i = 0; i < n; ++i) {
@@ -231,6 +232,7 @@ void tables_to_f32(const Tables<double>& a, Tables<float>& b) {
     b.M[i] = (float)a.M[i];
     b.S[i] = (float)a.S[i];
     b.B[i] = (float)a.B[i];
+    b.D[i] = (float)a.D[i];
     b.Dg[i] = (float)a.Dg[i];
   }
   for (int i = 0; i < kMaxN; ++i) {

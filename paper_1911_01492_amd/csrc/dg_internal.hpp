@@ -19,6 +19,7 @@ struct Tables {
   T M[kMaxN * kMaxN];   // mass       M_ij = sum_q w_q l_i(x_q) l_j(x_q)
   T S[kMaxN * kMaxN];   // stiffness  S_ij = sum_q w_q l_i'(x_q) l_j'(x_q)
   T B[kMaxN * kMaxN];   // interpolation GLL -> Gauss, B_qi = l_i(x_q)
+  T D[kMaxN * kMaxN];   // derivative at the Gauss points, D_qi = l_i'(x_q)
   T Dg[kMaxN * kMaxN];  // collocation derivative on the Gauss points (Dg B = D)
   T d0[kMaxN];          // l_i'(0)
   T d1[kMaxN];          // l_i'(1)

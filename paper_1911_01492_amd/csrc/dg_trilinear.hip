@@ -1,15 +1,576 @@
-// dg_trilinear.hip -- SWIPDG apply on trilinear elements (placeholder launchers).
+// dg_trilinear.hip -- SWIPDG apply on trilinear hexahedra (curved meshes,
+// "problem C" with multilinear geometries of Sec. 3.3), Jacobians computed
+// on the fly at every volume and face quadrature point.
+//
+// Volume (sum factorisation through the Gauss points):
+//   v    = (B (x) B (x) B) u                      interpolation GLL -> Gauss
+//   gr_d = Dg along axis d applied to v            reference gradient
+//   g    = G_q gr,  G_q = w_q K |det J| J^{-1} J^{-T} = w_q K adj(J) adj(J)^T / |det J|
+//   y    = (B^T (x) B^T (x) B^T) sum_d Dg_d^T g_d
+// Faces (Sec. 4.1 face form b_h^e, with its readings as in the affine path):
+// at the n^2 face Gauss points, traces and reference gradients of both sides
+// (normal derivative from each side's lines, tangential interpolation and
+// derivatives by 2D sum factorisation through LDS), physical gradients with
+// each side's own Jacobian, area-weighted normal n dS = dF/dxi_a x dF/dxi_b
+// of T^-; the test-function side is projected back with the transposed
+// tangential operators.  Every face is evaluated by both of its elements,
+// which write only their own rows (no atomics).
+//
+// The discrete form is symmetric, so the transposed apply evaluates the same
+// kernel.
 #include "dg_internal.hpp"
 #include "dg_kernels.hpp"
+#include "dg_lines.hpp"
+#include "dg_geom.hpp"
 
 namespace dg {
 
-hipError_t launch_apply_trilinear(int, int, int, int, const MeshArgs<double>&, const MeshArgs<float>&,
-                                  const void*, void*, double*, unsigned*, double*, const int*, hipStream_t) {
-  return hipErrorNotSupported;
+// out_i = sum_j A[i][j] a_j  (TA: A[j][i]), A with row stride kMaxN
+template <int N, typename TC, bool TA>
+__device__ __forceinline__ void contract(const TC* A, const TC (&a)[N], TC (&out)[N]) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    TC s = TC(0);
+#pragma unroll
+    for (int j = 0; j < N; ++j) s += (TA ? A[j * kMaxN + i] : A[i * kMaxN + j]) * a[j];
+    out[i] = s;
+  }
 }
-hipError_t launch_diag_trilinear(int, const MeshArgs<double>&, double*, hipStream_t) {
-  return hipErrorNotSupported;
+
+template <typename TC>
+__device__ __forceinline__ void corner_of(const MeshArgs<TC>& m, int64_t e, int c, int a, TC& out) {
+  const int ex = (int)(e % m.nx), ey = (int)((e / m.nx) % m.ny), ez = (int)(e / ((int64_t)m.nx * m.ny));
+  const int vx = ex + (c & 1), vy = ey + ((c >> 1) & 1), vz = ez + ((c >> 2) & 1);
+  const int64_t v = vx + (int64_t)(m.nx + 1) * (vy + (int64_t)(m.ny + 1) * vz);
+  out = m.vert[3 * v + a];
+}
+
+// Face contributions of the face normal to axis D on side s of the thread's
+// element, added into the element's accumulator tile Y.  All threads of the
+// block call this (it synchronises); act marks threads owning an element.
+template <int N, int D, typename TC, typename TIN>
+__device__ void face_term(const MeshArgs<TC>& m, const Tables<TC>& T, const TIN* __restrict__ x, int64_t e,
+                          int ex, int ey, int ez, const TC (&X)[8][3], TC K, int t1, int t2, const TC* U,
+                          TC* Y, TC (*F)[N * N], bool act, int s) {
+  constexpr int NN = N * N;
+  const int t = t1 + N * t2;
+  const int ax = (D == 0) ? 1 : 0;  // reference axis of t1
+  const int bx = (D == 2) ? 1 : 2;  // reference axis of t2
+  const TC* dS = s ? T.d1 : T.d0;   // own derivative at the own face end
+  const TC* dN = s ? T.d0 : T.d1;   // neighbour's derivative at its face end
+  int64_t nb = -1;
+  TC Uo = TC(0), Go = TC(0), Un = TC(0), Gn = TC(0);
+  if (act) {
+    nb = neighbour<D>(m, ex, ey, ez, s);
+    TC own[N];
+    lds_get<N, D>(U, t1, t2, own);
+    Uo = own[s ? N - 1 : 0];
+#pragma unroll
+    for (int i = 0; i < N; ++i) Go += dS[i] * own[i];
+    if (nb >= 0) {
+      TC nl[N];
+      glb_get<N, D, TC, TIN>(x, nb, t1, t2, nl);
+      Un = nl[s ? 0 : N - 1];
+#pragma unroll
+      for (int i = 0; i < N; ++i) Gn += dN[i] * nl[i];
+    }
+  }
+  __syncthreads();  // face buffers free
+  if (act) {
+    F[0][t] = Uo;
+    F[1][t] = Go;
+    F[2][t] = Un;
+    F[3][t] = Gn;
+  }
+  __syncthreads();
+  if (act) {  // interpolation / derivative along t1 (axis ax)
+    TC bu = 0, du = 0, bg = 0, bun = 0, dun = 0, bgn = 0;
+#pragma unroll
+    for (int a = 0; a < N; ++a) {
+      const TC B = T.B[t1 * kMaxN + a], Dd = T.D[t1 * kMaxN + a];
+      bu += B * F[0][t2 * N + a];
+      du += Dd * F[0][t2 * N + a];
+      bg += B * F[1][t2 * N + a];
+      bun += B * F[2][t2 * N + a];
+      dun += Dd * F[2][t2 * N + a];
+      bgn += B * F[3][t2 * N + a];
+    }
+    F[4][t] = bu;
+    F[5][t] = du;
+    F[6][t] = bg;
+    F[7][t] = bun;
+    F[8][t] = dun;
+    F[9][t] = bgn;
+  }
+  __syncthreads();
+  TC P = 0, Ra = 0, Rb = 0, Rd = 0;
+  if (act) {  // along t2 (axis bx): values at face Gauss point (qa, qb) = (t1, t2)
+    TC uo = 0, gao = 0, gbo = 0, gdo = 0, un = 0, gan = 0, gbn = 0, gdn = 0;
+#pragma unroll
+    for (int b = 0; b < N; ++b) {
+      const TC B = T.B[t2 * kMaxN + b], Dd = T.D[t2 * kMaxN + b];
+      uo += B * F[4][b * N + t1];
+      gao += B * F[5][b * N + t1];
+      gbo += Dd * F[4][b * N + t1];
+      gdo += B * F[6][b * N + t1];
+      un += B * F[7][b * N + t1];
+      gan += B * F[8][b * N + t1];
+      gbn += Dd * F[7][b * N + t1];
+      gdn += B * F[9][b * N + t1];
+    }
+    TC xi[3];
+    xi[D] = TC(s);
+    xi[ax] = T.gx[t1];
+    xi[bx] = T.gx[t2];
+    TC Jo[3][3], Ao[3][3];
+    trilinear_jacobian(X, xi, Jo);
+    adj3(Jo, Ao);
+    const TC deto = det3(Jo);
+    TC gro[3];
+    gro[D] = gdo;
+    gro[ax] = gao;
+    gro[bx] = gbo;
+    TC go[3];  // physical gradient, own side: adj^T gr / det
+#pragma unroll
+    for (int c = 0; c < 3; ++c) go[c] = (Ao[0][c] * gro[0] + Ao[1][c] * gro[1] + Ao[2][c] * gro[2]) / deto;
+    const TC w = T.gw[t1] * T.gw[t2];
+    const TC h = D == 0 ? m.hx : (D == 1 ? m.hy : m.hz);
+    const TC sig = m.sig_hat / h;
+    TC Nv[3];
+    const int c1 = (D + 1) % 3, c2 = (D + 2) % 3;
+    if (nb >= 0) {
+      TC Xn[8][3];
+#pragma unroll
+      for (int c = 0; c < 8; ++c)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) corner_of(m, nb, c, a, Xn[c][a]);
+      TC xin[3];
+      xin[D] = TC(1 - s);
+      xin[ax] = xi[ax];
+      xin[bx] = xi[bx];
+      TC Jn[3][3], An[3][3];
+      trilinear_jacobian(Xn, xin, Jn);
+      adj3(Jn, An);
+      const TC detn = det3(Jn);
+      TC grn[3];
+      grn[D] = gdn;
+      grn[ax] = gan;
+      grn[bx] = gbn;
+      TC gn[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) gn[c] = (An[0][c] * grn[0] + An[1][c] * grn[1] + An[2][c] * grn[2]) / detn;
+      // n dS from T^-: the own element on the upper face, the neighbour on the lower face
+      const TC (&Jm)[3][3] = s ? Jo : Jn;
+      Nv[0] = Jm[1][c1] * Jm[2][c2] - Jm[2][c1] * Jm[1][c2];
+      Nv[1] = Jm[2][c1] * Jm[0][c2] - Jm[0][c1] * Jm[2][c2];
+      Nv[2] = Jm[0][c1] * Jm[1][c2] - Jm[1][c1] * Jm[0][c2];
+      const TC area = sqrt(Nv[0] * Nv[0] + Nv[1] * Nv[1] + Nv[2] * Nv[2]);
+      const TC Kn = m.K[nb];
+      const TC gam = TC(2) * K * Kn / (K + Kn);
+      const TC Jq = s ? uo - un : un - uo;
+      const TC Fq = TC(0.5) * gam * w * ((go[0] + gn[0]) * Nv[0] + (go[1] + gn[1]) * Nv[1] + (go[2] + gn[2]) * Nv[2]);
+      const TC pen = sig * gam * area * w * Jq;
+      P = s ? (pen - Fq) : (Fq - pen);
+      const TC cr = -TC(0.5) * gam * w * Jq / deto;
+      TC R[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) R[c] = cr * (Ao[c][0] * Nv[0] + Ao[c][1] * Nv[1] + Ao[c][2] * Nv[2]);
+      Ra = R[ax];
+      Rb = R[bx];
+      Rd = R[D];
+    } else {
+      // weak Dirichlet: -K grad u.n v - K grad v.n u + sigma K u v, outward n
+      const TC sg = s ? TC(1) : TC(-1);
+      Nv[0] = sg * (Jo[1][c1] * Jo[2][c2] - Jo[2][c1] * Jo[1][c2]);
+      Nv[1] = sg * (Jo[2][c1] * Jo[0][c2] - Jo[0][c1] * Jo[2][c2]);
+      Nv[2] = sg * (Jo[0][c1] * Jo[1][c2] - Jo[1][c1] * Jo[0][c2]);
+      const TC area = sqrt(Nv[0] * Nv[0] + Nv[1] * Nv[1] + Nv[2] * Nv[2]);
+      P = -K * w * (go[0] * Nv[0] + go[1] * Nv[1] + go[2] * Nv[2]) + sig * K * area * w * uo;
+      const TC cr = -K * w * uo / deto;
+      TC R[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) R[c] = cr * (Ao[c][0] * Nv[0] + Ao[c][1] * Nv[1] + Ao[c][2] * Nv[2]);
+      Ra = R[ax];
+      Rb = R[bx];
+      Rd = R[D];
+    }
+    F[0][t] = P;  // F[0..3] were last read before the previous barrier
+    F[1][t] = Ra;
+    F[2][t] = Rb;
+    F[3][t] = Rd;
+  }
+  __syncthreads();
+  if (act) {  // transposed tangential operators, contraction over qb: thread (qa, b) = (t1, t2)
+    TC xs = 0, ys = 0, zs = 0;
+#pragma unroll
+    for (int qb = 0; qb < N; ++qb) {
+      const TC B = T.B[qb * kMaxN + t2], Dd = T.D[qb * kMaxN + t2];
+      xs += B * F[0][qb * N + t1] + Dd * F[2][qb * N + t1];
+      ys += B * F[1][qb * N + t1];
+      zs += B * F[3][qb * N + t1];
+    }
+    F[4][t2 * N + t1] = xs;
+    F[5][t2 * N + t1] = ys;
+    F[6][t2 * N + t1] = zs;
+  }
+  __syncthreads();
+  if (act) {  // contraction over qa: thread (a, b) = (t1, t2) owns face node (a, b) of its line
+    TC out = 0, z = 0;
+#pragma unroll
+    for (int qa = 0; qa < N; ++qa) {
+      const TC B = T.B[qa * kMaxN + t1], Dd = T.D[qa * kMaxN + t1];
+      out += B * F[4][t2 * N + qa] + Dd * F[5][t2 * N + qa];
+      z += B * F[6][t2 * N + qa];
+    }
+    TC yl[N];
+    lds_get<N, D>(Y, t1, t2, yl);
+#pragma unroll
+    for (int i = 0; i < N; ++i) yl[i] += dS[i] * z;
+    yl[s ? N - 1 : 0] += out;
+    lds_put<N, D>(Y, t1, t2, yl);
+  }
+  (void)NN;
+}
+
+template <int N, typename TIN, typename TOUT, typename TC, bool DOT>
+__global__ __launch_bounds__(kBlock) void k_apply_trilinear(MeshArgs<TC> m, const TIN* __restrict__ x,
+                                                            TOUT* __restrict__ y, double* partials,
+                                                            unsigned* counter, double* dot_out,
+                                                            const int* skip) {
+  constexpr int NN = N * N, N3 = NN * N, EPB = elems_per_block(N);
+  __shared__ TC sU[EPB * N3], sA[EPB * N3], sB[EPB * N3], sC[EPB * N3];
+  __shared__ TC sX[EPB][8][3];
+  __shared__ TC sF[EPB][10][NN];
+  __shared__ double red[kBlock / 64];
+  if (skip != nullptr && *skip) return;
+  const Tables<TC>& T = *m.tab;
+  const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
+  const int tid = threadIdx.x, el = tid / NN, t = tid % NN, t1 = t % N, t2 = t / N;
+  const int64_t e = blk * EPB + el;
+  const bool act = (el < EPB) && (e < m.E);
+  const int le = act ? el : 0;
+  TC* U = sU + le * N3;
+  TC* A = sA + le * N3;
+  TC* B = sB + le * N3;
+  TC* C = sC + le * N3;
+  int ex = 0, ey = 0, ez = 0;
+  TC K = TC(1);
+  TC uz[N];
+  if (act) {
+    ex = (int)(e % m.nx);
+    ey = (int)((e / m.nx) % m.ny);
+    ez = (int)(e / ((int64_t)m.nx * m.ny));
+    K = m.K[e];
+    if (t < 24) corner_of(m, e, t / 3, t % 3, sX[le][t / 3][t % 3]);
+    glb_get<N, 2, TC, TIN>(x, e, t1, t2, uz);
+    lds_put<N, 2>(U, t1, t2, uz);
+    TC a[N];
+    contract<N, TC, false>(T.B, uz, a);  // phase Z: interpolate along z
+    lds_put<N, 2>(A, t1, t2, a);
+  }
+  __syncthreads();
+  TC X[8][3];
+#pragma unroll
+  for (int c = 0; c < 8; ++c)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) X[c][a] = sX[le][c][a];
+  if (act) {  // phase Y
+    TC a[N], b[N];
+    lds_get<N, 1>(A, t1, t2, a);
+    contract<N, TC, false>(T.B, a, b);
+    lds_put<N, 1>(B, t1, t2, b);
+  }
+  __syncthreads();
+  if (act) {  // phase X: v and d/dxi_0
+    TC a[N], v[N], d1[N];
+    lds_get<N, 0>(B, t1, t2, a);
+    contract<N, TC, false>(T.B, a, v);
+    contract<N, TC, false>(T.Dg, v, d1);
+    lds_put<N, 0>(A, t1, t2, v);
+    lds_put<N, 0>(C, t1, t2, d1);
+  }
+  __syncthreads();
+  if (act) {  // phase Y': d/dxi_1
+    TC v[N], d2[N];
+    lds_get<N, 1>(A, t1, t2, v);
+    contract<N, TC, false>(T.Dg, v, d2);
+    lds_put<N, 1>(B, t1, t2, d2);
+  }
+  __syncthreads();
+  if (act) {  // phase Z': d/dxi_2, geometry, g = G gr, Dg_z^T g_2
+    TC v[N], d1[N], d2[N], d3[N], g1[N], g2[N], g3[N], wz[N];
+    lds_get<N, 2>(A, t1, t2, v);
+    lds_get<N, 2>(C, t1, t2, d1);
+    lds_get<N, 2>(B, t1, t2, d2);
+    contract<N, TC, false>(T.Dg, v, d3);
+    const TC wq12 = T.gw[t1] * T.gw[t2] * K;
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+      const TC xi[3] = {T.gx[t1], T.gx[t2], T.gx[q]};
+      TC J[3][3], Aj[3][3];
+      trilinear_jacobian(X, xi, J);
+      adj3(J, Aj);
+      const TC c = wq12 * T.gw[q] / fabs(det3(J));
+      // G = c adj adj^T (symmetric)
+      TC Gm[3][3];
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int cc = r; cc < 3; ++cc) {
+          const TC sgm = Aj[r][0] * Aj[cc][0] + Aj[r][1] * Aj[cc][1] + Aj[r][2] * Aj[cc][2];
+          Gm[r][cc] = c * sgm;
+          Gm[cc][r] = c * sgm;
+        }
+      g1[q] = Gm[0][0] * d1[q] + Gm[0][1] * d2[q] + Gm[0][2] * d3[q];
+      g2[q] = Gm[1][0] * d1[q] + Gm[1][1] * d2[q] + Gm[1][2] * d3[q];
+      g3[q] = Gm[2][0] * d1[q] + Gm[2][1] * d2[q] + Gm[2][2] * d3[q];
+    }
+    contract<N, TC, true>(T.Dg, g3, wz);
+    lds_put<N, 2>(A, t1, t2, wz);
+    lds_put<N, 2>(C, t1, t2, g1);
+    lds_put<N, 2>(B, t1, t2, g2);
+  }
+  __syncthreads();
+  if (act) {  // phase Y'': += Dg_y^T g_1
+    TC g2[N], w[N], r[N];
+    lds_get<N, 1>(B, t1, t2, g2);
+    lds_get<N, 1>(A, t1, t2, w);
+    contract<N, TC, true>(T.Dg, g2, r);
+#pragma unroll
+    for (int i = 0; i < N; ++i) w[i] += r[i];
+    lds_put<N, 1>(A, t1, t2, w);
+  }
+  __syncthreads();
+  if (act) {  // phase X'': += Dg_x^T g_0, then B_x^T
+    TC g1[N], w[N], r[N], o[N];
+    lds_get<N, 0>(C, t1, t2, g1);
+    lds_get<N, 0>(A, t1, t2, w);
+    contract<N, TC, true>(T.Dg, g1, r);
+#pragma unroll
+    for (int i = 0; i < N; ++i) w[i] += r[i];
+    contract<N, TC, true>(T.B, w, o);
+    lds_put<N, 0>(A, t1, t2, o);
+  }
+  __syncthreads();
+  if (act) {  // phase Y''': B_y^T
+    TC w[N], o[N];
+    lds_get<N, 1>(A, t1, t2, w);
+    contract<N, TC, true>(T.B, w, o);
+    lds_put<N, 1>(A, t1, t2, o);
+  }
+  __syncthreads();
+  if (act) {  // phase Z''': B_z^T -> accumulator C
+    TC w[N], o[N];
+    lds_get<N, 2>(A, t1, t2, w);
+    contract<N, TC, true>(T.B, w, o);
+    lds_put<N, 2>(C, t1, t2, o);
+  }
+  // faces (each call synchronises before touching shared buffers)
+  face_term<N, 0, TC, TIN>(m, T, x, e, ex, ey, ez, X, K, t1, t2, U, C, sF[le], act, 0);
+  face_term<N, 0, TC, TIN>(m, T, x, e, ex, ey, ez, X, K, t1, t2, U, C, sF[le], act, 1);
+  __syncthreads();
+  face_term<N, 1, TC, TIN>(m, T, x, e, ex, ey, ez, X, K, t1, t2, U, C, sF[le], act, 0);
+  face_term<N, 1, TC, TIN>(m, T, x, e, ex, ey, ez, X, K, t1, t2, U, C, sF[le], act, 1);
+  __syncthreads();
+  face_term<N, 2, TC, TIN>(m, T, x, e, ex, ey, ez, X, K, t1, t2, U, C, sF[le], act, 0);
+  face_term<N, 2, TC, TIN>(m, T, x, e, ex, ey, ez, X, K, t1, t2, U, C, sF[le], act, 1);
+  __syncthreads();
+  double part = 0.0;
+  if (act) {
+    TC o[N];
+    lds_get<N, 2>(C, t1, t2, o);
+    TOUT* py = y + e * N3;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      const TOUT v = (TOUT)o[i];
+      py[lidx<N, 2>(t1, t2, i)] = v;
+      if (DOT) part += (double)uz[i] * (double)v;
+    }
+  }
+  if (DOT) {
+    double s = block_sum<kBlock>(part, red);
+    double mine[1] = {s};
+    grid_finish<1, kBlock>(mine, partials, counter, gridDim.x, blockIdx.x,
+                           [&](const double* tot) { *dot_out = tot[0]; });
+  }
+}
+
+// ---------------------------------------------------------------- diagonal
+// one block per element: G_q of every volume point into LDS, then one thread
+// per DOF sums gr_i^T G_q gr_i over the points, plus the face terms of the
+// face-layer DOFs (a_e(phi_i, phi_i) with phi_i on its own side).
+template <int N>
+__global__ __launch_bounds__(512) void k_diag_trilinear(MeshArgs<double> m, double* __restrict__ d) {
+  constexpr int NN = N * N, N3 = NN * N;
+  __shared__ double G[N3][6];
+  const int64_t e = blockIdx.x;
+  const int t = threadIdx.x;
+  const Tables<double>& T = *m.tab;
+  double X[8][3];
+  element_corners(m, e, X);
+  const double K = m.K[e];
+  if (t < N3) {
+    const int q1 = t % N, q2 = (t / N) % N, q3 = t / NN;
+    const double xi[3] = {T.gx[q1], T.gx[q2], T.gx[q3]};
+    double J[3][3], Aj[3][3];
+    trilinear_jacobian(X, xi, J);
+    adj3(J, Aj);
+    const double c = T.gw[q1] * T.gw[q2] * T.gw[q3] * K / fabs(det3(J));
+    int k = 0;
+    for (int r = 0; r < 3; ++r)
+      for (int cc = r; cc < 3; ++cc)
+        G[t][k++] = c * (Aj[r][0] * Aj[cc][0] + Aj[r][1] * Aj[cc][1] + Aj[r][2] * Aj[cc][2]);
+  }
+  __syncthreads();
+  if (t >= N3) return;
+  const int i1 = t % N, i2 = (t / N) % N, i3 = t / NN;
+  const int ii[3] = {i1, i2, i3};
+  double acc = 0.0;
+  for (int q3 = 0; q3 < N; ++q3)
+    for (int q2 = 0; q2 < N; ++q2)
+      for (int q1 = 0; q1 < N; ++q1) {
+        const double b1 = T.B[q1 * kMaxN + i1], b2 = T.B[q2 * kMaxN + i2], b3 = T.B[q3 * kMaxN + i3];
+        const double g0 = T.D[q1 * kMaxN + i1] * b2 * b3;
+        const double g1 = b1 * T.D[q2 * kMaxN + i2] * b3;
+        const double g2 = b1 * b2 * T.D[q3 * kMaxN + i3];
+        const double* Gq = G[q1 + N * (q2 + N * q3)];
+        acc += Gq[0] * g0 * g0 + Gq[3] * g1 * g1 + Gq[5] * g2 * g2 +
+               2.0 * (Gq[1] * g0 * g1 + Gq[2] * g0 * g2 + Gq[4] * g1 * g2);
+      }
+  const int ex = (int)(e % m.nx), ey = (int)((e / m.nx) % m.ny), ez = (int)(e / ((int64_t)m.nx * m.ny));
+  for (int D = 0; D < 3; ++D) {
+    const int ax = (D == 0) ? 1 : 0, bx = (D == 2) ? 1 : 2;
+    const int c1 = (D + 1) % 3, c2 = (D + 2) % 3;
+    const double h = D == 0 ? m.hx : (D == 1 ? m.hy : m.hz);
+    const double sig = m.sig_hat / h;
+    for (int s = 0; s < 2; ++s) {
+      int64_t nb;
+      if (D == 0) nb = neighbour<0>(m, ex, ey, ez, s);
+      else if (D == 1) nb = neighbour<1>(m, ex, ey, ez, s);
+      else nb = neighbour<2>(m, ex, ey, ez, s);
+      const bool self = (nb == e);
+      if (self && s == 0) continue;  // the element's own periodic face: once
+      const int end = s ? N - 1 : 0;
+      if (!self && ii[D] != end) continue;
+      double gam = K;
+      if (nb >= 0) {
+        const double Kn = m.K[nb];
+        gam = 2.0 * K * Kn / (K + Kn);
+      }
+      for (int qb = 0; qb < N; ++qb)
+        for (int qa = 0; qa < N; ++qa) {
+          const double w = T.gw[qa] * T.gw[qb];
+          // value and physical gradient of phi_i on this element at xi_D = side
+          auto eval = [&](int side, double& val, double (&g)[3], double (&Jc)[3][3]) {
+            double xi[3];
+            xi[D] = side;
+            xi[ax] = T.gx[qa];
+            xi[bx] = T.gx[qb];
+            double Aj[3][3];
+            trilinear_jacobian(X, xi, Jc);
+            adj3(Jc, Aj);
+            const double det = det3(Jc);
+            const double* dE = side ? T.d1 : T.d0;
+            const double la = T.B[qa * kMaxN + ii[ax]], lb = T.B[qb * kMaxN + ii[bx]];
+            const double le = (ii[D] == (side ? N - 1 : 0)) ? 1.0 : 0.0;
+            val = le * la * lb;
+            double gr[3];
+            gr[D] = dE[ii[D]] * la * lb;
+            gr[ax] = le * T.D[qa * kMaxN + ii[ax]] * lb;
+            gr[bx] = le * la * T.D[qb * kMaxN + ii[bx]];
+            for (int c = 0; c < 3; ++c) g[c] = (Aj[0][c] * gr[0] + Aj[1][c] * gr[1] + Aj[2][c] * gr[2]) / det;
+          };
+          double v1, gA[3], J1[3][3];
+          eval(s, v1, gA, J1);
+          double Nv[3];
+          Nv[0] = J1[1][c1] * J1[2][c2] - J1[2][c1] * J1[1][c2];
+          Nv[1] = J1[2][c1] * J1[0][c2] - J1[0][c1] * J1[2][c2];
+          Nv[2] = J1[0][c1] * J1[1][c2] - J1[1][c1] * J1[0][c2];
+          const double area = sqrt(Nv[0] * Nv[0] + Nv[1] * Nv[1] + Nv[2] * Nv[2]);
+          if (self) {  // phi_i on both sides of the face: [phi] = phi(1) - phi(0)
+            double v0, gB[3], J0[3][3];
+            eval(0, v0, gB, J0);
+            const double jump = v1 - v0;
+            const double avg = 0.5 * gam * ((gA[0] + gB[0]) * Nv[0] + (gA[1] + gB[1]) * Nv[1] + (gA[2] + gB[2]) * Nv[2]);
+            acc += w * (-2.0 * avg * jump + sig * gam * area * jump * jump);
+          } else if (nb >= 0) {
+            const double fl = gA[0] * Nv[0] + gA[1] * Nv[1] + gA[2] * Nv[2];
+            const double sg = s ? -1.0 : 1.0;  // [phi] = +phi on the upper face, -phi on the lower
+            acc += w * (sg * gam * fl * v1 + sig * gam * area * v1 * v1);
+          } else {
+            const double sg = s ? 1.0 : -1.0;  // outward normal
+            const double fl = sg * (gA[0] * Nv[0] + gA[1] * Nv[1] + gA[2] * Nv[2]);
+            acc += w * (-2.0 * K * fl * v1 + sig * K * area * v1 * v1);
+          }
+        }
+    }
+  }
+  d[e * N3 + t] = acc;
+}
+
+// ---------------------------------------------------------------- launchers
+template <int N, typename TIN, typename TOUT, typename TC, bool DOT>
+static hipError_t run_tri(const MeshArgs<TC>& m, const void* x, void* y, double* partials, unsigned* counter,
+                          double* dot_out, const int* skip, hipStream_t s) {
+  const int64_t nb = element_blocks(N, m.E);
+  hipLaunchKernelGGL((k_apply_trilinear<N, TIN, TOUT, TC, DOT>), dim3((unsigned)nb), dim3(kBlock), 0, s, m,
+                     (const TIN*)x, (TOUT*)y, partials, counter, dot_out, skip);
+  return hipGetLastError();
+}
+
+template <int N, bool DOT>
+static hipError_t run_tri_prec(int prec, const MeshArgs<double>& m64, const MeshArgs<float>& m32, const void* x,
+                               void* y, double* partials, unsigned* counter, double* dot_out, const int* skip,
+                               hipStream_t s) {
+  switch (prec) {
+    case 0: return run_tri<N, double, double, double, DOT>(m64, x, y, partials, counter, dot_out, skip, s);
+    case 1: return run_tri<N, float, float, float, DOT>(m32, x, y, partials, counter, dot_out, skip, s);
+    case 2: return run_tri<N, uint16_t, float, float, DOT>(m32, x, y, partials, counter, dot_out, skip, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int N>
+static hipError_t run_tri_n(int prec, int dot, const MeshArgs<double>& m64, const MeshArgs<float>& m32,
+                            const void* x, void* y, double* partials, unsigned* counter, double* dot_out,
+                            const int* skip, hipStream_t s) {
+  if (dot) return run_tri_prec<N, true>(prec, m64, m32, x, y, partials, counter, dot_out, skip, s);
+  return run_tri_prec<N, false>(prec, m64, m32, x, y, partials, counter, dot_out, skip, s);
+}
+
+hipError_t launch_apply_trilinear(int n, int prec, int trans, int dot, const MeshArgs<double>& m64,
+                                  const MeshArgs<float>& m32, const void* x, void* y, double* partials,
+                                  unsigned* counter, double* dot_out, const int* skip, hipStream_t s) {
+  (void)trans;  // symmetric form: A^T x is evaluated by the same kernel
+  switch (n) {
+    case 2: return run_tri_n<2>(prec, dot, m64, m32, x, y, partials, counter, dot_out, skip, s);
+    case 3: return run_tri_n<3>(prec, dot, m64, m32, x, y, partials, counter, dot_out, skip, s);
+    case 4: return run_tri_n<4>(prec, dot, m64, m32, x, y, partials, counter, dot_out, skip, s);
+    case 5: return run_tri_n<5>(prec, dot, m64, m32, x, y, partials, counter, dot_out, skip, s);
+    case 6: return run_tri_n<6>(prec, dot, m64, m32, x, y, partials, counter, dot_out, skip, s);
+    case 7: return run_tri_n<7>(prec, dot, m64, m32, x, y, partials, counter, dot_out, skip, s);
+    case 8: return run_tri_n<8>(prec, dot, m64, m32, x, y, partials, counter, dot_out, skip, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int N>
+static hipError_t run_tri_diag(const MeshArgs<double>& m, double* d, hipStream_t s) {
+  const int th = ((N * N * N + 63) / 64) * 64;
+  hipLaunchKernelGGL((k_diag_trilinear<N>), dim3((unsigned)m.E), dim3(th), 0, s, m, d);
+  return hipGetLastError();
+}
+hipError_t launch_diag_trilinear(int n, const MeshArgs<double>& m, double* d, hipStream_t s) {
+  switch (n) {
+    case 2: return run_tri_diag<2>(m, d, s);
+    case 3: return run_tri_diag<3>(m, d, s);
+    case 4: return run_tri_diag<4>(m, d, s);
+    case 5: return run_tri_diag<5>(m, d, s);
+    case 6: return run_tri_diag<6>(m, d, s);
+    case 7: return run_tri_diag<7>(m, d, s);
+    case 8: return run_tri_diag<8>(m, d, s);
+  }
+  return hipErrorInvalidValue;
 }
 
 }  // namespace dg

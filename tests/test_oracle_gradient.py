@@ -56,3 +56,12 @@ def test_gradient_sum_is_homogeneity():
     # homogeneity of the assembled matrix itself
     B = O.assemble(m.replace(theta=m.theta + np.log(3.0)))
     assert abs(B - 3.0 * A).max() <= 1e-13 * abs(B).max()
+
+
+def test_gradient_element_subset():
+    m = O.Mesh(3, 3, 2, 2, theta=I.theta(18, seed=21))
+    u = I.uniform_vector(m.ndof, seed=22)
+    v = I.uniform_vector(m.ndof, seed=23)
+    g = O.dA_dtheta(m, u, v)
+    el = [0, 7, 17]
+    assert np.array_equal(O.dA_dtheta_elems(m, u, v, el), g[el])
