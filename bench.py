@@ -113,6 +113,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", default="", help="comma list of extras to run (default: all)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain 256 MiB device copy (reference for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -127,6 +129,15 @@ def main():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
     dev = lambda a, dt=torch.float64: torch.as_tensor(np.ascontiguousarray(a)).to("cuda", dt)  # noqa: E731
+
+    if args.calibrate_copy:
+        src = torch.ones(1 << 26, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy calibration: 5 x 256 MiB device-to-device copies")
+        del src, dst
 
     # ------------------------------------------------------------ headline
     wl = "dirichlet_q3_32"

@@ -94,7 +94,7 @@ def test_adjoint_gradient_small_vs_oracle_and_fd():
     J0, u0, A0 = J(theta)
     lam = spla.spsolve(A0.T.tocsc(), u0 - u_obs)
     g_ora = -O.dA_dtheta(m, lam, u0)
-    assert abs(float(loss) - J0) <= 1e-10 * J0
+    assert abs(float(loss.detach()) - J0) <= 1e-10 * J0
     assert np.max(np.abs(g_gpu - g_ora)) <= 1e-8 * np.max(np.abs(g_ora))
     h = 1e-6
     for T in I.fd_elements(N ** 3, m=8):
