@@ -17,12 +17,13 @@
 // factorisation as the volume term (Sec. 3.3: matrix-free, sum-factorised,
 // no gather/scatter: the kernels index the global element-blocked vectors).
 //
-// Layout: block = elems_per_block(n) consecutive elements (after the XCD
-// remap), n^2 threads per element; per element three n^3 LDS tiles.
+// Layout: a workgroup owns a brick of BX x BY x BZ elements (tile_dims(n)),
+// n^2 threads per element, three n^3 LDS tiles per element.  Neighbour lines
+// inside the brick come from LDS, the others from HBM (issued up front).
 //
-//   phase Z : own z-lines from HBM, z-neighbour lines   -> bz = L_z u
-//   phase Y : own y-lines from LDS, y-neighbour lines   -> by = L_y u
-//   phase X : own x-lines from LDS, x-neighbour lines   -> bx = L_x u,
+//   phase Z : own z-lines, z-neighbour lines   -> bz = L_z u
+//   phase Y : own y-lines, y-neighbour lines   -> by = L_y u
+//   phase X : own x-lines, x-neighbour lines   -> bx = L_x u,
 //             c = M_x by, e = M_x bz
 //   phase Y2: f = M_y bx + c, g = M_y e
 //   phase Z2: y = M_z f + g -> HBM
@@ -35,21 +36,22 @@
 namespace dg {
 
 // 1D SWIPDG operator on one line:  b = L u  (TRANS: b = L^T u), with
-//   volume   K (At / h) S u                      (At = h_t1 h_t2, h = h_d)
+//   volume   vs S u                         (vs = K At / h, At = h_t1 h_t2, h = h_d)
 //   upper face (this element is T^-):  J = u[n-1] - uH[0],
-//       F = cF (G^- + G^+),  G^- = d1.u / h,  G^+ = d0.uH / h
-//       b[n-1] += At (-F + aP J),   b[i] -= At cC d1[i] J
+//       F = GH (G^- + G^+),  G^- = d1.u / h,  G^+ = d0.uH / h
+//       b[n-1] += At (aP J - F),   b[i] -= At (GH / h) d1[i] J
 //   lower face (this element is T^+):  J = uL[n-1] - u[0],
-//       F = cF (G^- + G^+),  G^- = d1.uL / h,  G^+ = d0.u / h
-//       b[0]   += At (F - aP J),    b[i] -= At cC d0[i] J
-// interior faces: gamma = 2 K K' / (K + K'), cF = gamma/2, aP = sigma gamma,
-// cC = gamma / (2h); Dirichlet faces: neighbour terms 0, cF = K, aP = sigma K,
-// cC = K / h.  The transpose swaps the roles of cF / h and cC.
+//       F = GL (G^- + G^+),  G^- = d1.uL / h,  G^+ = d0.u / h
+//       b[0]   += At (F - aP J),   b[i] -= At (GL / h) d0[i] J
+// with the face coefficient G = gamma/2 = K K'/(K + K') and aP = sigma gamma
+// = 2 sigma G on interior faces, G = K and aP = sigma K on Dirichlet faces
+// (neighbour terms 0).  The per-face algebra is symmetric (the coefficients
+// of the flux-times-jump and jump-times-flux terms coincide), so the
+// transpose only transposes S.
 template <int N, typename TC, bool TRANS>
 __device__ __forceinline__ void line_op(const Tables<TC>& T, const TC (&u)[N], const TC (&uL)[N],
-                                        const TC (&uH)[N], bool hasL, bool hasH, TC K, TC KL, TC KH,
-                                        TC h, TC At, TC sig_hat, bool faces, TC (&b)[N]) {
-  const TC vs = K * At / h;
+                                        const TC (&uH)[N], bool hasL, bool hasH, TC GL, TC GH, TC vs,
+                                        TC ih, TC sig, TC At, bool faces, TC (&b)[N]) {
 #pragma unroll
   for (int i = 0; i < N; ++i) {
     TC s = TC(0);
@@ -58,57 +60,39 @@ __device__ __forceinline__ void line_op(const Tables<TC>& T, const TC (&u)[N], c
     b[i] = vs * s;
   }
   if (!faces) return;
-  const TC ih = TC(1) / h;
-  const TC sig = sig_hat * ih;
   {  // upper face
-    TC Gm = TC(0), Gp = TC(0);
+    TC g = TC(0);
 #pragma unroll
-    for (int j = 0; j < N; ++j) Gm += T.d1[j] * u[j];
-    TC Up = TC(0), aF, aP, aC;
+    for (int j = 0; j < N; ++j) g += T.d1[j] * u[j];
+    TC Up = TC(0);
     if (hasH) {
 #pragma unroll
-      for (int j = 0; j < N; ++j) Gp += T.d0[j] * uH[j];
+      for (int j = 0; j < N; ++j) g += T.d0[j] * uH[j];
       Up = uH[0];
-      const TC g = TC(2) * K * KH / (K + KH);
-      aF = TC(0.5) * g;
-      aP = sig * g;
-      aC = TC(0.5) * g * ih;
-    } else {
-      aF = K;
-      aP = sig * K;
-      aC = K * ih;
     }
-    const TC cF = TRANS ? aC * h : aF, cC = TRANS ? aF * ih : aC;
     const TC J = u[N - 1] - Up;
-    const TC F = cF * ih * (Gm + Gp);
-    b[N - 1] += At * (aP * J - F);
-    const TC cj = At * cC * J;
+    const TC aP = sig * GH * (hasH ? TC(2) : TC(1));
+    const TC GAi = At * GH * ih;
+    b[N - 1] += At * aP * J - GAi * g;
+    const TC cj = GAi * J;
 #pragma unroll
     for (int i = 0; i < N; ++i) b[i] -= cj * T.d1[i];
   }
   {  // lower face
-    TC Gm = TC(0), Gp = TC(0);
+    TC g = TC(0);
 #pragma unroll
-    for (int j = 0; j < N; ++j) Gp += T.d0[j] * u[j];
-    TC Um = TC(0), aF, aP, aC;
+    for (int j = 0; j < N; ++j) g += T.d0[j] * u[j];
+    TC Um = TC(0);
     if (hasL) {
 #pragma unroll
-      for (int j = 0; j < N; ++j) Gm += T.d1[j] * uL[j];
+      for (int j = 0; j < N; ++j) g += T.d1[j] * uL[j];
       Um = uL[N - 1];
-      const TC g = TC(2) * K * KL / (K + KL);
-      aF = TC(0.5) * g;
-      aP = sig * g;
-      aC = TC(0.5) * g * ih;
-    } else {
-      aF = K;
-      aP = sig * K;
-      aC = K * ih;
     }
-    const TC cF = TRANS ? aC * h : aF, cC = TRANS ? aF * ih : aC;
     const TC J = Um - u[0];
-    const TC F = cF * ih * (Gm + Gp);
-    b[0] += At * (F - aP * J);
-    const TC cj = At * cC * J;
+    const TC aP = sig * GL * (hasL ? TC(2) : TC(1));
+    const TC GAi = At * GL * ih;
+    b[0] += GAi * g - At * aP * J;
+    const TC cj = GAi * J;
 #pragma unroll
     for (int i = 0; i < N; ++i) b[i] -= cj * T.d0[i];
   }
@@ -126,101 +110,133 @@ __device__ __forceinline__ void mass_line(const Tables<TC>& T, const TC (&a)[N],
   }
 }
 
-// line operator of axis D for the thread's line, neighbour lines from HBM
-template <int N, int D, typename TC, typename TIN, bool TRANS>
-__device__ __forceinline__ void axis_op(const MeshArgs<TC>& m, const Tables<TC>& T,
-                                        const TIN* __restrict__ x, int ex, int ey, int ez, TC K,
-                                        int t1, int t2, const TC (&u)[N], TC (&b)[N]) {
-  const int64_t nL = neighbour<D>(m, ex, ey, ez, 0), nH = neighbour<D>(m, ex, ey, ez, 1);
-  TC uL[N], uH[N];
-  TC KL = TC(1), KH = TC(1);
-  if (nL >= 0) {
-    glb_get<N, D, TC, TIN>(x, nL, t1, t2, uL);
-    KL = m.K[nL];
-  } else {
-#pragma unroll
-    for (int i = 0; i < N; ++i) uL[i] = TC(0);
+// Brick of elements per workgroup for n nodes per direction (BX x BY x BZ,
+// at most kBlock / n^2 elements); x is the fastest element index inside the
+// brick so that a wave's elements share their y and z position.
+__host__ __device__ constexpr int tile_x(int n) { return n == 2 ? 4 : n == 3 ? 4 : n == 4 ? 4 : n == 5 ? 5 : n == 6 ? 7 : n == 7 ? 5 : 4; }
+__host__ __device__ constexpr int tile_y(int n) { return n == 2 ? 4 : n == 3 ? 3 : n == 4 ? 2 : n == 5 ? 2 : 1; }
+__host__ __device__ constexpr int tile_z(int n) { return n == 2 ? 4 : n == 3 ? 2 : n == 4 ? 2 : 1; }
+
+// neighbour coordinate along one axis (periodic wrap), -1 on a Dirichlet boundary
+__device__ __forceinline__ int nb_coord(int c, int s, int Nd, int periodic) {
+  int v = c + (s ? 1 : -1);
+  if (v < 0 || v >= Nd) {
+    if (!periodic) return -1;
+    v = v < 0 ? Nd - 1 : 0;
   }
-  if (nH >= 0) {
-    glb_get<N, D, TC, TIN>(x, nH, t1, t2, uH);
-    KH = m.K[nH];
-  } else {
-#pragma unroll
-    for (int i = 0; i < N; ++i) uH[i] = TC(0);
-  }
-  const TC h = D == 0 ? m.hx : (D == 1 ? m.hy : m.hz);
-  const TC At = D == 0 ? m.hy * m.hz : (D == 1 ? m.hx * m.hz : m.hx * m.hy);
-  line_op<N, TC, TRANS>(T, u, uL, uH, nL >= 0, nH >= 0, K, KL, KH, h, At, m.sig_hat, true, b);
+  return v;
 }
 
-template <typename TOUT>
-__device__ __forceinline__ TOUT store_cast(double v) { return (TOUT)v; }
+// The neighbour lines of axis D, side s: from the brick's LDS tiles when the
+// neighbour is inside the brick, otherwise from HBM.  has = false on a
+// Dirichlet boundary (line set to 0).
+template <int N, int D, int BX, int BY, int BZ, typename TC, typename TIN>
+__device__ __forceinline__ void neighbour_line(const TIN* __restrict__ x, const TC* sU, int nx, int ny,
+                                               const int (&c)[3], const int (&o)[3], const int (&Nd)[3],
+                                               int periodic, int s, int t1, int t2, TC (&v)[N], bool& has) {
+  constexpr int N3 = N * N * N;
+  const int cc = nb_coord(c[D], s, Nd[D], periodic);
+  has = cc >= 0;
+  if (!has) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] = TC(0);
+    return;
+  }
+  int g[3] = {c[0], c[1], c[2]};
+  g[D] = cc;
+  const int l = cc - o[D];
+  constexpr int Bd = D == 0 ? BX : (D == 1 ? BY : BZ);
+  if (l >= 0 && l < Bd) {
+    const int el = (g[0] - o[0]) + BX * ((g[1] - o[1]) + BY * (g[2] - o[2]));
+    lds_get<N, D>(sU + el * N3, t1, t2, v);
+  } else {
+    const int64_t e = g[0] + (int64_t)nx * (g[1] + (int64_t)ny * g[2]);
+    glb_get<N, D, TC, TIN>(x, e, t1, t2, v);
+  }
+}
 
-// y = A x (TRANS: A^T x).  DOT: also <x, y> (y as stored) into *dot_out by a
-// deterministic grid reduction.  skip != nullptr && *skip: do nothing (used
-// by the solver once it has converged).
+// y = A x (TRANS: A^T x) on affine meshes.  DOT: also the block partials of
+// <x, y> (y as stored) for the CG scalar <p, A p>.  skip != nullptr &&
+// *skip: do nothing (the solver has converged).
 template <int N, typename TIN, typename TOUT, typename TC, bool TRANS, bool DOT>
 __global__ __launch_bounds__(kBlock) void k_apply_affine(MeshArgs<TC> m, const TIN* __restrict__ x,
                                                          TOUT* __restrict__ y, double* partials,
-                                                         unsigned* counter, double* dot_out,
                                                          const int* skip) {
-  constexpr int NN = N * N, N3 = NN * N, EPB = elems_per_block(N);
-  __shared__ TC sU[EPB * N3], sA[EPB * N3], sB[EPB * N3];
+  constexpr int NN = N * N, N3 = NN * N;
+  constexpr int BX = tile_x(N), BY = tile_y(N), BZ = tile_z(N), TE = BX * BY * BZ;
+  static_assert(TE * NN <= kBlock, "brick too large");
+  __shared__ TC sU[TE * N3], sA[TE * N3], sB[TE * N3];
   __shared__ double red[kBlock / 64];
   if (skip != nullptr && *skip) return;
   const Tables<TC>& T = *m.tab;
-  const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
-  const int tid = threadIdx.x, el = tid / NN, t = tid % NN, t1 = t % N, t2 = t / N;
-  const int64_t e = blk * EPB + el;
-  const bool act = (el < EPB) && (e < m.E);
-  TC* U = sU + (act ? el : 0) * N3;
-  TC* A = sA + (act ? el : 0) * N3;
-  TC* B = sB + (act ? el : 0) * N3;
-  int ex = 0, ey = 0, ez = 0;
-  TC K = TC(1);
-  TC uz[N];
+  // brick coordinates: uniform per workgroup (scalar arithmetic)
+  const int ntx = (m.nx + BX - 1) / BX, nty = (m.ny + BY - 1) / BY;
+  const int tb = (int)xcd_remap(blockIdx.x, gridDim.x);
+  const int o[3] = {(tb % ntx) * BX, ((tb / ntx) % nty) * BY, (tb / (ntx * nty)) * BZ};
+  const int Nd[3] = {m.nx, m.ny, m.nz};
+  const int tid = threadIdx.x, el = tid / NN, t = tid - el * NN, t1 = t % N, t2 = t / N;
+  const int lx = el % BX, ly = (el / BX) % BY, lz = el / (BX * BY);
+  const int c[3] = {o[0] + lx, o[1] + ly, o[2] + lz};
+  const bool act = el < TE && c[0] < m.nx && c[1] < m.ny && c[2] < m.nz;
+  const int le = act ? el : 0;
+  TC* U = sU + le * N3;
+  TC* A = sA + le * N3;
+  TC* B = sB + le * N3;
+  const int64_t e = c[0] + (int64_t)m.nx * (c[1] + (int64_t)m.ny * c[2]);
+  TC uz[N], K = TC(1), G[6];
   if (act) {
-    ex = (int)(e % m.nx);
-    ey = (int)((e / m.nx) % m.ny);
-    ez = (int)(e / ((int64_t)m.nx * m.ny));
-    K = m.K[e];
-    // phase Z
-    TC b[N];
     glb_get<N, 2, TC, TIN>(x, e, t1, t2, uz);
-    axis_op<N, 2, TC, TIN, TRANS>(m, T, x, ex, ey, ez, K, t1, t2, uz, b);
+    K = m.K[e];
+#pragma unroll
+    for (int f = 0; f < 6; ++f) G[f] = m.G[6 * e + f];
     lds_put<N, 2>(U, t1, t2, uz);
-    lds_put<N, 2>(B, t1, t2, b);
   }
   __syncthreads();
-  if (act) {  // phase Y
-    TC u[N], b[N];
+  if (act) {  // phase Z
+    TC uL[N], uH[N], b[N];
+    bool hL, hH;
+    neighbour_line<N, 2, BX, BY, BZ, TC, TIN>(x, sU, m.nx, m.ny, c, o, Nd, m.periodic, 0, t1, t2, uL, hL);
+    neighbour_line<N, 2, BX, BY, BZ, TC, TIN>(x, sU, m.nx, m.ny, c, o, Nd, m.periodic, 1, t1, t2, uH, hH);
+    line_op<N, TC, TRANS>(T, uz, uL, uH, hL, hH, G[4], G[5], K * m.vs[2], m.ih[2], m.sg[2], m.At[2], true, b);
+    lds_put<N, 2>(B, t1, t2, b);
+  }
+  if (act) {  // phase Y (reads only U, writes A: no barrier needed after phase Z)
+    TC u[N], uL[N], uH[N], b[N];
+    bool hL, hH;
     lds_get<N, 1>(U, t1, t2, u);
-    axis_op<N, 1, TC, TIN, TRANS>(m, T, x, ex, ey, ez, K, t1, t2, u, b);
+    neighbour_line<N, 1, BX, BY, BZ, TC, TIN>(x, sU, m.nx, m.ny, c, o, Nd, m.periodic, 0, t1, t2, uL, hL);
+    neighbour_line<N, 1, BX, BY, BZ, TC, TIN>(x, sU, m.nx, m.ny, c, o, Nd, m.periodic, 1, t1, t2, uH, hH);
+    line_op<N, TC, TRANS>(T, u, uL, uH, hL, hH, G[2], G[3], K * m.vs[1], m.ih[1], m.sg[1], m.At[1], true, b);
     lds_put<N, 1>(A, t1, t2, b);
   }
   __syncthreads();
+  TC bx[N];
   if (act) {  // phase X
-    TC u[N], bx[N], by[N], bz[N], c[N], ee[N];
+    TC u[N], uL[N], uH[N], by[N], bz[N], cc[N], ee[N];
+    bool hL, hH;
     lds_get<N, 0>(U, t1, t2, u);
-    axis_op<N, 0, TC, TIN, TRANS>(m, T, x, ex, ey, ez, K, t1, t2, u, bx);
+    neighbour_line<N, 0, BX, BY, BZ, TC, TIN>(x, sU, m.nx, m.ny, c, o, Nd, m.periodic, 0, t1, t2, uL, hL);
+    neighbour_line<N, 0, BX, BY, BZ, TC, TIN>(x, sU, m.nx, m.ny, c, o, Nd, m.periodic, 1, t1, t2, uH, hH);
+    line_op<N, TC, TRANS>(T, u, uL, uH, hL, hH, G[0], G[1], K * m.vs[0], m.ih[0], m.sg[0], m.At[0], true, bx);
     lds_get<N, 0>(A, t1, t2, by);
     lds_get<N, 0>(B, t1, t2, bz);
-    mass_line<N, TC, TRANS>(T, by, c);
+    mass_line<N, TC, TRANS>(T, by, cc);
     mass_line<N, TC, TRANS>(T, bz, ee);
-    lds_put<N, 0>(U, t1, t2, bx);
-    lds_put<N, 0>(A, t1, t2, c);
+    lds_put<N, 0>(A, t1, t2, cc);
     lds_put<N, 0>(B, t1, t2, ee);
   }
+  __syncthreads();  // U (read as neighbour data above) is free now
+  if (act) lds_put<N, 0>(U, t1, t2, bx);
   __syncthreads();
   if (act) {  // phase Y2
-    TC bx[N], c[N], ee[N], f[N], g[N];
+    TC f[N], cc[N], ee[N], g[N];
     lds_get<N, 1>(U, t1, t2, bx);
-    lds_get<N, 1>(A, t1, t2, c);
+    lds_get<N, 1>(A, t1, t2, cc);
     lds_get<N, 1>(B, t1, t2, ee);
     mass_line<N, TC, TRANS>(T, bx, f);
     mass_line<N, TC, TRANS>(T, ee, g);
 #pragma unroll
-    for (int i = 0; i < N; ++i) f[i] += c[i];
+    for (int i = 0; i < N; ++i) f[i] += cc[i];
     lds_put<N, 1>(U, t1, t2, f);
     lds_put<N, 1>(A, t1, t2, g);
   }
@@ -240,10 +256,8 @@ __global__ __launch_bounds__(kBlock) void k_apply_affine(MeshArgs<TC> m, const T
     }
   }
   if (DOT) {
-    double s = block_sum<kBlock>(part, red);
-    double mine[1] = {s};
-    grid_finish<1, kBlock>(mine, partials, counter, gridDim.x, blockIdx.x,
-                           [&](const double* tot) { *dot_out = tot[0]; });
+    const double mine[1] = {block_sum<kBlock>(part, red)};
+    store_partials<1>(mine, partials, blockIdx.x);
   }
 }
 
@@ -277,10 +291,8 @@ __global__ __launch_bounds__(256) void k_diag_affine(MeshArgs<double> m, double*
       uL[i] = (nL == e && i == id) ? 1.0 : 0.0;
       uH[i] = (nH == e && i == id) ? 1.0 : 0.0;
     }
-    const double KL = nL >= 0 ? m.K[nL] : 1.0, KH = nH >= 0 ? m.K[nH] : 1.0;
-    const double h = D == 0 ? m.hx : (D == 1 ? m.hy : m.hz);
-    const double At = D == 0 ? m.hy * m.hz : (D == 1 ? m.hx * m.hz : m.hx * m.hy);
-    line_op<N, double, false>(T, u, uL, uH, nL >= 0, nH >= 0, K, KL, KH, h, At, m.sig_hat, true, b);
+    line_op<N, double, false>(T, u, uL, uH, nL >= 0, nH >= 0, m.G[6 * e + 2 * D], m.G[6 * e + 2 * D + 1],
+                              K * m.vs[D], m.ih[D], m.sg[D], m.At[D], true, b);
     double bi = 0.0;
 #pragma unroll
     for (int i = 0; i < N; ++i)
@@ -414,21 +426,21 @@ __global__ __launch_bounds__(kBlock) void k_dA_dtheta_affine(MeshArgs<double> m,
   if (act) {  // Z
     double lv[N], w[N];
     lds_get<N, 2>(V, t1, t2, lv);
-    line_op<N, double, false>(T, lv, z0, z0, false, false, 1.0, 1.0, 1.0, m.hz, m.hx * m.hy, m.sig_hat, false, w);
+    line_op<N, double, false>(T, lv, z0, z0, false, false, 0.0, 0.0, m.vs[2], m.ih[2], m.sg[2], m.At[2], false, w);
     lds_put<N, 2>(W, t1, t2, w);
   }
   __syncthreads();
   if (act) {  // Y
     double lv[N], w[N];
     lds_get<N, 1>(V, t1, t2, lv);
-    line_op<N, double, false>(T, lv, z0, z0, false, false, 1.0, 1.0, 1.0, m.hy, m.hx * m.hz, m.sig_hat, false, w);
+    line_op<N, double, false>(T, lv, z0, z0, false, false, 0.0, 0.0, m.vs[1], m.ih[1], m.sg[1], m.At[1], false, w);
     lds_put<N, 1>(X, t1, t2, w);
   }
   __syncthreads();
   if (act) {  // X
     double lv[N], wx[N], wy[N], wz[N], c[N], ee[N];
     lds_get<N, 0>(V, t1, t2, lv);
-    line_op<N, double, false>(T, lv, z0, z0, false, false, 1.0, 1.0, 1.0, m.hx, m.hy * m.hz, m.sig_hat, false, wx);
+    line_op<N, double, false>(T, lv, z0, z0, false, false, 0.0, 0.0, m.vs[0], m.ih[0], m.sg[0], m.At[0], false, wx);
     lds_get<N, 0>(X, t1, t2, wy);
     lds_get<N, 0>(W, t1, t2, wz);
     mass_line<N, double, false>(T, wy, c);
@@ -471,6 +483,36 @@ __global__ __launch_bounds__(kBlock) void k_dA_dtheta_affine(MeshArgs<double> m,
   }
 }
 
+// Face coefficients G[6e + 2d + s] = K K' / (K + K') (interior, = gamma_e / 2)
+// or K (Dirichlet face), in FP64 and FP32.
+__global__ void k_face_coef(MeshArgs<double> m, double* __restrict__ G64, float* __restrict__ G32) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= m.E) return;
+  const int ex = (int)(e % m.nx), ey = (int)((e / m.nx) % m.ny), ez = (int)(e / ((int64_t)m.nx * m.ny));
+  const double K = m.K[e];
+#pragma unroll
+  for (int D = 0; D < 3; ++D)
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      int64_t nb;
+      if (D == 0) nb = neighbour<0>(m, ex, ey, ez, s);
+      else if (D == 1) nb = neighbour<1>(m, ex, ey, ez, s);
+      else nb = neighbour<2>(m, ex, ey, ez, s);
+      double g = K;
+      if (nb >= 0) {
+        const double Kn = m.K[nb];
+        g = K * Kn / (K + Kn);
+      }
+      G64[6 * e + 2 * D + s] = g;
+      G32[6 * e + 2 * D + s] = (float)g;
+    }
+}
+
+hipError_t launch_face_coef(const MeshArgs<double>& m, double* G64, float* G32, hipStream_t s) {
+  hipLaunchKernelGGL(k_face_coef, dim3((unsigned)((m.E + 255) / 256)), dim3(256), 0, s, m, G64, G32);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- launchers
 
 int64_t element_blocks(int n, int64_t E) {
@@ -478,23 +520,30 @@ int64_t element_blocks(int n, int64_t E) {
   return (E + epb - 1) / epb;
 }
 
+int64_t affine_tiles(int n, int nx, int ny, int nz) {
+  const int bx = tile_x(n), by = tile_y(n), bz = tile_z(n);
+  return (int64_t)((nx + bx - 1) / bx) * ((ny + by - 1) / by) * ((nz + bz - 1) / bz);
+}
+
 template <int N, typename TIN, typename TOUT, typename TC, bool TRANS, bool DOT>
-static hipError_t run_apply(const MeshArgs<TC>& m, const void* x, void* y, double* partials,
-                            unsigned* counter, double* dot_out, const int* skip, hipStream_t s) {
-  const int64_t nb = element_blocks(N, m.E);
+static hipError_t run_apply(const MeshArgs<TC>& m, const void* x, void* y, double* partials, CgState* st,
+                            int par, const int* skip, hipStream_t s) {
+  const int64_t nb = affine_tiles(N, m.nx, m.ny, m.nz);
   hipLaunchKernelGGL((k_apply_affine<N, TIN, TOUT, TC, TRANS, DOT>), dim3((unsigned)nb), dim3(kBlock), 0, s, m,
-                     (const TIN*)x, (TOUT*)y, partials, counter, dot_out, skip);
-  return hipGetLastError();
+                     (const TIN*)x, (TOUT*)y, partials, skip);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || !DOT) return e;
+  return launch_finish_dot(partials, nb, st, par, s);
 }
 
 template <int N, bool TRANS, bool DOT>
 static hipError_t run_apply_prec(int prec, const MeshArgs<double>& m64, const MeshArgs<float>& m32,
-                                 const void* x, void* y, double* partials, unsigned* counter,
-                                 double* dot_out, const int* skip, hipStream_t s) {
+                                 const void* x, void* y, double* partials, CgState* st, int par,
+                                 const int* skip, hipStream_t s) {
   switch (prec) {
-    case 0: return run_apply<N, double, double, double, TRANS, DOT>(m64, x, y, partials, counter, dot_out, skip, s);
-    case 1: return run_apply<N, float, float, float, TRANS, DOT>(m32, x, y, partials, counter, dot_out, skip, s);
-    case 2: return run_apply<N, uint16_t, float, float, TRANS, DOT>(m32, x, y, partials, counter, dot_out, skip, s);
+    case 0: return run_apply<N, double, double, double, TRANS, DOT>(m64, x, y, partials, st, par, skip, s);
+    case 1: return run_apply<N, float, float, float, TRANS, DOT>(m32, x, y, partials, st, par, skip, s);
+    case 2: return run_apply<N, uint16_t, float, float, TRANS, DOT>(m32, x, y, partials, st, par, skip, s);
   }
   return hipErrorInvalidValue;
 }
@@ -502,26 +551,26 @@ static hipError_t run_apply_prec(int prec, const MeshArgs<double>& m64, const Me
 template <int N>
 static hipError_t run_apply_n(int prec, int trans, int dot, const MeshArgs<double>& m64,
                               const MeshArgs<float>& m32, const void* x, void* y, double* partials,
-                              unsigned* counter, double* dot_out, const int* skip, hipStream_t s) {
+                              CgState* st, int par, const int* skip, hipStream_t s) {
   if (trans) {
-    if (dot) return run_apply_prec<N, true, true>(prec, m64, m32, x, y, partials, counter, dot_out, skip, s);
-    return run_apply_prec<N, true, false>(prec, m64, m32, x, y, partials, counter, dot_out, skip, s);
+    if (dot) return run_apply_prec<N, true, true>(prec, m64, m32, x, y, partials, st, par, skip, s);
+    return run_apply_prec<N, true, false>(prec, m64, m32, x, y, partials, st, par, skip, s);
   }
-  if (dot) return run_apply_prec<N, false, true>(prec, m64, m32, x, y, partials, counter, dot_out, skip, s);
-  return run_apply_prec<N, false, false>(prec, m64, m32, x, y, partials, counter, dot_out, skip, s);
+  if (dot) return run_apply_prec<N, false, true>(prec, m64, m32, x, y, partials, st, par, skip, s);
+  return run_apply_prec<N, false, false>(prec, m64, m32, x, y, partials, st, par, skip, s);
 }
 
 hipError_t launch_apply_affine(int n, int prec, int trans, int dot, const MeshArgs<double>& m64,
                                const MeshArgs<float>& m32, const void* x, void* y, double* partials,
-                               unsigned* counter, double* dot_out, const int* skip, hipStream_t s) {
+                               CgState* st, int par, const int* skip, hipStream_t s) {
   switch (n) {
-    case 2: return run_apply_n<2>(prec, trans, dot, m64, m32, x, y, partials, counter, dot_out, skip, s);
-    case 3: return run_apply_n<3>(prec, trans, dot, m64, m32, x, y, partials, counter, dot_out, skip, s);
-    case 4: return run_apply_n<4>(prec, trans, dot, m64, m32, x, y, partials, counter, dot_out, skip, s);
-    case 5: return run_apply_n<5>(prec, trans, dot, m64, m32, x, y, partials, counter, dot_out, skip, s);
-    case 6: return run_apply_n<6>(prec, trans, dot, m64, m32, x, y, partials, counter, dot_out, skip, s);
-    case 7: return run_apply_n<7>(prec, trans, dot, m64, m32, x, y, partials, counter, dot_out, skip, s);
-    case 8: return run_apply_n<8>(prec, trans, dot, m64, m32, x, y, partials, counter, dot_out, skip, s);
+    case 2: return run_apply_n<2>(prec, trans, dot, m64, m32, x, y, partials, st, par, skip, s);
+    case 3: return run_apply_n<3>(prec, trans, dot, m64, m32, x, y, partials, st, par, skip, s);
+    case 4: return run_apply_n<4>(prec, trans, dot, m64, m32, x, y, partials, st, par, skip, s);
+    case 5: return run_apply_n<5>(prec, trans, dot, m64, m32, x, y, partials, st, par, skip, s);
+    case 6: return run_apply_n<6>(prec, trans, dot, m64, m32, x, y, partials, st, par, skip, s);
+    case 7: return run_apply_n<7>(prec, trans, dot, m64, m32, x, y, partials, st, par, skip, s);
+    case 8: return run_apply_n<8>(prec, trans, dot, m64, m32, x, y, partials, st, par, skip, s);
   }
   return hipErrorInvalidValue;
 }

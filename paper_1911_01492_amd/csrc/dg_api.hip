@@ -29,6 +29,8 @@ struct dg_ctx {
   Tables<float>* tab32;
   double* K64;
   float* K32;
+  double* G64;           // face coefficients, 6 per element
+  float* G32;
   double* vert64;
   float* vert32;
   double* dinv64;
@@ -245,7 +247,7 @@ void tables_to_f32(const Tables<double>& a, Tables<float>& b) {
 
 // ------------------------------------------------------------------ workspace
 struct Layout {
-  size_t tab64, tab32, K64, K32, vert64, vert32, dinv64, dinv32, r64, p64, q64, r32, d32, p32, q32, p16,
+  size_t tab64, tab32, K64, K32, G64, G32, vert64, vert32, dinv64, dinv32, r64, p64, q64, r32, d32, p32, q32, p16,
       partials, st, total;
 };
 
@@ -282,6 +284,8 @@ Layout layout(const dg_mesh_desc* m) {
   L.tab32 = take(sizeof(Tables<float>));
   L.K64 = take(E * sizeof(double));
   L.K32 = take(E * sizeof(float));
+  L.G64 = take(6 * E * sizeof(double));
+  L.G32 = take(6 * E * sizeof(float));
   L.vert64 = take(tri ? nv * 3 * sizeof(double) : 0);
   L.vert32 = take(tri ? nv * 3 * sizeof(float) : 0);
   L.dinv64 = take(nd * sizeof(double));
@@ -294,11 +298,26 @@ Layout layout(const dg_mesh_desc* m) {
   L.p32 = take(nd * sizeof(float));
   L.q32 = take(nd * sizeof(float));
   L.p16 = take(nd * sizeof(uint16_t));
-  const int64_t nb = std::max<int64_t>(element_blocks(n, E), kMaxVecBlocks);
+  const int64_t nb = std::max<int64_t>(std::max<int64_t>(element_blocks(n, E), vec_blocks(nd)),
+                                       affine_tiles(n, m->nx, m->ny, m->nz));
   L.partials = take((size_t)nb * 3 * sizeof(double));
   L.st = take(2 * sizeof(CgState));
   L.total = o;
   return L;
+}
+
+// 1/h_d, sigma_e = sig_hat / h_d, face area and At / h_d, computed in FP64
+template <typename T>
+void fill_scales(MeshArgs<T>& m) {
+  const double h[3] = {1.0 / m.nx, 1.0 / m.ny, 1.0 / m.nz};
+  const double sh = (double)m.sig_hat;
+  for (int d = 0; d < 3; ++d) {
+    const double at = h[(d + 1) % 3] * h[(d + 2) % 3];
+    m.ih[d] = (T)(1.0 / h[d]);
+    m.sg[d] = (T)(sh / h[d]);
+    m.At[d] = (T)at;
+    m.vs[d] = (T)(at / h[d]);
+  }
 }
 
 MeshArgs<double> args64(const dg_ctx* c) {
@@ -313,8 +332,10 @@ MeshArgs<double> args64(const dg_ctx* c) {
   m.hz = 1.0 / c->desc.nz;
   m.sig_hat = c->desc.penalty_hat > 0 ? c->desc.penalty_hat : 2.0 * c->n * c->n;
   m.K = c->K64;
+  m.G = c->G64;
   m.vert = c->vert64;
   m.tab = c->tab64;
+  fill_scales(m);
   return m;
 }
 MeshArgs<float> args32(const dg_ctx* c) {
@@ -329,20 +350,29 @@ MeshArgs<float> args32(const dg_ctx* c) {
   m.hz = (float)(1.0 / c->desc.nz);
   m.sig_hat = (float)(c->desc.penalty_hat > 0 ? c->desc.penalty_hat : 2.0 * c->n * c->n);
   m.K = c->K32;
+  m.G = c->G32;
   m.vert = c->vert32;
   m.tab = c->tab32;
+  fill_scales(m);
   return m;
 }
 
-hipError_t apply_any(dg_ctx* c, int prec, int trans, int dot, const void* x, void* y, double* dot_out,
+// dot != 0: <x, A x> into st->pq (st must then be given; par selects rho for the
+// breakdown check)
+hipError_t apply_any(dg_ctx* c, int prec, int trans, int dot, const void* x, void* y, CgState* st, int par,
                      const int* skip, hipStream_t s) {
   const MeshArgs<double> m64 = args64(c);
   const MeshArgs<float> m32 = args32(c);
-  unsigned* counter = &c->st[0].counter;
   if (c->trilinear)
-    return launch_apply_trilinear(c->n, prec, trans, dot, m64, m32, x, y, c->partials, counter, dot_out,
-                                  skip, s);
-  return launch_apply_affine(c->n, prec, trans, dot, m64, m32, x, y, c->partials, counter, dot_out, skip, s);
+    return launch_apply_trilinear(c->n, prec, trans, dot, m64, m32, x, y, c->partials, st, par, skip, s);
+  return launch_apply_affine(c->n, prec, trans, dot, m64, m32, x, y, c->partials, st, par, skip, s);
+}
+
+hipError_t coef_setup(dg_ctx* c, const double* theta, hipStream_t s) {
+  hipError_t e = launch_exp(c->E, theta, c->K64, c->K32, s);
+  if (e != hipSuccess) return e;
+  MeshArgs<double> m = args64(c);
+  return launch_face_coef(m, c->G64, c->G32, s);
 }
 
 hipError_t compute_dinv(dg_ctx* c, hipStream_t s) {
@@ -390,6 +420,8 @@ int dg_setup(const dg_mesh_desc* mesh, dg_ctx** out, void* stream) {
   c->tab32 = (Tables<float>*)(w + L.tab32);
   c->K64 = (double*)(w + L.K64);
   c->K32 = (float*)(w + L.K32);
+  c->G64 = (double*)(w + L.G64);
+  c->G32 = (float*)(w + L.G32);
   c->vert64 = c->trilinear ? (double*)(w + L.vert64) : nullptr;
   c->vert32 = c->trilinear ? (float*)(w + L.vert32) : nullptr;
   c->dinv64 = (double*)(w + L.dinv64);
@@ -423,7 +455,7 @@ int dg_setup(const dg_mesh_desc* mesh, dg_ctx** out, void* stream) {
   SETUP_TRY(hipMemcpyAsync(c->tab64, &t64, sizeof(t64), hipMemcpyHostToDevice, s));
   SETUP_TRY(hipMemcpyAsync(c->tab32, &t32, sizeof(t32), hipMemcpyHostToDevice, s));
   SETUP_TRY(hipMemsetAsync(c->st, 0, 2 * sizeof(CgState), s));
-  SETUP_TRY(launch_exp(c->E, mesh->theta, c->K64, c->K32, s));
+  SETUP_TRY(coef_setup(c, mesh->theta, s));
   if (c->trilinear) {
     const int64_t nv3 = (int64_t)(mesh->nx + 1) * (mesh->ny + 1) * (mesh->nz + 1) * 3;
     SETUP_TRY(hipMemcpyAsync(c->vert64, mesh->vertices, nv3 * sizeof(double), hipMemcpyDeviceToDevice, s));
@@ -442,7 +474,7 @@ int dg_set_theta(dg_ctx* c, const double* theta, void* stream) {
   if (!c) return fail(nullptr, DG_ERR_ARG, "ctx is NULL");
   if (!theta) return fail(c, DG_ERR_ARG, "theta is NULL");
   hipStream_t s = (hipStream_t)stream;
-  HIP_TRY(c, launch_exp(c->E, theta, c->K64, c->K32, s));
+  HIP_TRY(c, coef_setup(c, theta, s));
   HIP_TRY(c, compute_dinv(c, s));
   return DG_OK;
 }
@@ -460,7 +492,7 @@ static int apply_common(dg_ctx* c, int prec, int trans, const void* x, void* y, 
   const char* xb = (const char*)x;
   const char* yb = (const char*)y;
   if (xb < yb + c->ndof * eout && yb < xb + c->ndof * ein) return fail(c, DG_ERR_ARG, "x and y overlap");
-  HIP_TRY(c, apply_any(c, prec, trans, 0, x, y, nullptr, nullptr, (hipStream_t)stream));
+  HIP_TRY(c, apply_any(c, prec, trans, 0, x, y, nullptr, 0, nullptr, (hipStream_t)stream));
   return DG_OK;
 }
 
@@ -526,7 +558,7 @@ int pcg64(dg_ctx* c, const dg_cg_opts* o, const double* b, double* x, int maxit,
   const double* dinv = o->precond == DG_PC_JACOBI ? c->dinv64 : nullptr;
   CgState* st = &c->st[0];
   const int check = o->check_every > 0 ? o->check_every : 8;
-  HIP_TRY(c, apply_any(c, DG_F64, o->transpose, 0, x, c->q64, nullptr, nullptr, s));
+  HIP_TRY(c, apply_any(c, DG_F64, o->transpose, 0, x, c->q64, nullptr, 0, nullptr, s));
   HIP_TRY(c, (launch_cg_init<double, double, double, double>(n, b, c->q64, c->r64, c->p64, dinv, o->rtol, st,
                                                             c->partials, s)));
   CgState hs;
@@ -537,7 +569,7 @@ int pcg64(dg_ctx* c, const dg_cg_opts* o, const double* b, double* x, int maxit,
     const int chunk = std::min(check, maxit - it);
     for (int j = 0; j < chunk; ++j, ++it) {
       const int par = it & 1;
-      HIP_TRY(c, apply_any(c, DG_F64, o->transpose, 1, c->p64, c->q64, &st->pq, &st->done, s));
+      HIP_TRY(c, apply_any(c, DG_F64, o->transpose, 1, c->p64, c->q64, st, par, &st->done, s));
       HIP_TRY(c, (launch_cg_update<double, double, double, double>(n, x, c->r64, c->p64, c->q64, dinv, par, st,
                                                                   c->partials, s)));
       HIP_TRY(c, (launch_cg_pupdate<double, double, double>(n, c->r64, c->p64, dinv, par, st, s)));
@@ -551,7 +583,7 @@ int pcg64(dg_ctx* c, const dg_cg_opts* o, const double* b, double* x, int maxit,
 }
 
 int true_residual(dg_ctx* c, int transpose, const double* b, const double* x, double& rel, hipStream_t s) {
-  HIP_TRY(c, apply_any(c, DG_F64, transpose, 0, x, c->q64, nullptr, nullptr, s));
+  HIP_TRY(c, apply_any(c, DG_F64, transpose, 0, x, c->q64, nullptr, 0, nullptr, s));
   HIP_TRY(c, launch_resid_norm(c->ndof, b, c->q64, &c->st[0], c->partials, s));
   CgState hs;
   int rc = read_state(c, 0, hs, s);
@@ -579,7 +611,7 @@ int pcg_inner(dg_ctx* c, const dg_cg_opts* o, int prec, double inner_rtol, int m
     const int chunk = std::min(check, maxit - it);
     for (int j = 0; j < chunk; ++j, ++it) {
       const int par = it & 1;
-      HIP_TRY(c, apply_any(c, prec, o->transpose, 1, p, c->q32, &st->pq, &st->done, s));
+      HIP_TRY(c, apply_any(c, prec, o->transpose, 1, p, c->q32, st, par, &st->done, s));
       HIP_TRY(c, (launch_cg_update<float, float, TP, float>(n, c->d32, c->r32, p, c->q32, dinv, par, st,
                                                             c->partials, s)));
       HIP_TRY(c, (launch_cg_pupdate<float, TP, float>(n, c->r32, p, dinv, par, st, s)));
@@ -630,7 +662,7 @@ int dg_cg_solve(dg_ctx* c, const dg_cg_opts* o, const double* b, double* x, dg_c
     const int max_outer = o->max_outer > 0 ? o->max_outer : 30;
     int outer = 0;
     for (;;) {
-      HIP_TRY(c, apply_any(c, DG_F64, o->transpose, 0, x, c->q64, nullptr, nullptr, s));
+      HIP_TRY(c, apply_any(c, DG_F64, o->transpose, 0, x, c->q64, nullptr, 0, nullptr, s));
       HIP_TRY(c, launch_dc_residual(c->ndof, b, c->q64, c->r32, &c->st[0], c->partials, s));
       CgState hs;
       rc = read_state(c, 0, hs, s);

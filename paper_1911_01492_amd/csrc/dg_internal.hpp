@@ -36,8 +36,14 @@ struct MeshArgs {
   T hx, hy, hz;         // 1/nx, 1/ny, 1/nz
   T sig_hat;            // penalty_hat (sigma_e = sig_hat / h_d)
   const T* K;           // E coefficients K_T = exp(theta_T)
+  const T* G;           // 6 per element: face coefficient of face (d, s) at [6e + 2d + s]:
+                        // gamma_e / 2 = K K' / (K + K') on interior faces, K on Dirichlet faces
   const T* vert;        // trilinear meshes: (nx+1)(ny+1)(nz+1) x 3 vertex coordinates
   const Tables<T>* tab; // 1D tables
+  T ih[3];              // 1 / h_d
+  T sg[3];              // sigma_e = sig_hat / h_d
+  T At[3];              // face area h_t1 h_t2 of faces normal to d
+  T vs[3];              // At_d / h_d (volume stiffness scale along d, without K)
 };
 
 // Block -> logical tile: consecutive logical tiles go to the same XCD (the
@@ -102,28 +108,26 @@ __device__ double block_sum(double v, double* red /* BLOCK/64 entries */) {
   return s;
 }
 
-// Grid-level finish of a set of per-block partial sums: the last block to
-// arrive sums the partials in block order (deterministic), calls fin(totals)
-// with thread 0, and resets the arrival counter.  NV values per block.
-template <int NV, int BLOCK, typename Fin>
-__device__ void grid_finish(const double (&mine)[NV], double* partials, unsigned* counter,
-                            int64_t nblocks, int64_t myblock, Fin fin) {
-  __shared__ bool last;
-  __shared__ double red[NV][BLOCK / 64 + 1];
+// Per-block partial sums are written with plain stores and summed by a
+// separate single-block kernel launched next on the same stream (kernel
+// boundaries make them visible).  This avoids device-scope fences inside
+// the producing kernels, which on gfx950 would write back the XCD's L2.
+template <int NV>
+__device__ __forceinline__ void store_partials(const double (&mine)[NV], double* partials, int64_t myblock) {
   if (threadIdx.x == 0) {
 #pragma unroll
     for (int v = 0; v < NV; ++v) partials[myblock * NV + v] = mine[v];
-    __threadfence();
-    unsigned prev = atomicAdd(counter, 1u);
-    last = (prev == (unsigned)(nblocks - 1));
   }
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
+}
+
+// Deterministic sum of nblocks x NV partials by one block of kBlock threads:
+// fixed assignment of partials to threads, wave sums, then waves in order.
+template <int NV, int BLOCK>
+__device__ void sum_partials(const double* partials, int64_t nblocks, double (&tot)[NV]) {
+  __shared__ double red[NV][BLOCK / 64];
   double acc[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) acc[v] = 0.0;
-  // fixed assignment of partials to threads, then fixed-order tree
   for (int64_t b = threadIdx.x; b < nblocks; b += BLOCK) {
 #pragma unroll
     for (int v = 0; v < NV; ++v) acc[v] += partials[b * NV + v];
@@ -135,16 +139,10 @@ __device__ void grid_finish(const double (&mine)[NV], double* partials, unsigned
     if (lane == 0) red[v][w] = s;
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    double tot[NV];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      tot[v] = 0.0;
-      for (int i = 0; i < (BLOCK + 63) / 64; ++i) tot[v] += red[v][i];
-    }
-    fin(tot);
-    *counter = 0u;
-    __threadfence();
+  for (int v = 0; v < NV; ++v) {
+    tot[v] = 0.0;
+    for (int i = 0; i < BLOCK / 64; ++i) tot[v] += red[v][i];
   }
 }
 

@@ -25,15 +25,21 @@ struct CgState {
 
 constexpr int kMaxVecBlocks = 2048;
 
-// grid size of the per-element kernels
+// grid size of the per-element kernels (one block per elems_per_block(n)
+// elements), of the brick-tiled affine apply, and of the vector kernels
 int64_t element_blocks(int n, int64_t E);
+int64_t affine_tiles(int n, int nx, int ny, int nz);
+int64_t vec_blocks(int64_t n);
 
 // y = A x (trans: A^T x) on affine meshes; prec: 0 f64, 1 f32, 2 bf16 in / f32 out.
-// dot != 0: <x, y> -> *dot_out (deterministic grid reduction through partials/counter).
-// skip: device flag; when nonzero the kernel does nothing.
+// dot != 0: <x, y> -> st->pq (block partials, then a single-block finish kernel;
+// sets st->breakdown / st->done when <p, A p> is not positive, par selects rho).
+// skip: device flag; when nonzero the kernels do nothing.
 hipError_t launch_apply_affine(int n, int prec, int trans, int dot, const MeshArgs<double>& m64,
                                const MeshArgs<float>& m32, const void* x, void* y, double* partials,
-                               unsigned* counter, double* dot_out, const int* skip, hipStream_t s);
+                               CgState* st, int par, const int* skip, hipStream_t s);
+hipError_t launch_face_coef(const MeshArgs<double>& m, double* G64, float* G32, hipStream_t s);
+hipError_t launch_finish_dot(const double* partials, int64_t nblocks, CgState* st, int par, hipStream_t s);
 hipError_t launch_diag_affine(int n, const MeshArgs<double>& m, double* d, hipStream_t s);
 hipError_t launch_dA_affine(int n, const MeshArgs<double>& m, const double* u, const double* v, double* g,
                             hipStream_t s);
@@ -41,7 +47,7 @@ hipError_t launch_dA_affine(int n, const MeshArgs<double>& m, const double* u, c
 // trilinear meshes
 hipError_t launch_apply_trilinear(int n, int prec, int trans, int dot, const MeshArgs<double>& m64,
                                   const MeshArgs<float>& m32, const void* x, void* y, double* partials,
-                                  unsigned* counter, double* dot_out, const int* skip, hipStream_t s);
+                                  CgState* st, int par, const int* skip, hipStream_t s);
 hipError_t launch_diag_trilinear(int n, const MeshArgs<double>& m, double* d, hipStream_t s);
 
 // geometry / load vector (any mesh)

@@ -235,7 +235,6 @@ __device__ void face_term(const MeshArgs<TC>& m, const Tables<TC>& T, const TIN*
 template <int N, typename TIN, typename TOUT, typename TC, bool DOT>
 __global__ __launch_bounds__(kBlock) void k_apply_trilinear(MeshArgs<TC> m, const TIN* __restrict__ x,
                                                             TOUT* __restrict__ y, double* partials,
-                                                            unsigned* counter, double* dot_out,
                                                             const int* skip) {
   constexpr int NN = N * N, N3 = NN * N, EPB = elems_per_block(N);
   __shared__ TC sU[EPB * N3], sA[EPB * N3], sB[EPB * N3], sC[EPB * N3];
@@ -261,7 +260,7 @@ __global__ __launch_bounds__(kBlock) void k_apply_trilinear(MeshArgs<TC> m, cons
     ey = (int)((e / m.nx) % m.ny);
     ez = (int)(e / ((int64_t)m.nx * m.ny));
     K = m.K[e];
-    if (t < 24) corner_of(m, e, t / 3, t % 3, sX[le][t / 3][t % 3]);
+    for (int q = t; q < 24; q += NN) corner_of(m, e, q / 3, q % 3, sX[le][q / 3][q % 3]);
     glb_get<N, 2, TC, TIN>(x, e, t1, t2, uz);
     lds_put<N, 2>(U, t1, t2, uz);
     TC a[N];
@@ -388,10 +387,8 @@ __global__ __launch_bounds__(kBlock) void k_apply_trilinear(MeshArgs<TC> m, cons
     }
   }
   if (DOT) {
-    double s = block_sum<kBlock>(part, red);
-    double mine[1] = {s};
-    grid_finish<1, kBlock>(mine, partials, counter, gridDim.x, blockIdx.x,
-                           [&](const double* tot) { *dot_out = tot[0]; });
+    const double mine[1] = {block_sum<kBlock>(part, red)};
+    store_partials<1>(mine, partials, blockIdx.x);
   }
 }
 
@@ -510,46 +507,47 @@ __global__ __launch_bounds__(512) void k_diag_trilinear(MeshArgs<double> m, doub
 
 // ---------------------------------------------------------------- launchers
 template <int N, typename TIN, typename TOUT, typename TC, bool DOT>
-static hipError_t run_tri(const MeshArgs<TC>& m, const void* x, void* y, double* partials, unsigned* counter,
-                          double* dot_out, const int* skip, hipStream_t s) {
+static hipError_t run_tri(const MeshArgs<TC>& m, const void* x, void* y, double* partials, CgState* st, int par,
+                          const int* skip, hipStream_t s) {
   const int64_t nb = element_blocks(N, m.E);
   hipLaunchKernelGGL((k_apply_trilinear<N, TIN, TOUT, TC, DOT>), dim3((unsigned)nb), dim3(kBlock), 0, s, m,
-                     (const TIN*)x, (TOUT*)y, partials, counter, dot_out, skip);
-  return hipGetLastError();
+                     (const TIN*)x, (TOUT*)y, partials, skip);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || !DOT) return e;
+  return launch_finish_dot(partials, nb, st, par, s);
 }
 
 template <int N, bool DOT>
 static hipError_t run_tri_prec(int prec, const MeshArgs<double>& m64, const MeshArgs<float>& m32, const void* x,
-                               void* y, double* partials, unsigned* counter, double* dot_out, const int* skip,
-                               hipStream_t s) {
+                               void* y, double* partials, CgState* st, int par, const int* skip, hipStream_t s) {
   switch (prec) {
-    case 0: return run_tri<N, double, double, double, DOT>(m64, x, y, partials, counter, dot_out, skip, s);
-    case 1: return run_tri<N, float, float, float, DOT>(m32, x, y, partials, counter, dot_out, skip, s);
-    case 2: return run_tri<N, uint16_t, float, float, DOT>(m32, x, y, partials, counter, dot_out, skip, s);
+    case 0: return run_tri<N, double, double, double, DOT>(m64, x, y, partials, st, par, skip, s);
+    case 1: return run_tri<N, float, float, float, DOT>(m32, x, y, partials, st, par, skip, s);
+    case 2: return run_tri<N, uint16_t, float, float, DOT>(m32, x, y, partials, st, par, skip, s);
   }
   return hipErrorInvalidValue;
 }
 
 template <int N>
 static hipError_t run_tri_n(int prec, int dot, const MeshArgs<double>& m64, const MeshArgs<float>& m32,
-                            const void* x, void* y, double* partials, unsigned* counter, double* dot_out,
-                            const int* skip, hipStream_t s) {
-  if (dot) return run_tri_prec<N, true>(prec, m64, m32, x, y, partials, counter, dot_out, skip, s);
-  return run_tri_prec<N, false>(prec, m64, m32, x, y, partials, counter, dot_out, skip, s);
+                            const void* x, void* y, double* partials, CgState* st, int par, const int* skip,
+                            hipStream_t s) {
+  if (dot) return run_tri_prec<N, true>(prec, m64, m32, x, y, partials, st, par, skip, s);
+  return run_tri_prec<N, false>(prec, m64, m32, x, y, partials, st, par, skip, s);
 }
 
 hipError_t launch_apply_trilinear(int n, int prec, int trans, int dot, const MeshArgs<double>& m64,
                                   const MeshArgs<float>& m32, const void* x, void* y, double* partials,
-                                  unsigned* counter, double* dot_out, const int* skip, hipStream_t s) {
+                                  CgState* st, int par, const int* skip, hipStream_t s) {
   (void)trans;  // symmetric form: A^T x is evaluated by the same kernel
   switch (n) {
-    case 2: return run_tri_n<2>(prec, dot, m64, m32, x, y, partials, counter, dot_out, skip, s);
-    case 3: return run_tri_n<3>(prec, dot, m64, m32, x, y, partials, counter, dot_out, skip, s);
-    case 4: return run_tri_n<4>(prec, dot, m64, m32, x, y, partials, counter, dot_out, skip, s);
-    case 5: return run_tri_n<5>(prec, dot, m64, m32, x, y, partials, counter, dot_out, skip, s);
-    case 6: return run_tri_n<6>(prec, dot, m64, m32, x, y, partials, counter, dot_out, skip, s);
-    case 7: return run_tri_n<7>(prec, dot, m64, m32, x, y, partials, counter, dot_out, skip, s);
-    case 8: return run_tri_n<8>(prec, dot, m64, m32, x, y, partials, counter, dot_out, skip, s);
+    case 2: return run_tri_n<2>(prec, dot, m64, m32, x, y, partials, st, par, skip, s);
+    case 3: return run_tri_n<3>(prec, dot, m64, m32, x, y, partials, st, par, skip, s);
+    case 4: return run_tri_n<4>(prec, dot, m64, m32, x, y, partials, st, par, skip, s);
+    case 5: return run_tri_n<5>(prec, dot, m64, m32, x, y, partials, st, par, skip, s);
+    case 6: return run_tri_n<6>(prec, dot, m64, m32, x, y, partials, st, par, skip, s);
+    case 7: return run_tri_n<7>(prec, dot, m64, m32, x, y, partials, st, par, skip, s);
+    case 8: return run_tri_n<8>(prec, dot, m64, m32, x, y, partials, st, par, skip, s);
   }
   return hipErrorInvalidValue;
 }

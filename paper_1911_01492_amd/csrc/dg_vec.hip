@@ -4,14 +4,21 @@
 // The CG scalars live in device memory (CgState); every kernel reads them
 // there, so a solve needs no host round trip per iteration.  Reductions are
 // deterministic: fixed thread-to-data mapping, fixed-order tree per block,
-// and the last block to arrive sums the block partials in block order.
-// The convergence norm <r, r> is computed in the same reduction as <z, r>
-// (the merged check of Sec. 2.4), so an iteration has two reductions: <p, q>
+// block partials summed in block order by a single-block finish kernel.  The
+// convergence norm <r, r> is computed in the same reduction as <z, r> (the
+// merged check of Sec. 2.4), so an iteration has two reductions: <p, q>
 // (fused into the operator application) and {<z, r>, <r, r>}.
 #include "dg_internal.hpp"
 #include "dg_kernels.hpp"
 
 namespace dg {
+
+constexpr int kVecPerThread = 4;
+
+int64_t vec_blocks(int64_t n) {
+  int64_t b = (n + (int64_t)kBlock * kVecPerThread - 1) / ((int64_t)kBlock * kVecPerThread);
+  return b < 1 ? 1 : b;
+}
 
 template <typename TP>
 __device__ __forceinline__ double p_load(const TP* p, int64_t i) { return (double)p[i]; }
@@ -28,17 +35,21 @@ __device__ __forceinline__ void p_store<uint16_t>(uint16_t* p, int64_t i, double
 
 __device__ __forceinline__ bool finite_d(double v) { return v == v && v - v == 0.0; }
 
-// r = b - q; z = Dinv r; p = z; and {<z,r>, <r,r>, <b,b>} -> state (rho[0],
-// rr, bb, tol2 = rtol^2 bb, done, breakdown, iters = 0).  TV: type of r, q;
-// TB: type of b; TP: type of p; TD: type of Dinv (nullptr = no preconditioner).
+// element i of this thread's k-th slot: consecutive threads take consecutive
+// entries (coalesced), kVecPerThread slots per thread
+#define DG_VEC_LOOP(i, k, n)                                                              \
+  _Pragma("unroll") for (int k = 0; k < kVecPerThread; ++k)                               \
+    for (int64_t i = ((int64_t)blockIdx.x * kVecPerThread + k) * kBlock + threadIdx.x; i < (n); i = (n))
+
+// r = b - q; z = Dinv r; p = z;  partials {<z,r>, <r,r>, <b,b>}
 template <typename TB, typename TV, typename TP, typename TD>
 __global__ __launch_bounds__(kBlock) void k_cg_init(int64_t n, const TB* __restrict__ b,
                                                     const TV* __restrict__ q, TV* __restrict__ r,
                                                     TP* __restrict__ p, const TD* __restrict__ dinv,
-                                                    double rtol, CgState* st, double* partials) {
+                                                    double* partials) {
   __shared__ double red[kBlock / 64];
   double zr = 0.0, rr = 0.0, bb = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+  DG_VEC_LOOP(i, k, n) {
     const double bi = (double)b[i];
     const TV ri = (TV)(bi - (double)q[i]);
     r[i] = ri;
@@ -48,32 +59,18 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(int64_t n, const TB* __restr
     rr += (double)ri * (double)ri;
     bb += bi * bi;
   }
-  double s0 = block_sum<kBlock>(zr, red), s1 = block_sum<kBlock>(rr, red),
-         s2 = block_sum<kBlock>(bb, red);
-  double mine[3] = {s0, s1, s2};
-  grid_finish<3, kBlock>(mine, partials, &st->counter, gridDim.x, blockIdx.x, [&](const double* t) {
-    st->rho[0] = t[0];
-    st->rr = t[1];
-    st->rr0 = t[1];
-    st->bb = t[2];
-    st->tol2 = rtol * rtol * t[2];
-    st->iters = 0;
-    st->breakdown = 0;
-    st->done = (t[1] <= st->tol2) ? 1 : 0;
-    if (!finite_d(t[0]) || !finite_d(t[1])) { st->breakdown = 1; st->done = 1; }
-  });
+  const double mine[3] = {block_sum<kBlock>(zr, red), block_sum<kBlock>(rr, red), block_sum<kBlock>(bb, red)};
+  store_partials<3>(mine, partials, blockIdx.x);
 }
 
-// Inner-solve variant: the tolerance is relative to the initial residual
-// (tol2 = rtol^2 <r0, r0>), and the solution correction d starts at zero.
+// inner solve: d = 0; z = Dinv r; p = z;  partials {<z,r>, <r,r>}
 template <typename TV, typename TP, typename TD>
 __global__ __launch_bounds__(kBlock) void k_cg_init_inner(int64_t n, const TV* __restrict__ r,
                                                           TV* __restrict__ d, TP* __restrict__ p,
-                                                          const TD* __restrict__ dinv, double rtol,
-                                                          CgState* st, double* partials) {
+                                                          const TD* __restrict__ dinv, double* partials) {
   __shared__ double red[kBlock / 64];
   double zr = 0.0, rr = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+  DG_VEC_LOOP(i, k, n) {
     const double ri = (double)r[i];
     const double z = dinv ? (double)dinv[i] * ri : ri;
     d[i] = (TV)0;
@@ -81,42 +78,22 @@ __global__ __launch_bounds__(kBlock) void k_cg_init_inner(int64_t n, const TV* _
     zr += z * ri;
     rr += ri * ri;
   }
-  double s0 = block_sum<kBlock>(zr, red), s1 = block_sum<kBlock>(rr, red);
-  double mine[2] = {s0, s1};
-  grid_finish<2, kBlock>(mine, partials, &st->counter, gridDim.x, blockIdx.x, [&](const double* t) {
-    st->rho[0] = t[0];
-    st->rr = t[1];
-    st->rr0 = t[1];
-    st->bb = t[1];
-    st->tol2 = rtol * rtol * t[1];
-    st->iters = 0;
-    st->breakdown = 0;
-    st->done = (t[1] <= st->tol2) ? 1 : 0;
-    if (!finite_d(t[0]) || !finite_d(t[1])) { st->breakdown = 1; st->done = 1; }
-  });
+  const double mine[2] = {block_sum<kBlock>(zr, red), block_sum<kBlock>(rr, red)};
+  store_partials<2>(mine, partials, blockIdx.x);
 }
 
-// lambda = rho / <p, q>;  x += lambda p;  r -= lambda q;  z = Dinv r;
-// {<z, r>, <r, r>} -> rho[par ^ 1], rr; iters += 1; done when rr <= tol2.
+// lambda = rho / <p, q>;  x += lambda p;  r -= lambda q;  partials {<z,r>, <r,r>}, z = Dinv r
 template <typename TX, typename TV, typename TP, typename TD>
 __global__ __launch_bounds__(kBlock) void k_cg_update(int64_t n, TX* __restrict__ x, TV* __restrict__ r,
                                                       const TP* __restrict__ p,
                                                       const TV* __restrict__ q,
                                                       const TD* __restrict__ dinv, int par,
-                                                      CgState* st, double* partials) {
+                                                      const CgState* st, double* partials) {
   __shared__ double red[kBlock / 64];
   if (st->done) return;
-  const double pq = st->pq, rho = st->rho[par];
-  const double lam = rho / pq;
-  if (!(pq > 0.0) || !finite_d(lam)) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-      st->breakdown = 1;
-      st->done = 1;
-    }
-    return;
-  }
+  const double lam = st->rho[par] / st->pq;
   double zr = 0.0, rr = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+  DG_VEC_LOOP(i, k, n) {
     const double pi = p_load<TP>(p, i);
     x[i] = (TX)((double)x[i] + lam * pi);
     const TV ri = (TV)((double)r[i] - lam * (double)q[i]);
@@ -125,15 +102,8 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(int64_t n, TX* __restrict_
     zr += z * (double)ri;
     rr += (double)ri * (double)ri;
   }
-  double s0 = block_sum<kBlock>(zr, red), s1 = block_sum<kBlock>(rr, red);
-  double mine[2] = {s0, s1};
-  grid_finish<2, kBlock>(mine, partials, &st->counter, gridDim.x, blockIdx.x, [&](const double* t) {
-    st->rho[par ^ 1] = t[0];
-    st->rr = t[1];
-    st->iters += 1;
-    if (t[1] <= st->tol2) st->done = 1;
-    if (!finite_d(t[0]) || !finite_d(t[1])) { st->breakdown = 1; st->done = 1; }
-  });
+  const double mine[2] = {block_sum<kBlock>(zr, red), block_sum<kBlock>(rr, red)};
+  store_partials<2>(mine, partials, blockIdx.x);
 }
 
 // p = z + (rho[par^1] / rho[par]) p,  z = Dinv r
@@ -143,129 +113,159 @@ __global__ __launch_bounds__(kBlock) void k_cg_pupdate(int64_t n, const TV* __re
                                                        int par, const CgState* st) {
   if (st->done) return;
   const double beta = st->rho[par ^ 1] / st->rho[par];
-  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+  DG_VEC_LOOP(i, k, n) {
     const double ri = (double)r[i];
     const double z = dinv ? (double)dinv[i] * ri : ri;
     p_store<TP>(p, i, z + beta * p_load<TP>(p, i));
   }
 }
 
-// FP64 outer residual of the defect correction: r64 = b - q64, r32 = fp32(r64),
-// <r64, r64> and <b, b> -> st->rr, st->bb.
+// FP64 outer residual of the defect correction: r64 = b - q64, r32 = fp32(r64);
+// partials {<r64, r64>, <b, b>}
 __global__ __launch_bounds__(kBlock) void k_dc_residual(int64_t n, const double* __restrict__ b,
                                                         const double* __restrict__ q,
-                                                        float* __restrict__ r32, CgState* st,
-                                                        double* partials) {
+                                                        float* __restrict__ r32, double* partials) {
   __shared__ double red[kBlock / 64];
   double rr = 0.0, bb = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+  DG_VEC_LOOP(i, k, n) {
     const double bi = b[i];
     const double ri = bi - q[i];
     r32[i] = (float)ri;
     rr += ri * ri;
     bb += bi * bi;
   }
-  double s0 = block_sum<kBlock>(rr, red), s1 = block_sum<kBlock>(bb, red);
-  double mine[2] = {s0, s1};
-  grid_finish<2, kBlock>(mine, partials, &st->counter, gridDim.x, blockIdx.x, [&](const double* t) {
-    st->rr = t[0];
-    st->bb = t[1];
-  });
+  const double mine[2] = {block_sum<kBlock>(rr, red), block_sum<kBlock>(bb, red)};
+  store_partials<2>(mine, partials, blockIdx.x);
 }
 
 // x += d (FP64 solution update from the FP32 correction)
 __global__ __launch_bounds__(kBlock) void k_dc_update(int64_t n, double* __restrict__ x,
                                                       const float* __restrict__ d) {
-  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
-    x[i] += (double)d[i];
+  DG_VEC_LOOP(i, k, n) x[i] += (double)d[i];
 }
 
-// <b - q, b - q> and <b, b> (true residual check)
+// partials {<b - q, b - q>, <b, b>} (true residual check)
 __global__ __launch_bounds__(kBlock) void k_resid_norm(int64_t n, const double* __restrict__ b,
-                                                       const double* __restrict__ q, CgState* st,
-                                                       double* partials) {
+                                                       const double* __restrict__ q, double* partials) {
   __shared__ double red[kBlock / 64];
   double rr = 0.0, bb = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+  DG_VEC_LOOP(i, k, n) {
     const double ri = b[i] - q[i];
     rr += ri * ri;
     bb += b[i] * b[i];
   }
-  double s0 = block_sum<kBlock>(rr, red), s1 = block_sum<kBlock>(bb, red);
-  double mine[2] = {s0, s1};
-  grid_finish<2, kBlock>(mine, partials, &st->counter, gridDim.x, blockIdx.x, [&](const double* t) {
-    st->true_rr = t[0];
-    st->true_bb = t[1];
-  });
+  const double mine[2] = {block_sum<kBlock>(rr, red), block_sum<kBlock>(bb, red)};
+  store_partials<2>(mine, partials, blockIdx.x);
 }
 
-// elementwise helpers
-__global__ void k_exp(int64_t n, const double* __restrict__ th, double* __restrict__ K64,
-                      float* __restrict__ K32) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const double k = th ? exp(th[i]) : 1.0;
-  K64[i] = k;
-  K32[i] = (float)k;
+// ---------------------------------------------------------------- finish kernels
+// mode: what the totals mean and which state fields they set
+enum FinishMode {
+  FIN_DOT = 0,       // 1 value: pq
+  FIN_INIT = 1,      // 3 values: rho[0], rr (= rr0), bb; tol2 = rtol^2 bb
+  FIN_INIT_INNER = 2,// 2 values: rho[0], rr (= rr0 = bb); tol2 = rtol^2 rr
+  FIN_UPDATE = 3,    // 2 values: rho[par^1], rr; iters++; done when rr <= tol2
+  FIN_DC = 4,        // 2 values: rr, bb
+  FIN_TRUE = 5       // 2 values: true_rr, true_bb
+};
+
+template <int NV, int MODE>
+__global__ __launch_bounds__(kBlock) void k_finish(const double* partials, int64_t nblocks, CgState* st,
+                                                   int par, double rtol) {
+  if (MODE == FIN_DOT || MODE == FIN_UPDATE) {
+    if (st->done) return;
+  }
+  double t[NV];
+  sum_partials<NV, kBlock>(partials, nblocks, t);
+  if (threadIdx.x != 0) return;
+  if (MODE == FIN_DOT) {
+    st->pq = t[0];
+    const double lam = st->rho[par] / t[0];
+    if (!(t[0] > 0.0) || !finite_d(lam)) {
+      st->breakdown = 1;
+      st->done = 1;
+    }
+  } else if (MODE == FIN_INIT || MODE == FIN_INIT_INNER) {
+    st->rho[0] = t[0];
+    st->rr = t[1];
+    st->rr0 = t[1];
+    st->bb = MODE == FIN_INIT ? t[2] : t[1];
+    st->tol2 = rtol * rtol * st->bb;
+    st->iters = 0;
+    st->breakdown = 0;
+    st->done = (t[1] <= st->tol2) ? 1 : 0;
+    if (!finite_d(t[0]) || !finite_d(t[1])) {
+      st->breakdown = 1;
+      st->done = 1;
+    }
+  } else if (MODE == FIN_UPDATE) {
+    st->rho[par ^ 1] = t[0];
+    st->rr = t[1];
+    st->iters += 1;
+    if (t[1] <= st->tol2) st->done = 1;
+    if (!finite_d(t[0]) || !finite_d(t[1])) {
+      st->breakdown = 1;
+      st->done = 1;
+    }
+  } else if (MODE == FIN_DC) {
+    st->rr = t[0];
+    st->bb = t[1];
+  } else {
+    st->true_rr = t[0];
+    st->true_bb = t[1];
+  }
 }
-__global__ void k_inv_diag(int64_t n, const double* __restrict__ d, double* __restrict__ i64,
-                           float* __restrict__ i32) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const double v = 1.0 / d[i];
-  i64[i] = v;
-  i32[i] = (float)v;
+
+template <int NV, int MODE>
+static hipError_t finish(const double* partials, int64_t nb, CgState* st, int par, double rtol, hipStream_t s) {
+  hipLaunchKernelGGL((k_finish<NV, MODE>), dim3(1), dim3(kBlock), 0, s, partials, nb, st, par, rtol);
+  return hipGetLastError();
 }
-__global__ void k_to_f32(int64_t n, const double* __restrict__ a, float* __restrict__ b) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) b[i] = (float)a[i];
+
+hipError_t launch_finish_dot(const double* partials, int64_t nblocks, CgState* st, int par, hipStream_t s) {
+  return finish<1, FIN_DOT>(partials, nblocks, st, par, 0.0, s);
 }
 
 // ---------------------------------------------------------------- launchers
-static int vec_blocks(int64_t n) {
-  int64_t b = (n + kBlock * 4 - 1) / (kBlock * 4);
-  if (b < 1) b = 1;
-  if (b > kMaxVecBlocks) b = kMaxVecBlocks;
-  return (int)b;
-}
-
-#define DG_LAUNCH_CHECK() \
-  do {                                  \
-    hipError_t e_ = hipGetLastError();  \
-    if (e_ != hipSuccess) return e_;    \
+#define DG_TRY(expr)                     \
+  do {                                   \
+    hipError_t e_ = (expr);              \
+    if (e_ != hipSuccess) return e_;     \
   } while (0)
 
 template <typename TB, typename TV, typename TP, typename TD>
 hipError_t launch_cg_init(int64_t n, const TB* b, const TV* q, TV* r, TP* p, const TD* dinv, double rtol,
                           CgState* st, double* partials, hipStream_t s) {
-  hipLaunchKernelGGL((k_cg_init<TB, TV, TP, TD>), dim3(vec_blocks(n)), dim3(kBlock), 0, s, n, b, q, r, p,
-                     dinv, rtol, st, partials);
-  DG_LAUNCH_CHECK();
-  return hipSuccess;
+  const int64_t nb = vec_blocks(n);
+  hipLaunchKernelGGL((k_cg_init<TB, TV, TP, TD>), dim3((unsigned)nb), dim3(kBlock), 0, s, n, b, q, r, p, dinv,
+                     partials);
+  DG_TRY(hipGetLastError());
+  return finish<3, FIN_INIT>(partials, nb, st, 0, rtol, s);
 }
 template <typename TV, typename TP, typename TD>
 hipError_t launch_cg_init_inner(int64_t n, const TV* r, TV* d, TP* p, const TD* dinv, double rtol,
                                 CgState* st, double* partials, hipStream_t s) {
-  hipLaunchKernelGGL((k_cg_init_inner<TV, TP, TD>), dim3(vec_blocks(n)), dim3(kBlock), 0, s, n, r, d, p,
-                     dinv, rtol, st, partials);
-  DG_LAUNCH_CHECK();
-  return hipSuccess;
+  const int64_t nb = vec_blocks(n);
+  hipLaunchKernelGGL((k_cg_init_inner<TV, TP, TD>), dim3((unsigned)nb), dim3(kBlock), 0, s, n, r, d, p, dinv,
+                     partials);
+  DG_TRY(hipGetLastError());
+  return finish<2, FIN_INIT_INNER>(partials, nb, st, 0, rtol, s);
 }
 template <typename TX, typename TV, typename TP, typename TD>
 hipError_t launch_cg_update(int64_t n, TX* x, TV* r, const TP* p, const TV* q, const TD* dinv, int par,
                             CgState* st, double* partials, hipStream_t s) {
-  hipLaunchKernelGGL((k_cg_update<TX, TV, TP, TD>), dim3(vec_blocks(n)), dim3(kBlock), 0, s, n, x, r, p, q,
-                     dinv, par, st, partials);
-  DG_LAUNCH_CHECK();
-  return hipSuccess;
+  const int64_t nb = vec_blocks(n);
+  hipLaunchKernelGGL((k_cg_update<TX, TV, TP, TD>), dim3((unsigned)nb), dim3(kBlock), 0, s, n, x, r, p, q, dinv,
+                     par, st, partials);
+  DG_TRY(hipGetLastError());
+  return finish<2, FIN_UPDATE>(partials, nb, st, par, 0.0, s);
 }
 template <typename TV, typename TP, typename TD>
 hipError_t launch_cg_pupdate(int64_t n, const TV* r, TP* p, const TD* dinv, int par, const CgState* st,
                              hipStream_t s) {
-  hipLaunchKernelGGL((k_cg_pupdate<TV, TP, TD>), dim3(vec_blocks(n)), dim3(kBlock), 0, s, n, r, p, dinv,
-                     par, st);
-  DG_LAUNCH_CHECK();
-  return hipSuccess;
+  hipLaunchKernelGGL((k_cg_pupdate<TV, TP, TD>), dim3((unsigned)vec_blocks(n)), dim3(kBlock), 0, s, n, r, p,
+                     dinv, par, st);
+  return hipGetLastError();
 }
 
 // explicit instantiations used by the host solvers
@@ -300,35 +300,56 @@ template hipError_t launch_cg_pupdate<float, uint16_t, float>(int64_t, const flo
 
 hipError_t launch_dc_residual(int64_t n, const double* b, const double* q, float* r32, CgState* st,
                               double* partials, hipStream_t s) {
-  hipLaunchKernelGGL(k_dc_residual, dim3(vec_blocks(n)), dim3(kBlock), 0, s, n, b, q, r32, st, partials);
-  DG_LAUNCH_CHECK();
-  return hipSuccess;
+  const int64_t nb = vec_blocks(n);
+  hipLaunchKernelGGL(k_dc_residual, dim3((unsigned)nb), dim3(kBlock), 0, s, n, b, q, r32, partials);
+  DG_TRY(hipGetLastError());
+  return finish<2, FIN_DC>(partials, nb, st, 0, 0.0, s);
 }
 hipError_t launch_dc_update(int64_t n, double* x, const float* d, hipStream_t s) {
-  hipLaunchKernelGGL(k_dc_update, dim3(vec_blocks(n)), dim3(kBlock), 0, s, n, x, d);
-  DG_LAUNCH_CHECK();
-  return hipSuccess;
+  hipLaunchKernelGGL(k_dc_update, dim3((unsigned)vec_blocks(n)), dim3(kBlock), 0, s, n, x, d);
+  return hipGetLastError();
 }
 hipError_t launch_resid_norm(int64_t n, const double* b, const double* q, CgState* st, double* partials,
                              hipStream_t s) {
-  hipLaunchKernelGGL(k_resid_norm, dim3(vec_blocks(n)), dim3(kBlock), 0, s, n, b, q, st, partials);
-  DG_LAUNCH_CHECK();
-  return hipSuccess;
+  const int64_t nb = vec_blocks(n);
+  hipLaunchKernelGGL(k_resid_norm, dim3((unsigned)nb), dim3(kBlock), 0, s, n, b, q, partials);
+  DG_TRY(hipGetLastError());
+  return finish<2, FIN_TRUE>(partials, nb, st, 0, 0.0, s);
 }
+
+// ---------------------------------------------------------------- elementwise helpers
+__global__ void k_exp(int64_t n, const double* __restrict__ th, double* __restrict__ K64,
+                      float* __restrict__ K32) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double k = th ? exp(th[i]) : 1.0;
+  K64[i] = k;
+  K32[i] = (float)k;
+}
+__global__ void k_inv_diag(int64_t n, const double* __restrict__ d, double* __restrict__ i64,
+                           float* __restrict__ i32) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double v = 1.0 / d[i];
+  i64[i] = v;
+  i32[i] = (float)v;
+}
+__global__ void k_to_f32(int64_t n, const double* __restrict__ a, float* __restrict__ b) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = (float)a[i];
+}
+
 hipError_t launch_exp(int64_t n, const double* th, double* K64, float* K32, hipStream_t s) {
   hipLaunchKernelGGL(k_exp, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, th, K64, K32);
-  DG_LAUNCH_CHECK();
-  return hipSuccess;
+  return hipGetLastError();
 }
 hipError_t launch_inv_diag(int64_t n, const double* d, double* i64, float* i32, hipStream_t s) {
   hipLaunchKernelGGL(k_inv_diag, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, d, i64, i32);
-  DG_LAUNCH_CHECK();
-  return hipSuccess;
+  return hipGetLastError();
 }
 hipError_t launch_to_f32(int64_t n, const double* a, float* b, hipStream_t s) {
   hipLaunchKernelGGL(k_to_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, a, b);
-  DG_LAUNCH_CHECK();
-  return hipSuccess;
+  return hipGetLastError();
 }
 
 }  // namespace dg
