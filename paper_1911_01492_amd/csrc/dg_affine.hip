@@ -116,6 +116,10 @@ __device__ __forceinline__ void mass_line(const Tables<TC>& T, const TC (&a)[N],
 __host__ __device__ constexpr int tile_x(int n) { return n == 2 ? 4 : n == 3 ? 4 : n == 4 ? 4 : n == 5 ? 5 : n == 6 ? 7 : n == 7 ? 5 : 4; }
 __host__ __device__ constexpr int tile_y(int n) { return n == 2 ? 4 : n == 3 ? 3 : n == 4 ? 2 : n == 5 ? 2 : 1; }
 __host__ __device__ constexpr int tile_z(int n) { return n == 2 ? 4 : n == 3 ? 2 : n == 4 ? 2 : 1; }
+// threads per workgroup of the affine apply: the brick's lines, rounded up to whole waves
+__host__ __device__ constexpr int apply_block(int n) {
+  return ((tile_x(n) * tile_y(n) * tile_z(n) * n * n + 63) / 64) * 64;
+}
 
 // neighbour coordinate along one axis (periodic wrap), -1 on a Dirichlet boundary
 __device__ __forceinline__ int nb_coord(int c, int s, int Nd, int periodic) {
@@ -127,47 +131,136 @@ __device__ __forceinline__ int nb_coord(int c, int s, int Nd, int periodic) {
   return v;
 }
 
-// The neighbour lines of axis D, side s: from the brick's LDS tiles when the
-// neighbour is inside the brick, otherwise from HBM.  has = false on a
-// Dirichlet boundary (line set to 0).
-template <int N, int D, int BX, int BY, int BZ, typename TC, typename TIN>
-__device__ __forceinline__ void neighbour_line(const TIN* __restrict__ x, const TC* sU, int nx, int ny,
-                                               const int (&c)[3], const int (&o)[3], const int (&Nd)[3],
-                                               int periodic, int s, int t1, int t2, TC (&v)[N], bool& has) {
-  constexpr int N3 = N * N * N;
-  const int cc = nb_coord(c[D], s, Nd[D], periodic);
-  has = cc >= 0;
-  if (!has) {
+// Line operator with the neighbour data reduced to the two scalars the face
+// terms need: the neighbour's trace at the shared end (U) and its raw normal
+// derivative at that end (Gr = l'(end) . line, without 1/h).  Own face
+// scalars: u[0], g0 = d0.u, u[n-1], g1 = d1.u.  Same algebra as line_op.
+template <int N, typename TC, bool TRANS>
+__device__ __forceinline__ void line_op_s(const Tables<TC>& T, const TC (&u)[N], TC g0, TC g1, TC UL, TC GLr,
+                                          TC UH, TC GHr, bool hasL, bool hasH, TC GL, TC GH, TC vs, TC ih,
+                                          TC sig, TC At, TC (&b)[N]) {
 #pragma unroll
-    for (int i = 0; i < N; ++i) v[i] = TC(0);
-    return;
+  for (int i = 0; i < N; ++i) {
+    TC s = TC(0);
+#pragma unroll
+    for (int j = 0; j < N; ++j) s += (TRANS ? T.S[j * kMaxN + i] : T.S[i * kMaxN + j]) * u[j];
+    b[i] = vs * s;
   }
-  int g[3] = {c[0], c[1], c[2]};
-  g[D] = cc;
-  const int l = cc - o[D];
-  constexpr int Bd = D == 0 ? BX : (D == 1 ? BY : BZ);
-  if (l >= 0 && l < Bd) {
-    const int el = (g[0] - o[0]) + BX * ((g[1] - o[1]) + BY * (g[2] - o[2]));
-    lds_get<N, D>(sU + el * N3, t1, t2, v);
-  } else {
-    const int64_t e = g[0] + (int64_t)nx * (g[1] + (int64_t)ny * g[2]);
-    glb_get<N, D, TC, TIN>(x, e, t1, t2, v);
+  {  // upper face: this element is T^-
+    const TC g = g1 + (hasH ? GHr : TC(0));
+    const TC J = u[N - 1] - (hasH ? UH : TC(0));
+    const TC aP = sig * GH * (hasH ? TC(2) : TC(1));
+    const TC GAi = At * GH * ih;
+    b[N - 1] += At * aP * J - GAi * g;
+    const TC cj = GAi * J;
+#pragma unroll
+    for (int i = 0; i < N; ++i) b[i] -= cj * T.d1[i];
+  }
+  {  // lower face: this element is T^+
+    const TC g = g0 + (hasL ? GLr : TC(0));
+    const TC J = (hasL ? UL : TC(0)) - u[0];
+    const TC aP = sig * GL * (hasL ? TC(2) : TC(1));
+    const TC GAi = At * GL * ih;
+    b[0] += GAi * g - At * aP * J;
+    const TC cj = GAi * J;
+#pragma unroll
+    for (int i = 0; i < N; ++i) b[i] -= cj * T.d0[i];
   }
 }
+
+// d0 . u (END = 0) or d1 . u (END = 1)
+template <int N, typename TC, int END>
+__device__ __forceinline__ TC dot_end(const Tables<TC>& T, const TC (&u)[N]) {
+  TC s = TC(0);
+#pragma unroll
+  for (int j = 0; j < N; ++j) s += (END ? T.d1[j] : T.d0[j]) * u[j];
+  return s;
+}
+
+// Neighbour face scalars along axis D for both sides.  In-brick neighbours
+// publish their own face scalars in F (written by their threads in this
+// phase), out-of-brick neighbours come from HBM, Dirichlet sides are absent.
+template <int N, int D, int BX, int BY, int BZ, typename TC, typename TIN>
+struct AxisNeighbours {
+  bool inL, inH, glL, glH, hasL, hasH;
+  int elL, elH;
+  int64_t eL, eH;
+  TC gL[N], gH[N];
+  __device__ __forceinline__ void locate(int nx, int ny, const int (&c)[3], const int (&o)[3],
+                                         const int (&Nd)[3], int periodic) {
+    constexpr int Bd = D == 0 ? BX : (D == 1 ? BY : BZ);
+    constexpr int sD = D == 0 ? 1 : (D == 1 ? BX : BX * BY);
+    const int el = (c[0] - o[0]) + BX * ((c[1] - o[1]) + BY * (c[2] - o[2]));
+    const int cl = nb_coord(c[D], 0, Nd[D], periodic), ch = nb_coord(c[D], 1, Nd[D], periodic);
+    hasL = cl >= 0;
+    hasH = ch >= 0;
+    const int ll = cl - o[D], lh = ch - o[D];
+    inL = hasL && ll >= 0 && ll < Bd;
+    inH = hasH && lh >= 0 && lh < Bd;
+    glL = hasL && !inL;
+    glH = hasH && !inH;
+    elL = el + (ll - (c[D] - o[D])) * sD;
+    elH = el + (lh - (c[D] - o[D])) * sD;
+    int g[3] = {c[0], c[1], c[2]};
+    g[D] = cl < 0 ? 0 : cl;
+    eL = g[0] + (int64_t)nx * (g[1] + (int64_t)ny * g[2]);
+    g[D] = ch < 0 ? 0 : ch;
+    eH = g[0] + (int64_t)nx * (g[1] + (int64_t)ny * g[2]);
+  }
+  // issue the HBM loads (before the own work of the phase, to hide latency)
+  __device__ __forceinline__ void fetch(const TIN* __restrict__ x, int t1, int t2) {
+    if (glL) glb_get<N, D, TC, TIN>(x, eL, t1, t2, gL);
+    if (glH) glb_get<N, D, TC, TIN>(x, eH, t1, t2, gH);
+  }
+  // the HBM neighbour lines reduced to their face scalars (frees the lines)
+  TC uL, dL, uH, dH;
+  __device__ __forceinline__ void reduce(const Tables<TC>& T) {
+    uL = dL = uH = dH = TC(0);
+    if (glL) {
+      uL = gL[N - 1];
+      dL = dot_end<N, TC, 1>(T, gL);
+    }
+    if (glH) {
+      uH = gH[0];
+      dH = dot_end<N, TC, 0>(T, gH);
+    }
+  }
+  // neighbour scalars: low side -> its upper-face (U, d1.u), high side -> its lower-face (U, d0.u)
+  __device__ __forceinline__ void scalars(const TC* F, int t, TC& UL, TC& GLr, TC& UH, TC& GHr) const {
+    constexpr int NN = N * N;
+    UL = uL;
+    GLr = dL;
+    UH = uH;
+    GHr = dH;
+    if (inL) {
+      UL = F[(elL * 4 + 2) * NN + t];
+      GLr = F[(elL * 4 + 3) * NN + t];
+    }
+    if (inH) {
+      UH = F[(elH * 4 + 0) * NN + t];
+      GHr = F[(elH * 4 + 1) * NN + t];
+    }
+  }
+};
 
 // y = A x (TRANS: A^T x) on affine meshes.  DOT: also the block partials of
 // <x, y> (y as stored) for the CG scalar <p, A p>.  skip != nullptr &&
 // *skip: do nothing (the solver has converged).
 template <int N, typename TIN, typename TOUT, typename TC, bool TRANS, bool DOT>
-__global__ __launch_bounds__(kBlock) void k_apply_affine(MeshArgs<TC> m, const TIN* __restrict__ x,
+__global__ __launch_bounds__(apply_block(N)) void k_apply_affine(MeshArgs<TC> m, const TIN* __restrict__ x,
                                                          TOUT* __restrict__ y, double* partials,
                                                          const int* skip) {
   constexpr int NN = N * N, N3 = NN * N;
   constexpr int BX = tile_x(N), BY = tile_y(N), BZ = tile_z(N), TE = BX * BY * BZ;
-  static_assert(TE * NN <= kBlock, "brick too large");
-  __shared__ TC sU[TE * N3], sA[TE * N3], sB[TE * N3];
-  __shared__ double red[kBlock / 64];
+  constexpr int PE = Lay<N, TC>::PE;
+  constexpr bool F_IN_U = 4 * NN <= PE;  // face-scalar exchange area aliases the U tiles
+  constexpr int BLOCK = apply_block(N);
+  static_assert(TE * NN <= BLOCK && BLOCK <= kBlock, "brick too large");
+  __shared__ TC sU[TE * PE], sA[TE * PE], sB[TE * PE];
+  __shared__ TC sFx[F_IN_U ? 1 : TE * 4 * NN];
+  __shared__ double red[BLOCK / 64];
   if (skip != nullptr && *skip) return;
+  TC* F = F_IN_U ? sU : sFx;
   const Tables<TC>& T = *m.tab;
   // brick coordinates: uniform per workgroup (scalar arithmetic)
   const int ntx = (m.nx + BX - 1) / BX, nty = (m.ny + BY - 1) / BY;
@@ -179,45 +272,85 @@ __global__ __launch_bounds__(kBlock) void k_apply_affine(MeshArgs<TC> m, const T
   const int c[3] = {o[0] + lx, o[1] + ly, o[2] + lz};
   const bool act = el < TE && c[0] < m.nx && c[1] < m.ny && c[2] < m.nz;
   const int le = act ? el : 0;
-  TC* U = sU + le * N3;
-  TC* A = sA + le * N3;
-  TC* B = sB + le * N3;
+  TC* U = sU + le * PE;
+  TC* A = sA + le * PE;
+  TC* B = sB + le * PE;
+  TC* Fe = F + le * 4 * NN;
   const int64_t e = c[0] + (int64_t)m.nx * (c[1] + (int64_t)m.ny * c[2]);
-  TC uz[N], K = TC(1), G[6];
+  TC uz[N], u[N], K = TC(1), G[6];
+  AxisNeighbours<N, 2, BX, BY, BZ, TC, TIN> nz;
+  AxisNeighbours<N, 1, BX, BY, BZ, TC, TIN> ny;
+  AxisNeighbours<N, 0, BX, BY, BZ, TC, TIN> nxn;
   if (act) {
+    nz.locate(m.nx, m.ny, c, o, Nd, m.periodic);
+    nz.fetch(x, t1, t2);
     glb_get<N, 2, TC, TIN>(x, e, t1, t2, uz);
     K = m.K[e];
 #pragma unroll
     for (int f = 0; f < 6; ++f) G[f] = m.G[6 * e + f];
-    lds_put<N, 2>(U, t1, t2, uz);
+    nz.reduce(T);
+  }
+  // ---------------- phase Z
+  TC g0 = TC(0), g1 = TC(0);
+  if (act) {
+    g0 = dot_end<N, TC, 0>(T, uz);
+    g1 = dot_end<N, TC, 1>(T, uz);
+    Fe[0 * NN + t] = uz[0];
+    Fe[1 * NN + t] = g0;
+    Fe[2 * NN + t] = uz[N - 1];
+    Fe[3 * NN + t] = g1;
   }
   __syncthreads();
-  if (act) {  // phase Z
-    TC uL[N], uH[N], b[N];
-    bool hL, hH;
-    neighbour_line<N, 2, BX, BY, BZ, TC, TIN>(x, sU, m.nx, m.ny, c, o, Nd, m.periodic, 0, t1, t2, uL, hL);
-    neighbour_line<N, 2, BX, BY, BZ, TC, TIN>(x, sU, m.nx, m.ny, c, o, Nd, m.periodic, 1, t1, t2, uH, hH);
-    line_op<N, TC, TRANS>(T, uz, uL, uH, hL, hH, G[4], G[5], K * m.vs[2], m.ih[2], m.sg[2], m.At[2], true, b);
+  if (act) {
+    TC UL, GLr, UH, GHr, b[N];
+    nz.scalars(F, t, UL, GLr, UH, GHr);
+    line_op_s<N, TC, TRANS>(T, uz, g0, g1, UL, GLr, UH, GHr, nz.hasL, nz.hasH, G[4], G[5], K * m.vs[2], m.ih[2],
+                            m.sg[2], m.At[2], b);
     lds_put<N, 2>(B, t1, t2, b);
   }
-  if (act) {  // phase Y (reads only U, writes A: no barrier needed after phase Z)
-    TC u[N], uL[N], uH[N], b[N];
-    bool hL, hH;
-    lds_get<N, 1>(U, t1, t2, u);
-    neighbour_line<N, 1, BX, BY, BZ, TC, TIN>(x, sU, m.nx, m.ny, c, o, Nd, m.periodic, 0, t1, t2, uL, hL);
-    neighbour_line<N, 1, BX, BY, BZ, TC, TIN>(x, sU, m.nx, m.ny, c, o, Nd, m.periodic, 1, t1, t2, uH, hH);
-    line_op<N, TC, TRANS>(T, u, uL, uH, hL, hH, G[2], G[3], K * m.vs[1], m.ih[1], m.sg[1], m.At[1], true, b);
+  __syncthreads();
+  // ---------------- phase Y
+  if (act) {
+    ny.locate(m.nx, m.ny, c, o, Nd, m.periodic);
+    ny.fetch(x, t1, t2);
+    glb_get<N, 1, TC, TIN>(x, e, t1, t2, u);
+    ny.reduce(T);
+    g0 = dot_end<N, TC, 0>(T, u);
+    g1 = dot_end<N, TC, 1>(T, u);
+    Fe[0 * NN + t] = u[0];
+    Fe[1 * NN + t] = g0;
+    Fe[2 * NN + t] = u[N - 1];
+    Fe[3 * NN + t] = g1;
+  }
+  __syncthreads();
+  if (act) {
+    TC UL, GLr, UH, GHr, b[N];
+    ny.scalars(F, t, UL, GLr, UH, GHr);
+    line_op_s<N, TC, TRANS>(T, u, g0, g1, UL, GLr, UH, GHr, ny.hasL, ny.hasH, G[2], G[3], K * m.vs[1], m.ih[1],
+                            m.sg[1], m.At[1], b);
     lds_put<N, 1>(A, t1, t2, b);
   }
   __syncthreads();
+  // ---------------- phase X
+  if (act) {
+    nxn.locate(m.nx, m.ny, c, o, Nd, m.periodic);
+    nxn.fetch(x, t1, t2);
+    glb_get<N, 0, TC, TIN>(x, e, t1, t2, u);
+    nxn.reduce(T);
+    g0 = dot_end<N, TC, 0>(T, u);
+    g1 = dot_end<N, TC, 1>(T, u);
+    Fe[0 * NN + t] = u[0];
+    Fe[1 * NN + t] = g0;
+    Fe[2 * NN + t] = u[N - 1];
+    Fe[3 * NN + t] = g1;
+  }
+  __syncthreads();
   TC bx[N];
-  if (act) {  // phase X
-    TC u[N], uL[N], uH[N], by[N], bz[N], cc[N], ee[N];
-    bool hL, hH;
-    lds_get<N, 0>(U, t1, t2, u);
-    neighbour_line<N, 0, BX, BY, BZ, TC, TIN>(x, sU, m.nx, m.ny, c, o, Nd, m.periodic, 0, t1, t2, uL, hL);
-    neighbour_line<N, 0, BX, BY, BZ, TC, TIN>(x, sU, m.nx, m.ny, c, o, Nd, m.periodic, 1, t1, t2, uH, hH);
-    line_op<N, TC, TRANS>(T, u, uL, uH, hL, hH, G[0], G[1], K * m.vs[0], m.ih[0], m.sg[0], m.At[0], true, bx);
+  if (act) {
+    TC UL, GLr, UH, GHr, by[N], bz[N], cc[N], ee[N];
+    nxn.scalars(F, t, UL, GLr, UH, GHr);
+    line_op_s<N, TC, TRANS>(T, u, g0, g1, UL, GLr, UH, GHr, nxn.hasL, nxn.hasH, G[0], G[1], K * m.vs[0],
+                            m.ih[0], m.sg[0], m.At[0], bx);
     lds_get<N, 0>(A, t1, t2, by);
     lds_get<N, 0>(B, t1, t2, bz);
     mass_line<N, TC, TRANS>(T, by, cc);
@@ -225,7 +358,7 @@ __global__ __launch_bounds__(kBlock) void k_apply_affine(MeshArgs<TC> m, const T
     lds_put<N, 0>(A, t1, t2, cc);
     lds_put<N, 0>(B, t1, t2, ee);
   }
-  __syncthreads();  // U (read as neighbour data above) is free now
+  if (F_IN_U) __syncthreads();  // the face scalars in U have been read
   if (act) lds_put<N, 0>(U, t1, t2, bx);
   __syncthreads();
   if (act) {  // phase Y2
@@ -256,7 +389,7 @@ __global__ __launch_bounds__(kBlock) void k_apply_affine(MeshArgs<TC> m, const T
     }
   }
   if (DOT) {
-    const double mine[1] = {block_sum<kBlock>(part, red)};
+    const double mine[1] = {block_sum<BLOCK>(part, red)};
     store_partials<1>(mine, partials, blockIdx.x);
   }
 }
@@ -316,8 +449,8 @@ __global__ __launch_bounds__(kBlock) void k_dA_dtheta_affine(MeshArgs<double> m,
                                                              const double* __restrict__ u,
                                                              const double* __restrict__ v,
                                                              double* __restrict__ g) {
-  constexpr int NN = N * N, N3 = NN * N, EPB = elems_per_block(N);
-  __shared__ double sU[EPB * N3], sV[EPB * N3], sW[EPB * N3], sX[EPB * N3];
+  constexpr int NN = N * N, EPB = elems_per_block(N), PE = Lay<N, double>::PE;
+  __shared__ double sU[EPB * PE], sV[EPB * PE], sW[EPB * PE], sX[EPB * PE];
   __shared__ double sF[EPB][2][NN];
   __shared__ double sPart[kBlock];
   const Tables<double>& T = *m.tab;
@@ -325,10 +458,10 @@ __global__ __launch_bounds__(kBlock) void k_dA_dtheta_affine(MeshArgs<double> m,
   const int64_t e = (int64_t)blockIdx.x * EPB + el;
   const bool act = (el < EPB) && (e < m.E);
   const int le = act ? el : 0;
-  double* U = sU + le * N3;
-  double* V = sV + le * N3;
-  double* W = sW + le * N3;
-  double* X = sX + le * N3;
+  double* U = sU + le * PE;
+  double* V = sV + le * PE;
+  double* W = sW + le * PE;
+  double* X = sX + le * PE;
   int ex = 0, ey = 0, ez = 0;
   double K = 1.0;
   double part = 0.0;
@@ -529,7 +662,7 @@ template <int N, typename TIN, typename TOUT, typename TC, bool TRANS, bool DOT>
 static hipError_t run_apply(const MeshArgs<TC>& m, const void* x, void* y, double* partials, CgState* st,
                             int par, const int* skip, hipStream_t s) {
   const int64_t nb = affine_tiles(N, m.nx, m.ny, m.nz);
-  hipLaunchKernelGGL((k_apply_affine<N, TIN, TOUT, TC, TRANS, DOT>), dim3((unsigned)nb), dim3(kBlock), 0, s, m,
+  hipLaunchKernelGGL((k_apply_affine<N, TIN, TOUT, TC, TRANS, DOT>), dim3((unsigned)nb), dim3(apply_block(N)), 0, s, m,
                      (const TIN*)x, (TOUT*)y, partials, skip);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !DOT) return e;

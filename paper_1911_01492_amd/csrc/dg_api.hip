@@ -262,7 +262,7 @@ int check_desc(const dg_mesh_desc* m, dg_ctx* c) {
   if (m->reserved != 0) return fail(c, DG_ERR_ARG, "reserved field must be 0");
   const double E = (double)m->nx * m->ny * m->nz;
   const double n3 = std::pow(m->degree + 1.0, 3);
-  if (E * n3 > 4.0e9) return fail(c, DG_ERR_ARG, "mesh too large (N_dof > 4e9)");
+  if (E * n3 >= 2147483648.0) return fail(c, DG_ERR_ARG, "mesh too large (N_dof must be below 2^31)");
   if ((double)m->nx * m->ny * m->nz > 2.0e9) return fail(c, DG_ERR_ARG, "too many elements");
   return DG_OK;
 }

@@ -236,8 +236,8 @@ template <int N, typename TIN, typename TOUT, typename TC, bool DOT>
 __global__ __launch_bounds__(kBlock) void k_apply_trilinear(MeshArgs<TC> m, const TIN* __restrict__ x,
                                                             TOUT* __restrict__ y, double* partials,
                                                             const int* skip) {
-  constexpr int NN = N * N, N3 = NN * N, EPB = elems_per_block(N);
-  __shared__ TC sU[EPB * N3], sA[EPB * N3], sB[EPB * N3], sC[EPB * N3];
+  constexpr int NN = N * N, N3 = NN * N, EPB = elems_per_block(N), PE = Lay<N, TC>::PE;
+  __shared__ TC sU[EPB * PE], sA[EPB * PE], sB[EPB * PE], sC[EPB * PE];
   __shared__ TC sX[EPB][8][3];
   __shared__ TC sF[EPB][10][NN];
   __shared__ double red[kBlock / 64];
@@ -248,10 +248,10 @@ __global__ __launch_bounds__(kBlock) void k_apply_trilinear(MeshArgs<TC> m, cons
   const int64_t e = blk * EPB + el;
   const bool act = (el < EPB) && (e < m.E);
   const int le = act ? el : 0;
-  TC* U = sU + le * N3;
-  TC* A = sA + le * N3;
-  TC* B = sB + le * N3;
-  TC* C = sC + le * N3;
+  TC* U = sU + le * PE;
+  TC* A = sA + le * PE;
+  TC* B = sB + le * PE;
+  TC* C = sC + le * PE;
   int ex = 0, ey = 0, ez = 0;
   TC K = TC(1);
   TC uz[N];
