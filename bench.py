@@ -78,6 +78,30 @@ def cold_apply(op, x, prec, reps, torch):
     return float(np.median(ts))
 
 
+KERNEL_SOURCES = ("paper_1911_01492_amd/csrc/dg_affine.hip", "paper_1911_01492_amd/csrc/dg_lines.hpp",
+                  "paper_1911_01492_amd/csrc/dg_internal.hpp")
+TRAFFIC_PROFILE = "profiles/k_apply_affine_q3_32_f64.txt"
+
+
+def measured_traffic():
+    """HBM bytes per launch of the headline kernel from the committed FETCH_SIZE / WRITE_SIZE
+    profile (copy-calibrated), or None when the kernel sources changed since it was taken."""
+    import hashlib
+    root = os.path.dirname(os.path.abspath(__file__))
+    try:
+        text = open(os.path.join(root, TRAFFIC_PROFILE)).read()
+    except OSError:
+        return None
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(root, f), "rb") as fh:
+            h.update(fh.read())
+    fields = dict(line.split(": ", 1) for line in text.splitlines() if ": " in line and not line.startswith(" "))
+    if fields.get("kernel_source_sha256_16") != h.hexdigest()[:16]:
+        return None
+    return float(fields["traffic_bytes_per_launch"])
+
+
 def cpu_baseline(seconds: float = 12.0):
     """The CPU oracle (CSR assembled by brute-force quadrature, OpenMP SpMV in
     FP64), timed on this host on a bounded sample of the headline workload:
@@ -171,7 +195,7 @@ def main():
                    "bc": "weak Dirichlet", "coefficient": "K=exp(g), g~N(0,1) per element, seed 1",
                    "x": "U(-1,1), seed 0", "step": "one FP64 operator application y = A x"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
                      "kernel": "k_apply_affine<4,double,double,double,false,false>",
                      "alg_bytes_per_dof": round(bpd, 4), "avg_launch_us": round(per * 1e6, 3),
                      "cold_launch_us": round(t_cold * 1e6, 3),
