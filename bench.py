@@ -34,6 +34,11 @@ FP64_PEAK_TFS = 78.6         # MI355X FP64 vector / MFMA (dense)
 FP32_PEAK_TFS = 157.3
 
 
+# pure FP64 PCG, then the FP64 defect correction with FP32 / BF16 inner solves,
+# restarted per correction or keeping the search direction
+CG_VARIANTS = (("f64", "restart"), ("f32", "restart"), ("bf16", "restart"), ("f32", "keep"), ("bf16", "keep"))
+
+
 def log(msg: str):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -216,11 +221,12 @@ def main():
         fq = 3 * math.pi ** 2 * torch.sin(math.pi * xq[:, 0]) * torch.sin(math.pi * xq[:, 1]) * \
             torch.sin(math.pi * xq[:, 2])
         b = op.load_vector(fq.contiguous())
-        for prec in ("f64", "f32", "bf16"):
-            op.cg_solve(b, prec_inner=prec, rtol=1e-10)  # warm
-            u, info = op.cg_solve(b, prec_inner=prec, rtol=1e-10)
-            extras[f"cg_{prec}_q3_32"] = info
-            log(f"cg {prec} q3_32: {info}")
+        for prec, mode in CG_VARIANTS:
+            op.cg_solve(b, prec_inner=prec, rtol=1e-10, dc_mode=mode)  # warm
+            u, info = op.cg_solve(b, prec_inner=prec, rtol=1e-10, dc_mode=mode)
+            tag = prec if prec == "f64" else f"{prec}_{mode}"
+            extras[f"cg_{tag}_q3_32"] = info
+            log(f"cg {tag} q3_32: {info}")
         del u, b, fq, xq
     del op, x, y
     torch.cuda.empty_cache()
@@ -257,14 +263,15 @@ def main():
         del X, ref
         torch.cuda.empty_cache()
         b3 = dev(I.uniform_vector(op3.ndof, seed=I.S_B))
-        for prec in ("f64", "f32", "bf16"):
-            u3, info = op3.cg_solve(b3, prec_inner=prec, rtol=1e-10)
-            extras[f"cg_{prec}_{wl3}"] = info
-            log(f"cg {prec} {wl3}: {info}")
+        for prec, mode in CG_VARIANTS:
+            u3, info = op3.cg_solve(b3, prec_inner=prec, rtol=1e-10, dc_mode=mode)
+            tag = prec if prec == "f64" else f"{prec}_{mode}"
+            extras[f"cg_{tag}_{wl3}"] = info
+            log(f"cg {tag} {wl3}: {info}")
             if prec == "f64":
                 u64 = u3
             else:
-                extras[f"cg_{prec}_{wl3}"]["rel_diff_vs_f64_solution"] = float(
+                extras[f"cg_{tag}_{wl3}"]["rel_diff_vs_f64_solution"] = float(
                     torch.linalg.norm(u3 - u64) / torch.linalg.norm(u64))
         del op3, b3, u3, u64
         torch.cuda.empty_cache()
@@ -296,7 +303,7 @@ def main():
             op4.dA_dtheta(lam, u)
         torch.cuda.synchronize()
         tda = (time.perf_counter() - tt) / 10
-        extras["adjoint_q3_32"] = {"loss": float(loss), "grad_norm": float(theta4.grad.norm()),
+        extras["adjoint_q3_32"] = {"loss": float(loss.detach()), "grad_norm": float(theta4.grad.norm()),
                                    "forward_plus_gradient_s": round(tg, 4), "dA_dtheta_ms": round(tda * 1e3, 4),
                                    "dA_dtheta_gdofs": round(op4.ndof / tda / 1e9, 3)}
         log(f"adjoint: {extras['adjoint_q3_32']}")

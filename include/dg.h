@@ -119,6 +119,18 @@ int dg_quadrature_points(dg_ctx* ctx, double* xq, void* stream);
  * values of f at the points of dg_quadrature_points (device, N_dof doubles). */
 int dg_load_vector(dg_ctx* ctx, const double* fq, double* b, void* stream);
 
+/* How the FP64 defect correction (prec_inner DG_F32 / DG_BF16) continues
+ * after an outer step x += d, r = b - A x (FP64):
+ *  DG_DC_RESTART  a fresh inner PCG on A d = r from d = 0 (default inner_rtol
+ *                 1e-5 for DG_F32, 1e-2 for DG_BF16; default max_outer 30);
+ *  DG_DC_KEEP     the FP64 residual replaces the inner one and CG continues
+ *                 along its current direction (p = z + beta p with the new
+ *                 residual); an inner segment ends when its residual fell by
+ *                 inner_rtol (default 0.1) or below half the outer target
+ *                 (default max_outer 200).  Falls back to a fresh direction
+ *                 after an inner breakdown. */
+enum dg_dc_mode { DG_DC_RESTART = 0, DG_DC_KEEP = 1 };
+
 typedef struct {
   int prec_inner;     /* DG_F64: FP64 PCG.  DG_F32 / DG_BF16: FP64 defect correction  *
                        * whose inner PCG runs on FP32 vectors with that apply          */
@@ -130,7 +142,7 @@ typedef struct {
   int max_outer;      /* outer corrections allowed (mixed precision)                  */
   int check_every;    /* host looks at the device convergence flag every this many     *
                        * iterations (>= 1; <= 0: default 8)                            */
-  int reserved;
+  int dc_mode;        /* enum dg_dc_mode (mixed precision only; must be valid always)  */
 } dg_cg_opts;
 
 typedef struct {

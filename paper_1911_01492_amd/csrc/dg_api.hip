@@ -570,9 +570,8 @@ int pcg64(dg_ctx* c, const dg_cg_opts* o, const double* b, double* x, int maxit,
     for (int j = 0; j < chunk; ++j, ++it) {
       const int par = it & 1;
       HIP_TRY(c, apply_any(c, DG_F64, o->transpose, 1, c->p64, c->q64, st, par, &st->done, s));
-      HIP_TRY(c, (launch_cg_update<double, double, double, double>(n, x, c->r64, c->p64, c->q64, dinv, par, st,
-                                                                  c->partials, s)));
-      HIP_TRY(c, (launch_cg_pupdate<double, double, double>(n, c->r64, c->p64, dinv, par, st, s)));
+      HIP_TRY(c, (launch_cg_update<double, double>(n, c->r64, c->q64, dinv, par, st, c->partials, s)));
+      HIP_TRY(c, (launch_cg_pupdate<double, double, double, double>(n, x, c->r64, c->p64, dinv, par, st, 0, s)));
     }
     rc = read_state(c, 0, hs, s);
     if (rc != DG_OK) return rc;
@@ -592,17 +591,24 @@ int true_residual(dg_ctx* c, int transpose, const double* b, const double* x, do
   return DG_OK;
 }
 
-// inner PCG on FP32 vectors: A_lo d = r32 to inner_rtol; TP = float or bf16
+// Inner PCG on FP32 vectors for A_lo d = r32 (TP = float or bf16 direction).
+// fresh: start from d = 0, p = z (init kernel, stop at inner_rtol ||r||);
+// otherwise continue from the state left by a residual replacement, whose
+// iteration parity is par0.  Returns iterations and the parity of the last
+// completed iteration.
 template <typename TP>
-int pcg_inner(dg_ctx* c, const dg_cg_opts* o, int prec, double inner_rtol, int maxit, int& iters, bool& broke,
-              hipStream_t s) {
+int pcg_inner(dg_ctx* c, const dg_cg_opts* o, int prec, bool fresh, double inner_rtol, int par0, int maxit,
+              int& iters, int& last_par, bool& broke, hipStream_t s) {
   const int64_t n = c->ndof;
   const float* dinv = o->precond == DG_PC_JACOBI ? c->dinv32 : nullptr;
   CgState* st = &c->st[1];
   TP* p = prec == DG_BF16 ? (TP*)c->p16 : (TP*)c->p32;
   const int check = o->check_every > 0 ? o->check_every : 8;
-  HIP_TRY(c, (launch_cg_init_inner<float, TP, float>(n, c->r32, c->d32, p, dinv, inner_rtol, st, c->partials,
-                                                     s)));
+  if (fresh) {
+    par0 = 0;
+    HIP_TRY(c, (launch_cg_init_inner<float, TP, float>(n, c->r32, c->d32, p, dinv, inner_rtol, st, c->partials,
+                                                       s)));
+  }
   CgState hs;
   int rc = read_state(c, 1, hs, s);
   if (rc != DG_OK) return rc;
@@ -610,17 +616,85 @@ int pcg_inner(dg_ctx* c, const dg_cg_opts* o, int prec, double inner_rtol, int m
   while (!hs.done && it < maxit) {
     const int chunk = std::min(check, maxit - it);
     for (int j = 0; j < chunk; ++j, ++it) {
-      const int par = it & 1;
+      const int par = (par0 + it) & 1;
       HIP_TRY(c, apply_any(c, prec, o->transpose, 1, p, c->q32, st, par, &st->done, s));
-      HIP_TRY(c, (launch_cg_update<float, float, TP, float>(n, c->d32, c->r32, p, c->q32, dinv, par, st,
-                                                            c->partials, s)));
-      HIP_TRY(c, (launch_cg_pupdate<float, TP, float>(n, c->r32, p, dinv, par, st, s)));
+      HIP_TRY(c, (launch_cg_update<float, float>(n, c->r32, c->q32, dinv, par, st, c->partials, s)));
+      HIP_TRY(c, (launch_cg_pupdate<float, float, TP, float>(n, c->d32, c->r32, p, dinv, par, st, 0, s)));
     }
     rc = read_state(c, 1, hs, s);
     if (rc != DG_OK) return rc;
   }
   iters = hs.iters;
+  last_par = (par0 + hs.iters - 1) & 1;
   broke = hs.breakdown != 0;
+  return DG_OK;
+}
+
+// FP64 defect correction around the FP32-vector inner PCG.
+// DG_DC_RESTART: every correction is a fresh inner solve to inner_rtol.
+// DG_DC_KEEP: an inner segment stops at an inner_rtol reduction of its
+// residual; x += d, the FP64 residual replaces the inner one, and CG goes on
+// along the old direction p (p = z + beta p with the replaced residual).
+template <typename TP>
+int dc_solve(dg_ctx* c, const dg_cg_opts* o, int prec, const double* b, double* x, int& total, int& outer,
+             bool& broke, double& rel, hipStream_t s) {
+  const bool keep = o->dc_mode == DG_DC_KEEP;
+  const double tin = o->inner_rtol > 0 ? o->inner_rtol
+                                       : (keep ? 0.1 : (prec == DG_F32 ? 1e-5 : 1e-2));
+  const int max_outer = o->max_outer > 0 ? o->max_outer : (keep ? 200 : 30);
+  const float* dinv = o->precond == DG_PC_JACOBI ? c->dinv32 : nullptr;
+  TP* p = prec == DG_BF16 ? (TP*)c->p16 : (TP*)c->p32;
+  bool fresh = true;
+  int last_par = 0;
+  int rc;
+  // first residual
+  HIP_TRY(c, apply_any(c, DG_F64, o->transpose, 0, x, c->q64, nullptr, 0, nullptr, s));
+  HIP_TRY(c, launch_dc_residual(c->ndof, b, c->q64, c->r32, &c->st[0], c->partials, s));
+  CgState hs;
+  rc = read_state(c, 0, hs, s);
+  if (rc != DG_OK) return rc;
+  rel = hs.bb > 0 ? std::sqrt(hs.rr / hs.bb) : std::sqrt(hs.rr);
+  for (;;) {
+    if (!(rel == rel)) {
+      broke = true;
+      break;
+    }
+    if (rel <= o->rtol || outer >= max_outer || total >= o->maxit) break;
+    int its = 0;
+    bool ib = false;
+    rc = pcg_inner<TP>(c, o, prec, fresh, tin, (last_par + 1) & 1, o->maxit - total, its, last_par, ib, s);
+    if (rc != DG_OK) return rc;
+    total += its;
+    HIP_TRY(c, launch_dc_update(c->ndof, x, c->d32, s));
+    ++outer;
+    if (ib && its == 0) {
+      broke = true;
+      break;
+    }
+    HIP_TRY(c, apply_any(c, DG_F64, o->transpose, 0, x, c->q64, nullptr, 0, nullptr, s));
+    if (keep && !ib && its > 0) {
+      // replace the residual, keep the direction
+      HIP_TRY(c, launch_dc_replace(c->ndof, b, c->q64, dinv, c->r32, &c->st[1], last_par, o->rtol, tin,
+                                   c->partials, s));
+      rc = read_state(c, 1, hs, s);
+      if (rc != DG_OK) return rc;
+      rel = hs.true_bb > 0 ? std::sqrt(hs.true_rr / hs.true_bb) : std::sqrt(hs.true_rr);
+      if (hs.breakdown) {
+        fresh = true;  // r32 holds the new residual; fall back to a fresh direction
+        continue;
+      }
+      if (rel <= o->rtol) break;
+      HIP_TRY(c, (launch_cg_pupdate<float, float, TP, float>(c->ndof, c->d32, c->r32, p, dinv, last_par,
+                                                             &c->st[1], 1, s)));
+      fresh = false;
+    } else {
+      HIP_TRY(c, launch_dc_residual(c->ndof, b, c->q64, c->r32, &c->st[0], c->partials, s));
+      rc = read_state(c, 0, hs, s);
+      if (rc != DG_OK) return rc;
+      rel = hs.bb > 0 ? std::sqrt(hs.rr / hs.bb) : std::sqrt(hs.rr);
+      fresh = true;
+    }
+  }
   return DG_OK;
 }
 
@@ -635,6 +709,7 @@ int dg_cg_solve(dg_ctx* c, const dg_cg_opts* o, const double* b, double* x, dg_c
   if (o->prec_inner != DG_F64 && o->prec_inner != DG_F32 && o->prec_inner != DG_BF16)
     return fail(c, DG_ERR_UNSUPPORTED, "unknown inner precision");
   if (o->precond != DG_PC_NONE && o->precond != DG_PC_JACOBI) return fail(c, DG_ERR_ARG, "unknown preconditioner");
+  if (o->dc_mode != DG_DC_RESTART && o->dc_mode != DG_DC_KEEP) return fail(c, DG_ERR_ARG, "unknown dc_mode");
   if (!(o->rtol > 0) || o->maxit < 1) return fail(c, DG_ERR_ARG, "rtol must be > 0 and maxit >= 1");
   if (!aligned(b, 8) || !aligned(x, 8)) return fail(c, DG_ERR_ARG, "misaligned b or x");
   hipStream_t s = (hipStream_t)stream;
@@ -658,36 +733,10 @@ int dg_cg_solve(dg_ctx* c, const dg_cg_opts* o, const double* b, double* x, dg_c
       info->restarts++;
     }
   } else {
-    const double tin = o->inner_rtol > 0 ? o->inner_rtol : (o->prec_inner == DG_F32 ? 1e-5 : 1e-2);
-    const int max_outer = o->max_outer > 0 ? o->max_outer : 30;
     int outer = 0;
-    for (;;) {
-      HIP_TRY(c, apply_any(c, DG_F64, o->transpose, 0, x, c->q64, nullptr, 0, nullptr, s));
-      HIP_TRY(c, launch_dc_residual(c->ndof, b, c->q64, c->r32, &c->st[0], c->partials, s));
-      CgState hs;
-      rc = read_state(c, 0, hs, s);
-      if (rc != DG_OK) return rc;
-      rel = hs.bb > 0 ? std::sqrt(hs.rr / hs.bb) : std::sqrt(hs.rr);
-      if (!(rel == rel)) {
-        broke = true;
-        break;
-      }
-      if (rel <= o->rtol || outer >= max_outer || total >= o->maxit) break;
-      int its = 0;
-      bool ib = false;
-      if (o->prec_inner == DG_F32)
-        rc = pcg_inner<float>(c, o, DG_F32, tin, o->maxit - total, its, ib, s);
-      else
-        rc = pcg_inner<uint16_t>(c, o, DG_BF16, tin, o->maxit - total, its, ib, s);
-      if (rc != DG_OK) return rc;
-      total += its;
-      HIP_TRY(c, launch_dc_update(c->ndof, x, c->d32, s));
-      ++outer;
-      if (ib && its == 0) {
-        broke = true;
-        break;
-      }
-    }
+    rc = o->prec_inner == DG_F32 ? dc_solve<float>(c, o, DG_F32, b, x, total, outer, broke, rel, s)
+                                 : dc_solve<uint16_t>(c, o, DG_BF16, b, x, total, outer, broke, rel, s);
+    if (rc != DG_OK) return rc;
     info->outer_iters = outer;
   }
   HIP_TRY(c, hipStreamSynchronize(s));

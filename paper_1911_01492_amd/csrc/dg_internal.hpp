@@ -120,17 +120,29 @@ __device__ __forceinline__ void store_partials(const double (&mine)[NV], double*
   }
 }
 
-// Deterministic sum of nblocks x NV partials by one block of kBlock threads:
+// Deterministic sum of nblocks x NV partials by one block of BLOCK threads:
 // fixed assignment of partials to threads, wave sums, then waves in order.
 template <int NV, int BLOCK>
 __device__ void sum_partials(const double* partials, int64_t nblocks, double (&tot)[NV]) {
+  // U loads per thread are issued before any is added, so a batch costs one
+  // memory latency (the partials come from every XCD and are not in this L2)
+  constexpr int U = 8;
   __shared__ double red[NV][BLOCK / 64];
   double acc[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) acc[v] = 0.0;
-  for (int64_t b = threadIdx.x; b < nblocks; b += BLOCK) {
+  for (int64_t b0 = threadIdx.x; b0 < nblocks; b0 += (int64_t)BLOCK * U) {
+    double val[U][NV];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) acc[v] += partials[b * NV + v];
+    for (int u = 0; u < U; ++u) {
+      const int64_t b = b0 + (int64_t)u * BLOCK;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) val[u][v] = b < nblocks ? partials[b * NV + v] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int v = 0; v < NV; ++v) acc[v] += val[u][v];
   }
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll

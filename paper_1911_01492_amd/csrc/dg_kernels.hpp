@@ -18,7 +18,7 @@ struct CgState {
   int done;         // 1 once converged or broken down: later kernels of the loop return at once
   int breakdown;    // 1 on a non-positive / non-finite CG scalar
   int iters;        // iterations completed
-  int pad0;
+  int xpend;        // 1 after an update: the deferred x += lambda p of that iteration is due
   unsigned counter; // arrival counter of the grid reductions (reset by the last block)
   unsigned pad1[3];
 };
@@ -62,15 +62,18 @@ hipError_t launch_cg_init(int64_t n, const TB* b, const TV* q, TV* r, TP* p, con
 template <typename TV, typename TP, typename TD>
 hipError_t launch_cg_init_inner(int64_t n, const TV* r, TV* d, TP* p, const TD* dinv, double rtol,
                                 CgState* st, double* partials, hipStream_t s);
+template <typename TV, typename TD>
+hipError_t launch_cg_update(int64_t n, TV* r, const TV* q, const TD* dinv, int par, CgState* st,
+                            double* partials, hipStream_t s);
 template <typename TX, typename TV, typename TP, typename TD>
-hipError_t launch_cg_update(int64_t n, TX* x, TV* r, const TP* p, const TV* q, const TD* dinv, int par,
-                            CgState* st, double* partials, hipStream_t s);
-template <typename TV, typename TP, typename TD>
-hipError_t launch_cg_pupdate(int64_t n, const TV* r, TP* p, const TD* dinv, int par, const CgState* st,
-                             hipStream_t s);
+hipError_t launch_cg_pupdate(int64_t n, TX* x, const TV* r, TP* p, const TD* dinv, int par, const CgState* st,
+                             int force_p, hipStream_t s);
 hipError_t launch_dc_residual(int64_t n, const double* b, const double* q, float* r32, CgState* st,
                               double* partials, hipStream_t s);
-hipError_t launch_dc_update(int64_t n, double* x, const float* d, hipStream_t s);
+hipError_t launch_dc_update(int64_t n, double* x, float* d, hipStream_t s);
+hipError_t launch_dc_replace(int64_t n, const double* b, const double* q, const float* dinv, float* r32,
+                             CgState* st, int par, double rtol, double reduction, double* partials,
+                             hipStream_t s);
 hipError_t launch_resid_norm(int64_t n, const double* b, const double* q, CgState* st, double* partials,
                              hipStream_t s);
 hipError_t launch_exp(int64_t n, const double* th, double* K64, float* K32, hipStream_t s);

@@ -17,7 +17,7 @@ constexpr int kVecPerThread = 4;
 
 int64_t vec_blocks(int64_t n) {
   int64_t b = (n + (int64_t)kBlock * kVecPerThread - 1) / ((int64_t)kBlock * kVecPerThread);
-  return b < 1 ? 1 : b;
+  return b < 1 ? 1 : (b > kMaxVecBlocks ? kMaxVecBlocks : b);
 }
 
 template <typename TP>
@@ -35,11 +35,14 @@ __device__ __forceinline__ void p_store<uint16_t>(uint16_t* p, int64_t i, double
 
 __device__ __forceinline__ bool finite_d(double v) { return v == v && v - v == 0.0; }
 
-// element i of this thread's k-th slot: consecutive threads take consecutive
-// entries (coalesced), kVecPerThread slots per thread
-#define DG_VEC_LOOP(i, k, n)                                                              \
-  _Pragma("unroll") for (int k = 0; k < kVecPerThread; ++k)                               \
-    for (int64_t i = ((int64_t)blockIdx.x * kVecPerThread + k) * kBlock + threadIdx.x; i < (n); i = (n))
+// Grid-stride loop over chunks of kBlock * kVecPerThread entries; within a
+// chunk consecutive threads take consecutive entries (coalesced) and each
+// thread handles kVecPerThread of them (unrolled, independent loads).
+#define DG_VEC_LOOP(i, k, n)                                                                          \
+  for (int64_t base_ = (int64_t)blockIdx.x * kBlock * kVecPerThread; base_ < (n);                     \
+       base_ += (int64_t)gridDim.x * kBlock * kVecPerThread)                                          \
+    _Pragma("unroll") for (int k = 0; k < kVecPerThread; ++k)                                         \
+      for (int64_t i = base_ + (int64_t)k * kBlock + threadIdx.x; i < (n); i = (n))
 
 // r = b - q; z = Dinv r; p = z;  partials {<z,r>, <r,r>, <b,b>}
 template <typename TB, typename TV, typename TP, typename TD>
@@ -82,11 +85,10 @@ __global__ __launch_bounds__(kBlock) void k_cg_init_inner(int64_t n, const TV* _
   store_partials<2>(mine, partials, blockIdx.x);
 }
 
-// lambda = rho / <p, q>;  x += lambda p;  r -= lambda q;  partials {<z,r>, <r,r>}, z = Dinv r
-template <typename TX, typename TV, typename TP, typename TD>
-__global__ __launch_bounds__(kBlock) void k_cg_update(int64_t n, TX* __restrict__ x, TV* __restrict__ r,
-                                                      const TP* __restrict__ p,
-                                                      const TV* __restrict__ q,
+// lambda = rho / <p, q>;  r -= lambda q;  partials {<z,r>, <r,r>}, z = Dinv r.
+// The matching x += lambda p is deferred to k_cg_pupdate, which reads p anyway.
+template <typename TV, typename TD>
+__global__ __launch_bounds__(kBlock) void k_cg_update(int64_t n, TV* __restrict__ r, const TV* __restrict__ q,
                                                       const TD* __restrict__ dinv, int par,
                                                       const CgState* st, double* partials) {
   __shared__ double red[kBlock / 64];
@@ -94,8 +96,6 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(int64_t n, TX* __restrict_
   const double lam = st->rho[par] / st->pq;
   double zr = 0.0, rr = 0.0;
   DG_VEC_LOOP(i, k, n) {
-    const double pi = p_load<TP>(p, i);
-    x[i] = (TX)((double)x[i] + lam * pi);
     const TV ri = (TV)((double)r[i] - lam * (double)q[i]);
     r[i] = ri;
     const double z = dinv ? (double)dinv[i] * (double)ri : (double)ri;
@@ -106,17 +106,27 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(int64_t n, TX* __restrict_
   store_partials<2>(mine, partials, blockIdx.x);
 }
 
-// p = z + (rho[par^1] / rho[par]) p,  z = Dinv r
-template <typename TV, typename TP, typename TD>
-__global__ __launch_bounds__(kBlock) void k_cg_pupdate(int64_t n, const TV* __restrict__ r,
+// x += lambda p when this iteration's update ran (st->xpend), then, unless the
+// solve has stopped, p = z + (rho[par^1] / rho[par]) p with z = Dinv r.
+// force_p: only the p update, with rho[par^1] just replaced by the residual
+// replacement of the defect correction (the direction is kept).
+template <typename TX, typename TV, typename TP, typename TD>
+__global__ __launch_bounds__(kBlock) void k_cg_pupdate(int64_t n, TX* __restrict__ x, const TV* __restrict__ r,
                                                        TP* __restrict__ p, const TD* __restrict__ dinv,
-                                                       int par, const CgState* st) {
-  if (st->done) return;
-  const double beta = st->rho[par ^ 1] / st->rho[par];
+                                                       int par, const CgState* st, int force_p) {
+  const bool xu = !force_p && st->xpend;
+  const bool pu = force_p ? true : !st->done;
+  if (!xu && !pu) return;
+  const double lam = xu ? st->rho[par] / st->pq : 0.0;
+  const double beta = pu ? st->rho[par ^ 1] / st->rho[par] : 0.0;
   DG_VEC_LOOP(i, k, n) {
-    const double ri = (double)r[i];
-    const double z = dinv ? (double)dinv[i] * ri : ri;
-    p_store<TP>(p, i, z + beta * p_load<TP>(p, i));
+    const double pi = p_load<TP>(p, i);
+    if (xu) x[i] = (TX)((double)x[i] + lam * pi);
+    if (pu) {
+      const double ri = (double)r[i];
+      const double z = dinv ? (double)dinv[i] * ri : ri;
+      p_store<TP>(p, i, z + beta * pi);
+    }
   }
 }
 
@@ -138,10 +148,35 @@ __global__ __launch_bounds__(kBlock) void k_dc_residual(int64_t n, const double*
   store_partials<2>(mine, partials, blockIdx.x);
 }
 
-// x += d (FP64 solution update from the FP32 correction)
-__global__ __launch_bounds__(kBlock) void k_dc_update(int64_t n, double* __restrict__ x,
-                                                      const float* __restrict__ d) {
-  DG_VEC_LOOP(i, k, n) x[i] += (double)d[i];
+// x += d (FP64 solution update from the FP32 correction); d = 0
+__global__ __launch_bounds__(kBlock) void k_dc_update(int64_t n, double* __restrict__ x, float* __restrict__ d) {
+  DG_VEC_LOOP(i, k, n) {
+    x[i] += (double)d[i];
+    d[i] = 0.0f;
+  }
+}
+
+// Residual replacement of the defect correction that keeps the inner search
+// direction: r64 = b - q64, r32 = fp32(r64), z = Dinv r32;
+// partials {<r64, r64>, <b, b>, <z, r32>}
+__global__ __launch_bounds__(kBlock) void k_dc_replace(int64_t n, const double* __restrict__ b,
+                                                       const double* __restrict__ q,
+                                                       const float* __restrict__ dinv,
+                                                       float* __restrict__ r32, double* partials) {
+  __shared__ double red[kBlock / 64];
+  double rr = 0.0, bb = 0.0, zr = 0.0;
+  DG_VEC_LOOP(i, k, n) {
+    const double bi = b[i];
+    const double ri = bi - q[i];
+    const float r32i = (float)ri;
+    r32[i] = r32i;
+    const double z = dinv ? (double)dinv[i] * (double)r32i : (double)r32i;
+    rr += ri * ri;
+    bb += bi * bi;
+    zr += z * (double)r32i;
+  }
+  const double mine[3] = {block_sum<kBlock>(rr, red), block_sum<kBlock>(bb, red), block_sum<kBlock>(zr, red)};
+  store_partials<3>(mine, partials, blockIdx.x);
 }
 
 // partials {<b - q, b - q>, <b, b>} (true residual check)
@@ -166,17 +201,24 @@ enum FinishMode {
   FIN_INIT_INNER = 2,// 2 values: rho[0], rr (= rr0 = bb); tol2 = rtol^2 rr
   FIN_UPDATE = 3,    // 2 values: rho[par^1], rr; iters++; done when rr <= tol2
   FIN_DC = 4,        // 2 values: rr, bb
-  FIN_TRUE = 5       // 2 values: true_rr, true_bb
+  FIN_TRUE = 5,      // 2 values: true_rr, true_bb
+  FIN_REPLACE = 6    // 3 values: true_rr (= rr), true_bb, rho[par^1]; restarts the inner stop test
 };
 
+constexpr int kFinishBlock = 1024;
+
 template <int NV, int MODE>
-__global__ __launch_bounds__(kBlock) void k_finish(const double* partials, int64_t nblocks, CgState* st,
-                                                   int par, double rtol) {
+__global__ __launch_bounds__(kFinishBlock) void k_finish(const double* partials, int64_t nblocks, CgState* st,
+                                                         int par, double rtol, double aux) {
+  if (MODE == FIN_DOT) {
+    // a new iteration starts: the deferred x update of the last one has been applied
+    if (threadIdx.x == 0) st->xpend = 0;
+  }
   if (MODE == FIN_DOT || MODE == FIN_UPDATE) {
     if (st->done) return;
   }
   double t[NV];
-  sum_partials<NV, kBlock>(partials, nblocks, t);
+  sum_partials<NV, kFinishBlock>(partials, nblocks, t);
   if (threadIdx.x != 0) return;
   if (MODE == FIN_DOT) {
     st->pq = t[0];
@@ -193,6 +235,7 @@ __global__ __launch_bounds__(kBlock) void k_finish(const double* partials, int64
     st->tol2 = rtol * rtol * st->bb;
     st->iters = 0;
     st->breakdown = 0;
+    st->xpend = 0;
     st->done = (t[1] <= st->tol2) ? 1 : 0;
     if (!finite_d(t[0]) || !finite_d(t[1])) {
       st->breakdown = 1;
@@ -202,6 +245,7 @@ __global__ __launch_bounds__(kBlock) void k_finish(const double* partials, int64
     st->rho[par ^ 1] = t[0];
     st->rr = t[1];
     st->iters += 1;
+    st->xpend = 1;
     if (t[1] <= st->tol2) st->done = 1;
     if (!finite_d(t[0]) || !finite_d(t[1])) {
       st->breakdown = 1;
@@ -210,15 +254,34 @@ __global__ __launch_bounds__(kBlock) void k_finish(const double* partials, int64
   } else if (MODE == FIN_DC) {
     st->rr = t[0];
     st->bb = t[1];
-  } else {
+  } else if (MODE == FIN_TRUE) {
     st->true_rr = t[0];
     st->true_bb = t[1];
+  } else {
+    // rtol: outer tolerance; aux: reduction asked of the next inner segment.
+    // The segment stops at aux * ||r|| or at half the outer target, whichever is larger.
+    st->true_rr = t[0];
+    st->true_bb = t[1];
+    st->rr = t[0];
+    st->rr0 = t[0];
+    st->rho[par ^ 1] = t[2];
+    const double a = aux * aux * t[0], o = 0.25 * rtol * rtol * t[1];
+    st->tol2 = a > o ? a : o;
+    st->iters = 0;
+    st->xpend = 0;
+    st->breakdown = 0;
+    st->done = 0;
+    if (!finite_d(t[0]) || !finite_d(t[2]) || !(t[2] > 0.0)) {
+      st->breakdown = 1;
+      st->done = 1;
+    }
   }
 }
 
 template <int NV, int MODE>
-static hipError_t finish(const double* partials, int64_t nb, CgState* st, int par, double rtol, hipStream_t s) {
-  hipLaunchKernelGGL((k_finish<NV, MODE>), dim3(1), dim3(kBlock), 0, s, partials, nb, st, par, rtol);
+static hipError_t finish(const double* partials, int64_t nb, CgState* st, int par, double rtol, hipStream_t s,
+                         double aux = 0.0) {
+  hipLaunchKernelGGL((k_finish<NV, MODE>), dim3(1), dim3(kFinishBlock), 0, s, partials, nb, st, par, rtol, aux);
   return hipGetLastError();
 }
 
@@ -251,20 +314,20 @@ hipError_t launch_cg_init_inner(int64_t n, const TV* r, TV* d, TP* p, const TD* 
   DG_TRY(hipGetLastError());
   return finish<2, FIN_INIT_INNER>(partials, nb, st, 0, rtol, s);
 }
-template <typename TX, typename TV, typename TP, typename TD>
-hipError_t launch_cg_update(int64_t n, TX* x, TV* r, const TP* p, const TV* q, const TD* dinv, int par,
-                            CgState* st, double* partials, hipStream_t s) {
+template <typename TV, typename TD>
+hipError_t launch_cg_update(int64_t n, TV* r, const TV* q, const TD* dinv, int par, CgState* st,
+                            double* partials, hipStream_t s) {
   const int64_t nb = vec_blocks(n);
-  hipLaunchKernelGGL((k_cg_update<TX, TV, TP, TD>), dim3((unsigned)nb), dim3(kBlock), 0, s, n, x, r, p, q, dinv,
-                     par, st, partials);
+  hipLaunchKernelGGL((k_cg_update<TV, TD>), dim3((unsigned)nb), dim3(kBlock), 0, s, n, r, q, dinv, par, st,
+                     partials);
   DG_TRY(hipGetLastError());
   return finish<2, FIN_UPDATE>(partials, nb, st, par, 0.0, s);
 }
-template <typename TV, typename TP, typename TD>
-hipError_t launch_cg_pupdate(int64_t n, const TV* r, TP* p, const TD* dinv, int par, const CgState* st,
-                             hipStream_t s) {
-  hipLaunchKernelGGL((k_cg_pupdate<TV, TP, TD>), dim3((unsigned)vec_blocks(n)), dim3(kBlock), 0, s, n, r, p,
-                     dinv, par, st);
+template <typename TX, typename TV, typename TP, typename TD>
+hipError_t launch_cg_pupdate(int64_t n, TX* x, const TV* r, TP* p, const TD* dinv, int par, const CgState* st,
+                             int force_p, hipStream_t s) {
+  hipLaunchKernelGGL((k_cg_pupdate<TX, TV, TP, TD>), dim3((unsigned)vec_blocks(n)), dim3(kBlock), 0, s, n, x, r,
+                     p, dinv, par, st, force_p);
   return hipGetLastError();
 }
 
@@ -272,31 +335,25 @@ hipError_t launch_cg_pupdate(int64_t n, const TV* r, TP* p, const TD* dinv, int 
 template hipError_t launch_cg_init<double, double, double, double>(int64_t, const double*, const double*,
                                                                    double*, double*, const double*, double,
                                                                    CgState*, double*, hipStream_t);
-template hipError_t launch_cg_update<double, double, double, double>(int64_t, double*, double*,
-                                                                     const double*, const double*,
-                                                                     const double*, int, CgState*, double*,
-                                                                     hipStream_t);
-template hipError_t launch_cg_pupdate<double, double, double>(int64_t, const double*, double*,
-                                                              const double*, int, const CgState*,
-                                                              hipStream_t);
+template hipError_t launch_cg_update<double, double>(int64_t, double*, const double*, const double*, int,
+                                                     CgState*, double*, hipStream_t);
+template hipError_t launch_cg_pupdate<double, double, double, double>(int64_t, double*, const double*, double*,
+                                                                      const double*, int, const CgState*, int,
+                                                                      hipStream_t);
 template hipError_t launch_cg_init_inner<float, float, float>(int64_t, const float*, float*, float*,
                                                               const float*, double, CgState*, double*,
                                                               hipStream_t);
 template hipError_t launch_cg_init_inner<float, uint16_t, float>(int64_t, const float*, float*, uint16_t*,
                                                                  const float*, double, CgState*, double*,
                                                                  hipStream_t);
-template hipError_t launch_cg_update<float, float, float, float>(int64_t, float*, float*, const float*,
-                                                                 const float*, const float*, int, CgState*,
-                                                                 double*, hipStream_t);
-template hipError_t launch_cg_update<float, float, uint16_t, float>(int64_t, float*, float*,
-                                                                    const uint16_t*, const float*,
-                                                                    const float*, int, CgState*, double*,
-                                                                    hipStream_t);
-template hipError_t launch_cg_pupdate<float, float, float>(int64_t, const float*, float*, const float*, int,
-                                                           const CgState*, hipStream_t);
-template hipError_t launch_cg_pupdate<float, uint16_t, float>(int64_t, const float*, uint16_t*,
-                                                              const float*, int, const CgState*,
-                                                              hipStream_t);
+template hipError_t launch_cg_update<float, float>(int64_t, float*, const float*, const float*, int, CgState*,
+                                                   double*, hipStream_t);
+template hipError_t launch_cg_pupdate<float, float, float, float>(int64_t, float*, const float*, float*,
+                                                                  const float*, int, const CgState*, int,
+                                                                  hipStream_t);
+template hipError_t launch_cg_pupdate<float, float, uint16_t, float>(int64_t, float*, const float*, uint16_t*,
+                                                                     const float*, int, const CgState*, int,
+                                                                     hipStream_t);
 
 hipError_t launch_dc_residual(int64_t n, const double* b, const double* q, float* r32, CgState* st,
                               double* partials, hipStream_t s) {
@@ -305,9 +362,17 @@ hipError_t launch_dc_residual(int64_t n, const double* b, const double* q, float
   DG_TRY(hipGetLastError());
   return finish<2, FIN_DC>(partials, nb, st, 0, 0.0, s);
 }
-hipError_t launch_dc_update(int64_t n, double* x, const float* d, hipStream_t s) {
+hipError_t launch_dc_update(int64_t n, double* x, float* d, hipStream_t s) {
   hipLaunchKernelGGL(k_dc_update, dim3((unsigned)vec_blocks(n)), dim3(kBlock), 0, s, n, x, d);
   return hipGetLastError();
+}
+hipError_t launch_dc_replace(int64_t n, const double* b, const double* q, const float* dinv, float* r32,
+                             CgState* st, int par, double rtol, double reduction, double* partials,
+                             hipStream_t s) {
+  const int64_t nb = vec_blocks(n);
+  hipLaunchKernelGGL(k_dc_replace, dim3((unsigned)nb), dim3(kBlock), 0, s, n, b, q, dinv, r32, partials);
+  DG_TRY(hipGetLastError());
+  return finish<3, FIN_REPLACE>(partials, nb, st, par, rtol, s, reduction);
 }
 hipError_t launch_resid_norm(int64_t n, const double* b, const double* q, CgState* st, double* partials,
                              hipStream_t s) {

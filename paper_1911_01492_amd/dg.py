@@ -49,10 +49,13 @@ class MeshDesc(ctypes.Structure):
                 ("workspace_bytes", ctypes.c_size_t)]
 
 
+DC_MODE = {"restart": 0, "keep": 1}
+
+
 class CgOpts(ctypes.Structure):
     _fields_ = [("prec_inner", ctypes.c_int), ("precond", ctypes.c_int), ("transpose", ctypes.c_int),
                 ("rtol", ctypes.c_double), ("inner_rtol", ctypes.c_double), ("maxit", ctypes.c_int),
-                ("max_outer", ctypes.c_int), ("check_every", ctypes.c_int), ("reserved", ctypes.c_int)]
+                ("max_outer", ctypes.c_int), ("check_every", ctypes.c_int), ("dc_mode", ctypes.c_int)]
 
 
 class CgInfo(ctypes.Structure):
@@ -211,13 +214,18 @@ class DGOperator:
 
     def cg_solve(self, b: torch.Tensor, x: Optional[torch.Tensor] = None, prec_inner: str = "f64",
                  precond: str = "jacobi", rtol: float = 1e-10, maxit: int = 100000,
-                 inner_rtol: float = 0.0, max_outer: int = 30, transpose: bool = False,
-                 check_every: int = 8, stream=None):
-        """Solve A x = b (A^T x = b).  Returns (x, info dict)."""
+                 inner_rtol: float = 0.0, max_outer: int = 0, transpose: bool = False,
+                 check_every: int = 8, dc_mode: str = "restart", stream=None):
+        """Solve A x = b (A^T x = b).  Returns (x, info dict).
+
+        prec_inner "f32" / "bf16" selects the FP64 defect correction; dc_mode
+        "restart" starts every inner solve afresh, "keep" replaces the inner
+        residual by the FP64 one and keeps the search direction.  inner_rtol
+        and max_outer <= 0 take the library defaults."""
         self._vec(b, torch.float64)
         x = torch.zeros_like(b) if x is None else self._vec(x, torch.float64)
         o = CgOpts(PREC[prec_inner], PRECOND[precond], 1 if transpose else 0, rtol, inner_rtol, maxit,
-                   max_outer, check_every, 0)
+                   max_outer, check_every, DC_MODE[dc_mode])
         info = CgInfo()
         rc = lib().dg_cg_solve(self._h, ctypes.byref(o), _ptr(b), _ptr(x), ctypes.byref(info),
                                _stream(stream))
