@@ -243,9 +243,53 @@ struct AxisNeighbours {
   }
 };
 
+// One face-aware direction of the affine apply: b = L_D u on this thread's
+// line along axis D (own line from HBM, neighbour face scalars from the
+// brick's exchange area F or from HBM).  Contains one barrier; every thread
+// of the block calls it.
+template <int N, int D, int BX, int BY, int BZ, typename TC, typename TIN, bool TRANS>
+__device__ __forceinline__ void face_phase(const MeshArgs<TC>& m, const Tables<TC>& T, const TIN* __restrict__ x,
+                                           bool act, int64_t e, const int (&c)[3], const int (&o)[3],
+                                           const int (&Nd)[3], int t, int t1, int t2, TC* F, TC* Fe, TC K, TC GL,
+                                           TC GH, TC (&b)[N]) {
+  constexpr int NN = N * N;
+  AxisNeighbours<N, D, BX, BY, BZ, TC, TIN> nb;
+  TC u[N], g0 = TC(0), g1 = TC(0);
+  if (act) {
+    nb.locate(m.nx, m.ny, c, o, Nd, m.periodic);
+    nb.fetch(x, t1, t2);
+    glb_get<N, D, TC, TIN>(x, e, t1, t2, u);
+    nb.reduce(T);
+    g0 = dot_end<N, TC, 0>(T, u);
+    g1 = dot_end<N, TC, 1>(T, u);
+    Fe[0 * NN + t] = u[0];
+    Fe[1 * NN + t] = g0;
+    Fe[2 * NN + t] = u[N - 1];
+    Fe[3 * NN + t] = g1;
+  }
+  __syncthreads();
+  if (act) {
+    TC UL, GLr, UH, GHr;
+    nb.scalars(F, t, UL, GLr, UH, GHr);
+    line_op_s<N, TC, TRANS>(T, u, g0, g1, UL, GLr, UH, GHr, nb.hasL, nb.hasH, GL, GH, K * m.vs[D], m.ih[D],
+                            m.sg[D], m.At[D], b);
+  }
+}
+
 // y = A x (TRANS: A^T x) on affine meshes.  DOT: also the block partials of
 // <x, y> (y as stored) for the CG scalar <p, A p>.  skip != nullptr &&
 // *skip: do nothing (the solver has converged).
+//
+// With b_d = L_d u (the 1D DG operator along d, face terms included) the
+// element result is y = M_z (M_y b_x + M_x b_y) + M_y M_x b_z.  The phases
+// keep two element tiles in LDS (S1, S2; the face-scalar exchange area
+// aliases S2), so that a block of the Q3 brick needs under 20 KB:
+//   X : b_x                      -> S1
+//   Y : b_y -> S2, M_y b_x       -> S1
+//   X2: M_y b_x + M_x b_y        -> S1
+//   Z : b_z -> S2, r = M_z S1       (registers)
+//   X3, Y3: S2 <- M_y M_x S2
+//   Z2: y = r + S2
 template <int N, typename TIN, typename TOUT, typename TC, bool TRANS, bool DOT>
 __global__ __launch_bounds__(apply_block(N)) void k_apply_affine(MeshArgs<TC> m, const TIN* __restrict__ x,
                                                          TOUT* __restrict__ y, double* partials,
@@ -253,14 +297,14 @@ __global__ __launch_bounds__(apply_block(N)) void k_apply_affine(MeshArgs<TC> m,
   constexpr int NN = N * N, N3 = NN * N;
   constexpr int BX = tile_x(N), BY = tile_y(N), BZ = tile_z(N), TE = BX * BY * BZ;
   constexpr int PE = Lay<N, TC>::PE;
-  constexpr bool F_IN_U = 4 * NN <= PE;  // face-scalar exchange area aliases the U tiles
+  constexpr bool F_IN_S2 = 4 * NN <= PE;
   constexpr int BLOCK = apply_block(N);
   static_assert(TE * NN <= BLOCK && BLOCK <= kBlock, "brick too large");
-  __shared__ TC sU[TE * PE], sA[TE * PE], sB[TE * PE];
-  __shared__ TC sFx[F_IN_U ? 1 : TE * 4 * NN];
+  __shared__ TC sS1[TE * PE], sS2[TE * PE];
+  __shared__ TC sFx[F_IN_S2 ? 1 : TE * 4 * NN];
   __shared__ double red[BLOCK / 64];
   if (skip != nullptr && *skip) return;
-  TC* F = F_IN_U ? sU : sFx;
+  TC* F = F_IN_S2 ? sS2 : sFx;
   const Tables<TC>& T = *m.tab;
   // brick coordinates: uniform per workgroup (scalar arithmetic)
   const int ntx = (m.nx + BX - 1) / BX, nty = (m.ny + BY - 1) / BY;
@@ -272,120 +316,77 @@ __global__ __launch_bounds__(apply_block(N)) void k_apply_affine(MeshArgs<TC> m,
   const int c[3] = {o[0] + lx, o[1] + ly, o[2] + lz};
   const bool act = el < TE && c[0] < m.nx && c[1] < m.ny && c[2] < m.nz;
   const int le = act ? el : 0;
-  TC* U = sU + le * PE;
-  TC* A = sA + le * PE;
-  TC* B = sB + le * PE;
+  TC* S1 = sS1 + le * PE;
+  TC* S2 = sS2 + le * PE;
   TC* Fe = F + le * 4 * NN;
   const int64_t e = c[0] + (int64_t)m.nx * (c[1] + (int64_t)m.ny * c[2]);
-  TC uz[N], u[N], K = TC(1), G[6];
-  AxisNeighbours<N, 2, BX, BY, BZ, TC, TIN> nz;
-  AxisNeighbours<N, 1, BX, BY, BZ, TC, TIN> ny;
-  AxisNeighbours<N, 0, BX, BY, BZ, TC, TIN> nxn;
+  TC K = TC(1), G[6];
   if (act) {
-    nz.locate(m.nx, m.ny, c, o, Nd, m.periodic);
-    nz.fetch(x, t1, t2);
-    glb_get<N, 2, TC, TIN>(x, e, t1, t2, uz);
     K = m.K[e];
 #pragma unroll
     for (int f = 0; f < 6; ++f) G[f] = m.G[6 * e + f];
-    nz.reduce(T);
   }
-  // ---------------- phase Z
-  TC g0 = TC(0), g1 = TC(0);
+  TC b[N], v[N], w[N];
+  // ---------------- X: b_x -> S1
+  face_phase<N, 0, BX, BY, BZ, TC, TIN, TRANS>(m, T, x, act, e, c, o, Nd, t, t1, t2, F, Fe, K, G[0], G[1], b);
+  if (act) lds_put<N, 0>(S1, t1, t2, b);
+  __syncthreads();  // F is rewritten by the next phase
+  // ---------------- Y: b_y -> S2, M_y b_x -> S1
+  face_phase<N, 1, BX, BY, BZ, TC, TIN, TRANS>(m, T, x, act, e, c, o, Nd, t, t1, t2, F, Fe, K, G[2], G[3], b);
   if (act) {
-    g0 = dot_end<N, TC, 0>(T, uz);
-    g1 = dot_end<N, TC, 1>(T, uz);
-    Fe[0 * NN + t] = uz[0];
-    Fe[1 * NN + t] = g0;
-    Fe[2 * NN + t] = uz[N - 1];
-    Fe[3 * NN + t] = g1;
+    lds_get<N, 1>(S1, t1, t2, v);
+    mass_line<N, TC, TRANS>(T, v, w);
+  }
+  if (F_IN_S2) __syncthreads();  // the face scalars in S2 have been read
+  if (act) {
+    lds_put<N, 1>(S2, t1, t2, b);
+    lds_put<N, 1>(S1, t1, t2, w);
   }
   __syncthreads();
+  // ---------------- X2: M_y b_x + M_x b_y -> S1
   if (act) {
-    TC UL, GLr, UH, GHr, b[N];
-    nz.scalars(F, t, UL, GLr, UH, GHr);
-    line_op_s<N, TC, TRANS>(T, uz, g0, g1, UL, GLr, UH, GHr, nz.hasL, nz.hasH, G[4], G[5], K * m.vs[2], m.ih[2],
-                            m.sg[2], m.At[2], b);
-    lds_put<N, 2>(B, t1, t2, b);
-  }
-  __syncthreads();
-  // ---------------- phase Y
-  if (act) {
-    ny.locate(m.nx, m.ny, c, o, Nd, m.periodic);
-    ny.fetch(x, t1, t2);
-    glb_get<N, 1, TC, TIN>(x, e, t1, t2, u);
-    ny.reduce(T);
-    g0 = dot_end<N, TC, 0>(T, u);
-    g1 = dot_end<N, TC, 1>(T, u);
-    Fe[0 * NN + t] = u[0];
-    Fe[1 * NN + t] = g0;
-    Fe[2 * NN + t] = u[N - 1];
-    Fe[3 * NN + t] = g1;
-  }
-  __syncthreads();
-  if (act) {
-    TC UL, GLr, UH, GHr, b[N];
-    ny.scalars(F, t, UL, GLr, UH, GHr);
-    line_op_s<N, TC, TRANS>(T, u, g0, g1, UL, GLr, UH, GHr, ny.hasL, ny.hasH, G[2], G[3], K * m.vs[1], m.ih[1],
-                            m.sg[1], m.At[1], b);
-    lds_put<N, 1>(A, t1, t2, b);
-  }
-  __syncthreads();
-  // ---------------- phase X
-  if (act) {
-    nxn.locate(m.nx, m.ny, c, o, Nd, m.periodic);
-    nxn.fetch(x, t1, t2);
-    glb_get<N, 0, TC, TIN>(x, e, t1, t2, u);
-    nxn.reduce(T);
-    g0 = dot_end<N, TC, 0>(T, u);
-    g1 = dot_end<N, TC, 1>(T, u);
-    Fe[0 * NN + t] = u[0];
-    Fe[1 * NN + t] = g0;
-    Fe[2 * NN + t] = u[N - 1];
-    Fe[3 * NN + t] = g1;
-  }
-  __syncthreads();
-  TC bx[N];
-  if (act) {
-    TC UL, GLr, UH, GHr, by[N], bz[N], cc[N], ee[N];
-    nxn.scalars(F, t, UL, GLr, UH, GHr);
-    line_op_s<N, TC, TRANS>(T, u, g0, g1, UL, GLr, UH, GHr, nxn.hasL, nxn.hasH, G[0], G[1], K * m.vs[0],
-                            m.ih[0], m.sg[0], m.At[0], bx);
-    lds_get<N, 0>(A, t1, t2, by);
-    lds_get<N, 0>(B, t1, t2, bz);
-    mass_line<N, TC, TRANS>(T, by, cc);
-    mass_line<N, TC, TRANS>(T, bz, ee);
-    lds_put<N, 0>(A, t1, t2, cc);
-    lds_put<N, 0>(B, t1, t2, ee);
-  }
-  if (F_IN_U) __syncthreads();  // the face scalars in U have been read
-  if (act) lds_put<N, 0>(U, t1, t2, bx);
-  __syncthreads();
-  if (act) {  // phase Y2
-    TC f[N], cc[N], ee[N], g[N];
-    lds_get<N, 1>(U, t1, t2, bx);
-    lds_get<N, 1>(A, t1, t2, cc);
-    lds_get<N, 1>(B, t1, t2, ee);
-    mass_line<N, TC, TRANS>(T, bx, f);
-    mass_line<N, TC, TRANS>(T, ee, g);
+    lds_get<N, 0>(S2, t1, t2, v);
+    lds_get<N, 0>(S1, t1, t2, w);
+    mass_line<N, TC, TRANS>(T, v, b);
 #pragma unroll
-    for (int i = 0; i < N; ++i) f[i] += cc[i];
-    lds_put<N, 1>(U, t1, t2, f);
-    lds_put<N, 1>(A, t1, t2, g);
+    for (int i = 0; i < N; ++i) w[i] += b[i];
+    lds_put<N, 0>(S1, t1, t2, w);
   }
   __syncthreads();
+  // ---------------- Z: b_z -> S2, r = M_z S1
+  TC r[N];
+  face_phase<N, 2, BX, BY, BZ, TC, TIN, TRANS>(m, T, x, act, e, c, o, Nd, t, t1, t2, F, Fe, K, G[4], G[5], b);
+  if (act) {
+    lds_get<N, 2>(S1, t1, t2, v);
+    mass_line<N, TC, TRANS>(T, v, r);
+  }
+  if (F_IN_S2) __syncthreads();
+  if (act) lds_put<N, 2>(S2, t1, t2, b);
+  __syncthreads();
+  // ---------------- X3, Y3: S2 <- M_y M_x S2
+  if (act) {
+    lds_get<N, 0>(S2, t1, t2, v);
+    mass_line<N, TC, TRANS>(T, v, w);
+    lds_put<N, 0>(S2, t1, t2, w);
+  }
+  __syncthreads();
+  if (act) {
+    lds_get<N, 1>(S2, t1, t2, v);
+    mass_line<N, TC, TRANS>(T, v, w);
+    lds_put<N, 1>(S2, t1, t2, w);
+  }
+  __syncthreads();
+  // ---------------- Z2: y = r + S2
   double part = 0.0;
-  if (act) {  // phase Z2
-    TC f[N], g[N], r[N];
-    lds_get<N, 2>(U, t1, t2, f);
-    lds_get<N, 2>(A, t1, t2, g);
-    mass_line<N, TC, TRANS>(T, f, r);
+  if (act) {
+    lds_get<N, 2>(S2, t1, t2, v);
     TOUT* py = y + e * N3;
+    if (DOT) glb_get<N, 2, TC, TIN>(x, e, t1, t2, w);
 #pragma unroll
     for (int i = 0; i < N; ++i) {
-      const TOUT v = (TOUT)(r[i] + g[i]);
-      py[lidx<N, 2>(t1, t2, i)] = v;
-      if (DOT) part += (double)uz[i] * (double)v;
+      const TOUT yv = (TOUT)(r[i] + v[i]);
+      py[lidx<N, 2>(t1, t2, i)] = yv;
+      if (DOT) part += (double)w[i] * (double)yv;
     }
   }
   if (DOT) {
