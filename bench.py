@@ -49,6 +49,44 @@ def alg_bytes_per_dof(n: int, in_b: int, out_b: int, k_b: int) -> float:
     return in_b + out_b + k_b / n ** 3
 
 
+def flops_per_dof(n: int, trilinear: bool = False) -> float:
+    """Algorithmic flops per DOF of one sum-factorised apply (not the 2 * 7 n^3
+    of the dense product it avoids): affine, collapsed Kronecker sum with the
+    face terms counted once per element side, 14 n + 48; trilinear quadrature
+    form, 24 n (volume contractions) + 120 (J, det J, J^-1 and G per point)
+    + 168 (face contractions) + 810 / n (face geometry)."""
+    if trilinear:
+        return 24 * n + 120 + 168 + 810 / n
+    return 14 * n + 48
+
+
+def launch_stats(op, x, prec, reps, torch):
+    """Median and minimum of single-launch times (HIP events on the launch stream)."""
+    y = op.apply(x, prec=prec)
+    s = torch.cuda.current_stream()
+    ts = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        op.apply(x, prec=prec, out=y)
+        e1.record(s)
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1) / 1e3)
+    return float(np.median(ts)), float(np.min(ts))
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def time_apply(op, x, prec, steps, warmup, torch):
     y = op.apply(x, prec=prec)
     for _ in range(warmup):
@@ -131,7 +169,7 @@ def cpu_baseline(seconds: float = 12.0):
             "sample": f"CSR SpMV of the Q3 lognormal-K Dirichlet operator on 16^3 elements "
                       f"({m.ndof} DOF, {A.nnz} stored entries), {reps} products in {t:.1f} s; "
                       f"CSR assembly took {t_asm:.1f} s",
-            "assembly_s": t_asm}
+            "assembly_s": t_asm, "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
 
 
 def main():
@@ -183,6 +221,8 @@ def main():
     bpd = alg_bytes_per_dof(n, 8, 8, 8)
     achieved = bpd * op.ndof / per / 1e9
     t_cold = cold_apply(op, x, "f64", 10, torch)
+    t_med, t_min = launch_stats(op, x, "f64", 50, torch)
+    fpd = flops_per_dof(n)
     result = {
         "metric": "GDOF/s of SIPG apply (fp64 vs fp32/bf16) + CG time-to-1e-10 residual",
         "value": round(gdofs, 3),
@@ -203,6 +243,10 @@ def main():
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
                      "kernel": "k_apply_affine<4,double,double,double,false,false>",
                      "alg_bytes_per_dof": round(bpd, 4), "avg_launch_us": round(per * 1e6, 3),
+                     "median_launch_us": round(t_med * 1e6, 3), "min_launch_us": round(t_min * 1e6, 3),
+                     "alg_flops_per_dof": fpd,
+                     "fp64_tflops": round(fpd * op.ndof / per / 1e12, 3),
+                     "fp64_frac": round(fpd * op.ndof / per / 1e12 / FP64_PEAK_TFS, 4),
                      "cold_launch_us": round(t_cold * 1e6, 3),
                      "cold_achieved": round(bpd * op.ndof / t_cold / 1e9, 1)},
         "paper_context": {"note": "Table 'Full operator application' (Sec. 3.3), matrix-free problem A, "
@@ -250,9 +294,13 @@ def main():
             per3 = tt / 20
             kb = 8 if prec == "f64" else 4
             bpd3 = alg_bytes_per_dof(n3, ib, ob, kb)
+            fp3 = flops_per_dof(n3)
+            peak3 = FP64_PEAK_TFS if prec == "f64" else FP32_PEAK_TFS
             ent = {"gdofs": round(op3.ndof / per3 / 1e9, 3), "ms": round(per3 * 1e3, 4),
                    "achieved_GBs": round(bpd3 * op3.ndof / per3 / 1e9, 1),
-                   "frac_hbm": round(bpd3 * op3.ndof / per3 / 1e9 / HBM_PEAK_GBS, 4)}
+                   "frac_hbm": round(bpd3 * op3.ndof / per3 / 1e9 / HBM_PEAK_GBS, 4),
+                   "tflops": round(fp3 * op3.ndof / per3 / 1e12, 3),
+                   "frac_alu": round(fp3 * op3.ndof / per3 / 1e12 / peak3, 4)}
             if prec == "f64":
                 ref = yy.clone()
             else:
@@ -320,8 +368,12 @@ def main():
             x5 = I.uniform_vector(op5.ndof)
             for prec, X5 in (("f64", dev(x5)), ("f32", dev(I.to_f32(x5), torch.float32))):
                 tt, yy = time_apply(op5, X5, prec, 10, 3, torch)
-                extras[f"apply_{prec}_trilinear_q7_48"] = {"gdofs": round(op5.ndof * 10 / tt / 1e9, 3),
-                                                           "ms": round(tt / 10 * 1e3, 4)}
+                fp5 = flops_per_dof(k5 + 1, trilinear=True)
+                peak5 = FP64_PEAK_TFS if prec == "f64" else FP32_PEAK_TFS
+                extras[f"apply_{prec}_trilinear_q7_48"] = {
+                    "gdofs": round(op5.ndof * 10 / tt / 1e9, 3), "ms": round(tt / 10 * 1e3, 4),
+                    "tflops": round(fp5 * op5.ndof * 10 / tt / 1e12, 3),
+                    "frac_alu": round(fp5 * op5.ndof * 10 / tt / 1e12 / peak5, 4)}
                 log(f"trilinear {prec}: {extras[f'apply_{prec}_trilinear_q7_48']}")
                 del yy
             del op5
