@@ -50,7 +50,7 @@ __device__ __forceinline__ void corner_of(const MeshArgs<TC>& m, int64_t e, int 
 // block call this (it synchronises); act marks threads owning an element.
 template <int N, int D, typename TC, typename TIN>
 __device__ void face_term(const MeshArgs<TC>& m, const Tables<TC>& T, const TIN* __restrict__ x, int64_t e,
-                          int ex, int ey, int ez, const TC (&X)[8][3], TC K, int t1, int t2, const TC* U,
+                          int ex, int ey, int ez, const TC (&X)[8][3], TC (&Xn)[8][3], TC K, int t1, int t2,
                           TC* Y, TC (*F)[N * N], bool act, int s) {
   constexpr int NN = N * N;
   const int t = t1 + N * t2;
@@ -62,8 +62,11 @@ __device__ void face_term(const MeshArgs<TC>& m, const Tables<TC>& T, const TIN*
   TC Uo = TC(0), Go = TC(0), Un = TC(0), Gn = TC(0);
   if (act) {
     nb = neighbour<D>(m, ex, ey, ez, s);
+    // the neighbour's corners, staged once per element (read after the barriers below)
+    if (nb >= 0)
+      for (int q = t; q < 24; q += NN) corner_of(m, nb, q / 3, q % 3, Xn[q / 3][q % 3]);
     TC own[N];
-    lds_get<N, D>(U, t1, t2, own);
+    glb_get<N, D, TC, TIN>(x, e, t1, t2, own);
     Uo = own[s ? N - 1 : 0];
 #pragma unroll
     for (int i = 0; i < N; ++i) Go += dS[i] * own[i];
@@ -139,11 +142,6 @@ __device__ void face_term(const MeshArgs<TC>& m, const Tables<TC>& T, const TIN*
     TC Nv[3];
     const int c1 = (D + 1) % 3, c2 = (D + 2) % 3;
     if (nb >= 0) {
-      TC Xn[8][3];
-#pragma unroll
-      for (int c = 0; c < 8; ++c)
-#pragma unroll
-        for (int a = 0; a < 3; ++a) corner_of(m, nb, c, a, Xn[c][a]);
       TC xin[3];
       xin[D] = TC(1 - s);
       xin[ax] = xi[ax];
@@ -229,7 +227,6 @@ __device__ void face_term(const MeshArgs<TC>& m, const Tables<TC>& T, const TIN*
     yl[s ? N - 1 : 0] += out;
     lds_put<N, D>(Y, t1, t2, yl);
   }
-  (void)NN;
 }
 
 template <int N, typename TIN, typename TOUT, typename TC, bool DOT>
@@ -237,8 +234,8 @@ __global__ __launch_bounds__(kBlock) void k_apply_trilinear(MeshArgs<TC> m, cons
                                                             TOUT* __restrict__ y, double* partials,
                                                             const int* skip) {
   constexpr int NN = N * N, N3 = NN * N, EPB = elems_per_block(N), PE = Lay<N, TC>::PE;
-  __shared__ TC sU[EPB * PE], sA[EPB * PE], sB[EPB * PE], sC[EPB * PE];
-  __shared__ TC sX[EPB][8][3];
+  __shared__ TC sA[EPB * PE], sB[EPB * PE], sC[EPB * PE];
+  __shared__ TC sX[EPB][8][3], sXn[EPB][8][3];
   __shared__ TC sF[EPB][10][NN];
   __shared__ double red[kBlock / 64];
   if (skip != nullptr && *skip) return;
@@ -248,31 +245,25 @@ __global__ __launch_bounds__(kBlock) void k_apply_trilinear(MeshArgs<TC> m, cons
   const int64_t e = blk * EPB + el;
   const bool act = (el < EPB) && (e < m.E);
   const int le = act ? el : 0;
-  TC* U = sU + le * PE;
   TC* A = sA + le * PE;
   TC* B = sB + le * PE;
   TC* C = sC + le * PE;
   int ex = 0, ey = 0, ez = 0;
   TC K = TC(1);
-  TC uz[N];
   if (act) {
+    TC uz[N];
     ex = (int)(e % m.nx);
     ey = (int)((e / m.nx) % m.ny);
     ez = (int)(e / ((int64_t)m.nx * m.ny));
     K = m.K[e];
     for (int q = t; q < 24; q += NN) corner_of(m, e, q / 3, q % 3, sX[le][q / 3][q % 3]);
     glb_get<N, 2, TC, TIN>(x, e, t1, t2, uz);
-    lds_put<N, 2>(U, t1, t2, uz);
     TC a[N];
     contract<N, TC, false>(T.B, uz, a);  // phase Z: interpolate along z
     lds_put<N, 2>(A, t1, t2, a);
   }
   __syncthreads();
-  TC X[8][3];
-#pragma unroll
-  for (int c = 0; c < 8; ++c)
-#pragma unroll
-    for (int a = 0; a < 3; ++a) X[c][a] = sX[le][c][a];
+  const TC (&X)[8][3] = sX[le];
   if (act) {  // phase Y
     TC a[N], b[N];
     lds_get<N, 1>(A, t1, t2, a);
@@ -297,11 +288,14 @@ __global__ __launch_bounds__(kBlock) void k_apply_trilinear(MeshArgs<TC> m, cons
   }
   __syncthreads();
   if (act) {  // phase Z': d/dxi_2, geometry, g = G gr, Dg_z^T g_2
-    TC v[N], d1[N], d2[N], d3[N], g1[N], g2[N], g3[N], wz[N];
-    lds_get<N, 2>(A, t1, t2, v);
+    TC d1[N], d2[N], d3[N], wz[N];
+    {
+      TC v[N];
+      lds_get<N, 2>(A, t1, t2, v);
+      contract<N, TC, false>(T.Dg, v, d3);
+    }
     lds_get<N, 2>(C, t1, t2, d1);
     lds_get<N, 2>(B, t1, t2, d2);
-    contract<N, TC, false>(T.Dg, v, d3);
     const TC wq12 = T.gw[t1] * T.gw[t2] * K;
 #pragma unroll
     for (int q = 0; q < N; ++q) {
@@ -320,14 +314,15 @@ __global__ __launch_bounds__(kBlock) void k_apply_trilinear(MeshArgs<TC> m, cons
           Gm[r][cc] = c * sgm;
           Gm[cc][r] = c * sgm;
         }
-      g1[q] = Gm[0][0] * d1[q] + Gm[0][1] * d2[q] + Gm[0][2] * d3[q];
-      g2[q] = Gm[1][0] * d1[q] + Gm[1][1] * d2[q] + Gm[1][2] * d3[q];
-      g3[q] = Gm[2][0] * d1[q] + Gm[2][1] * d2[q] + Gm[2][2] * d3[q];
+      const TC a1 = d1[q], a2 = d2[q], a3 = d3[q];  // G gr in place of gr
+      d1[q] = Gm[0][0] * a1 + Gm[0][1] * a2 + Gm[0][2] * a3;
+      d2[q] = Gm[1][0] * a1 + Gm[1][1] * a2 + Gm[1][2] * a3;
+      d3[q] = Gm[2][0] * a1 + Gm[2][1] * a2 + Gm[2][2] * a3;
     }
-    contract<N, TC, true>(T.Dg, g3, wz);
+    contract<N, TC, true>(T.Dg, d3, wz);
     lds_put<N, 2>(A, t1, t2, wz);
-    lds_put<N, 2>(C, t1, t2, g1);
-    lds_put<N, 2>(B, t1, t2, g2);
+    lds_put<N, 2>(C, t1, t2, d1);
+    lds_put<N, 2>(B, t1, t2, d2);
   }
   __syncthreads();
   if (act) {  // phase Y'': += Dg_y^T g_1
@@ -365,20 +360,22 @@ __global__ __launch_bounds__(kBlock) void k_apply_trilinear(MeshArgs<TC> m, cons
     lds_put<N, 2>(C, t1, t2, o);
   }
   // faces (each call synchronises before touching shared buffers)
-  face_term<N, 0, TC, TIN>(m, T, x, e, ex, ey, ez, X, K, t1, t2, U, C, sF[le], act, 0);
-  face_term<N, 0, TC, TIN>(m, T, x, e, ex, ey, ez, X, K, t1, t2, U, C, sF[le], act, 1);
+  face_term<N, 0, TC, TIN>(m, T, x, e, ex, ey, ez, X, sXn[le], K, t1, t2, C, sF[le], act, 0);
+  face_term<N, 0, TC, TIN>(m, T, x, e, ex, ey, ez, X, sXn[le], K, t1, t2, C, sF[le], act, 1);
   __syncthreads();
-  face_term<N, 1, TC, TIN>(m, T, x, e, ex, ey, ez, X, K, t1, t2, U, C, sF[le], act, 0);
-  face_term<N, 1, TC, TIN>(m, T, x, e, ex, ey, ez, X, K, t1, t2, U, C, sF[le], act, 1);
+  face_term<N, 1, TC, TIN>(m, T, x, e, ex, ey, ez, X, sXn[le], K, t1, t2, C, sF[le], act, 0);
+  face_term<N, 1, TC, TIN>(m, T, x, e, ex, ey, ez, X, sXn[le], K, t1, t2, C, sF[le], act, 1);
   __syncthreads();
-  face_term<N, 2, TC, TIN>(m, T, x, e, ex, ey, ez, X, K, t1, t2, U, C, sF[le], act, 0);
-  face_term<N, 2, TC, TIN>(m, T, x, e, ex, ey, ez, X, K, t1, t2, U, C, sF[le], act, 1);
+  face_term<N, 2, TC, TIN>(m, T, x, e, ex, ey, ez, X, sXn[le], K, t1, t2, C, sF[le], act, 0);
+  face_term<N, 2, TC, TIN>(m, T, x, e, ex, ey, ez, X, sXn[le], K, t1, t2, C, sF[le], act, 1);
   __syncthreads();
   double part = 0.0;
   if (act) {
     TC o[N];
     lds_get<N, 2>(C, t1, t2, o);
     TOUT* py = y + e * N3;
+    TC uz[N];
+    if (DOT) glb_get<N, 2, TC, TIN>(x, e, t1, t2, uz);
 #pragma unroll
     for (int i = 0; i < N; ++i) {
       const TOUT v = (TOUT)o[i];
