@@ -15,8 +15,11 @@
  * A grad v . grad w plus the face coupling forms b_h^e) for -div(K grad u) = f,
  * on an nx*ny*nz hexahedral mesh of the unit cube with trilinear element maps,
  * a tensor-product Q_k Lagrange basis on Gauss-Lobatto nodes and a scalar
- * coefficient K_T = exp(theta_T) per element.  The operator application of
- * Sec. 3.3 computes exactly this matrix-vector product without the matrix.
+ * coefficient K_T = exp(theta_T) per element, optionally plus a reaction term
+ * int c_T u v with a coefficient c_T per element (the diffusion-reaction
+ * problems whose operator throughput Sec. 3.3 reports).  The operator
+ * application of Sec. 3.3 computes exactly this matrix-vector product without
+ * the matrix.
  *
  * Readings taken where the printed form is silent or garbled (each is listed
  * with its justification in the design notes of the repository):
@@ -55,6 +58,7 @@ typedef struct {
   double penalty_hat;      /* sigma * h_d; <= 0 selects 2 (k+1)^2                */
   const double* vertices;  /* (nx+1)(ny+1)(nz+1) x 3, x-index fastest; NULL: uniform */
   const double* theta;     /* nx*ny*nz, K = exp(theta); NULL: K = 1              */
+  const double* reaction;  /* nx*ny*nz reaction coefficients c_T; NULL: none     */
 } oracle_mesh;
 }
 
@@ -164,6 +168,7 @@ struct Mesh {
   double sig_hat;
   const double* vert;
   const double* theta;
+  const double* reaction;
   std::vector<double> gll, gx, gw;
   int64_t E;
 };
@@ -180,6 +185,7 @@ Mesh make_mesh(const oracle_mesh* m) {
   M.sig_hat = m->penalty_hat > 0 ? m->penalty_hat : 2.0 * (M.k + 1) * (M.k + 1);
   M.vert = m->vertices;
   M.theta = m->theta;
+  M.reaction = m->reaction;
   gll_nodes(M.n, M.gll);
   gauss_rule(M.nq, M.gx, M.gw);
   M.E = (int64_t)M.N[0] * M.N[1] * M.N[2];
@@ -338,6 +344,25 @@ void volume_matrix(const Mesh& M, const Geo& g, S K, std::vector<S>& A) {
       }
 }
 
+/* Reaction (diffusion-reaction problems of Sec. 3.3):
+ * A[i][j] = sum_q w_q |det J_q| c phi_i phi_j. */
+void mass_matrix(const Mesh& M, const Geo& g, double c, std::vector<double>& A) {
+  const int n3 = M.n3, q = M.nq;
+  A.assign((size_t)n3 * n3, 0.0);
+  std::vector<double> val(n3), grad(3 * n3);
+  for (int q3 = 0; q3 < q; ++q3)
+    for (int q2 = 0; q2 < q; ++q2)
+      for (int q1 = 0; q1 < q; ++q1) {
+        double xi[3] = {M.gx[q1], M.gx[q2], M.gx[q3]};
+        double J[3][3];
+        jacobian(g, xi, J);
+        double w = M.gw[q1] * M.gw[q2] * M.gw[q3] * std::fabs(det3(J));
+        basis_at(M, xi, J, val.data(), grad.data());
+        for (int i = 0; i < n3; ++i)
+          for (int j = 0; j < n3; ++j) A[(size_t)i * n3 + j] += c * (w * val[i] * val[j]);
+      }
+}
+
 /* Interior face normal to axis d between T^- (geometry gm, face xi_d = 1) and
  * T^+ (geometry gp, face xi_d = 0), on the combined index set
  * beta = side * n3 + local (side 0 = T^-, side 1 = T^+).  Only rows in
@@ -470,6 +495,11 @@ void element_block_row(const Mesh& M, int64_t id, const std::vector<int64_t>& cp
   int so = slot(id);
   for (int i = 0; i < n3; ++i)
     for (int j = 0; j < n3; ++j) R[(size_t)i * ncol + so * n3 + j] += L[(size_t)i * n3 + j];
+  if (M.reaction) {
+    mass_matrix(M, g, M.reaction[id], L);
+    for (int i = 0; i < n3; ++i)
+      for (int j = 0; j < n3; ++j) R[(size_t)i * ncol + so * n3 + j] += L[(size_t)i * n3 + j];
+  }
   for (int d = 0; d < 3; ++d)
     for (int s = 0; s < 2; ++s) {
       int64_t nb = neighbour(M, e, d, s);

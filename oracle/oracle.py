@@ -52,7 +52,7 @@ class _CMesh(ctypes.Structure):
     _fields_ = [
         ("nx", _c_i32), ("ny", _c_i32), ("nz", _c_i32), ("degree", _c_i32),
         ("bc", _c_i32), ("quad_extra", _c_i32), ("mutation", _c_i32), ("pad_", _c_i32),
-        ("penalty_hat", _c_dbl), ("vertices", _c_vp), ("theta", _c_vp),
+        ("penalty_hat", _c_dbl), ("vertices", _c_vp), ("theta", _c_vp), ("reaction", _c_vp),
     ]
 
 
@@ -104,6 +104,7 @@ class Mesh:
     quad_extra: int = 0
     mutation: int = 0
     penalty_hat: float = 0.0
+    reaction: Optional[np.ndarray] = None   # (E,) float64 reaction coefficients c_T, element order
     _keep: list = field(default_factory=list, repr=False)
 
     @property
@@ -129,14 +130,17 @@ class Mesh:
             raise ValueError("theta has the wrong length")
         if vx is not None and vx.size != 3 * (self.nx + 1) * (self.ny + 1) * (self.nz + 1):
             raise ValueError("vertices have the wrong length")
-        self._keep = [th, vx]
+        rc = None if self.reaction is None else np.ascontiguousarray(self.reaction, dtype=np.float64)
+        if rc is not None and rc.size != self.E:
+            raise ValueError("reaction has the wrong length")
+        self._keep = [th, vx, rc]
         return _CMesh(self.nx, self.ny, self.nz, self.k, self.bc, self.quad_extra, self.mutation, 0,
-                      self.penalty_hat, _ptr(vx), _ptr(th))
+                      self.penalty_hat, _ptr(vx), _ptr(th), _ptr(rc))
 
     def replace(self, **kw) -> "Mesh":
         d = dict(nx=self.nx, ny=self.ny, nz=self.nz, k=self.k, bc=self.bc, theta=self.theta,
                  vertices=self.vertices, quad_extra=self.quad_extra, mutation=self.mutation,
-                 penalty_hat=self.penalty_hat)
+                 penalty_hat=self.penalty_hat, reaction=self.reaction)
         d.update(kw)
         return Mesh(**d)
 
