@@ -93,6 +93,14 @@ int dg_setup(const dg_mesh_desc* mesh, dg_ctx** out, void* stream);
  * recompute the Jacobi diagonal.  Asynchronous on `stream`. */
 int dg_set_theta(dg_ctx* ctx, const double* theta, void* stream);
 
+/* Add a reaction term int c_T u v to the form (the diffusion-reaction problems
+ * whose operator throughput Sec. 3.3 reports): c (device, nx*ny*nz doubles,
+ * c_T >= 0 for a definite operator) is copied into the workspace; c == NULL
+ * removes the term (the default after dg_setup).  The Jacobi diagonal is
+ * recomputed; dg_dA_dtheta is unaffected (c does not depend on theta).
+ * Asynchronous on `stream`. */
+int dg_set_reaction(dg_ctx* ctx, const double* c, void* stream);
+
 /* y = A x (Sec. 3.3 operator application; form of Sec. 4.1).  x and y are
  * device vectors of N_dof = nx*ny*nz*(k+1)^3 entries of the types given by
  * `prec` (enum dg_precision); x == y is rejected (DG_ERR_ARG). */

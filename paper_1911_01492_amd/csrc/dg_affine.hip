@@ -251,7 +251,7 @@ template <int N, int D, int BX, int BY, int BZ, typename TC, typename TIN, bool 
 __device__ __forceinline__ void face_phase(const MeshArgs<TC>& m, const Tables<TC>& T, const TIN* __restrict__ x,
                                            bool act, int64_t e, const int (&c)[3], const int (&o)[3],
                                            const int (&Nd)[3], int t, int t1, int t2, TC* F, TC* Fe, TC K, TC GL,
-                                           TC GH, TC (&b)[N]) {
+                                           TC GH, TC cr, TC (&b)[N]) {
   constexpr int NN = N * N;
   AxisNeighbours<N, D, BX, BY, BZ, TC, TIN> nb;
   TC u[N], g0 = TC(0), g1 = TC(0);
@@ -273,12 +273,19 @@ __device__ __forceinline__ void face_phase(const MeshArgs<TC>& m, const Tables<T
     nb.scalars(F, t, UL, GLr, UH, GHr);
     line_op_s<N, TC, TRANS>(T, u, g0, g1, UL, GLr, UH, GHr, nb.hasL, nb.hasH, GL, GH, K * m.vs[D], m.ih[D],
                             m.sg[D], m.At[D], b);
+    if (cr != TC(0)) {  // reaction c |T| M u along this line (the other two masses follow)
+      TC mu[N];
+      mass_line<N, TC, false>(T, u, mu);
+#pragma unroll
+      for (int i = 0; i < N; ++i) b[i] += cr * mu[i];
+    }
   }
 }
 
 // y = A x (TRANS: A^T x) on affine meshes.  DOT: also the block partials of
 // <x, y> (y as stored) for the CG scalar <p, A p>.  skip != nullptr &&
-// *skip: do nothing (the solver has converged).
+// *skip: do nothing (the solver has converged).  With a reaction term,
+// c_T |T| M_z u joins b_z, so that the last two masses complete c_T |T| M (x) M (x) M u.
 //
 // With b_d = L_d u (the 1D DG operator along d, face terms included) the
 // element result is y = M_z (M_y b_x + M_x b_y) + M_y M_x b_z.  The phases
@@ -320,19 +327,20 @@ __global__ __launch_bounds__(apply_block(N)) void k_apply_affine(MeshArgs<TC> m,
   TC* S2 = sS2 + le * PE;
   TC* Fe = F + le * 4 * NN;
   const int64_t e = c[0] + (int64_t)m.nx * (c[1] + (int64_t)m.ny * c[2]);
-  TC K = TC(1), G[6];
+  TC K = TC(1), G[6], cr = TC(0);
   if (act) {
     K = m.K[e];
 #pragma unroll
     for (int f = 0; f < 6; ++f) G[f] = m.G[6 * e + f];
+    if (m.R) cr = m.R[e] * m.vol;
   }
   TC b[N], v[N], w[N];
   // ---------------- X: b_x -> S1
-  face_phase<N, 0, BX, BY, BZ, TC, TIN, TRANS>(m, T, x, act, e, c, o, Nd, t, t1, t2, F, Fe, K, G[0], G[1], b);
+  face_phase<N, 0, BX, BY, BZ, TC, TIN, TRANS>(m, T, x, act, e, c, o, Nd, t, t1, t2, F, Fe, K, G[0], G[1], TC(0), b);
   if (act) lds_put<N, 0>(S1, t1, t2, b);
   __syncthreads();  // F is rewritten by the next phase
   // ---------------- Y: b_y -> S2, M_y b_x -> S1
-  face_phase<N, 1, BX, BY, BZ, TC, TIN, TRANS>(m, T, x, act, e, c, o, Nd, t, t1, t2, F, Fe, K, G[2], G[3], b);
+  face_phase<N, 1, BX, BY, BZ, TC, TIN, TRANS>(m, T, x, act, e, c, o, Nd, t, t1, t2, F, Fe, K, G[2], G[3], TC(0), b);
   if (act) {
     lds_get<N, 1>(S1, t1, t2, v);
     mass_line<N, TC, TRANS>(T, v, w);
@@ -355,7 +363,7 @@ __global__ __launch_bounds__(apply_block(N)) void k_apply_affine(MeshArgs<TC> m,
   __syncthreads();
   // ---------------- Z: b_z -> S2, r = M_z S1
   TC r[N];
-  face_phase<N, 2, BX, BY, BZ, TC, TIN, TRANS>(m, T, x, act, e, c, o, Nd, t, t1, t2, F, Fe, K, G[4], G[5], b);
+  face_phase<N, 2, BX, BY, BZ, TC, TIN, TRANS>(m, T, x, act, e, c, o, Nd, t, t1, t2, F, Fe, K, G[4], G[5], cr, b);
   if (act) {
     lds_get<N, 2>(S1, t1, t2, v);
     mass_line<N, TC, TRANS>(T, v, r);
@@ -433,6 +441,7 @@ __global__ __launch_bounds__(256) void k_diag_affine(MeshArgs<double> m, double*
       if (i == id) bi = b[i];
     acc += T.M[ta * kMaxN + ta] * T.M[tb * kMaxN + tb] * bi;
   }
+  if (m.R) acc += m.R[e] * m.vol * T.M[i1 * kMaxN + i1] * T.M[i2 * kMaxN + i2] * T.M[i3 * kMaxN + i3];
   d[gid] = acc;
 }
 

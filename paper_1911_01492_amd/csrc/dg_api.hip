@@ -31,6 +31,9 @@ struct dg_ctx {
   float* K32;
   double* G64;           // face coefficients, 6 per element
   float* G32;
+  double* R64;           // reaction coefficients, 1 per element (used when `reaction`)
+  float* R32;
+  bool reaction;
   double* vert64;
   float* vert32;
   double* dinv64;
@@ -247,8 +250,8 @@ void tables_to_f32(const Tables<double>& a, Tables<float>& b) {
 
 // ------------------------------------------------------------------ workspace
 struct Layout {
-  size_t tab64, tab32, K64, K32, G64, G32, vert64, vert32, dinv64, dinv32, r64, p64, q64, r32, d32, p32, q32, p16,
-      partials, st, total;
+  size_t tab64, tab32, K64, K32, G64, G32, R64, R32, vert64, vert32, dinv64, dinv32, r64, p64, q64, r32, d32, p32,
+      q32, p16, partials, st, total;
 };
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
@@ -286,6 +289,8 @@ Layout layout(const dg_mesh_desc* m) {
   L.K32 = take(E * sizeof(float));
   L.G64 = take(6 * E * sizeof(double));
   L.G32 = take(6 * E * sizeof(float));
+  L.R64 = take(E * sizeof(double));
+  L.R32 = take(E * sizeof(float));
   L.vert64 = take(tri ? nv * 3 * sizeof(double) : 0);
   L.vert32 = take(tri ? nv * 3 * sizeof(float) : 0);
   L.dinv64 = take(nd * sizeof(double));
@@ -335,6 +340,8 @@ MeshArgs<double> args64(const dg_ctx* c) {
   m.G = c->G64;
   m.vert = c->vert64;
   m.tab = c->tab64;
+  m.R = c->reaction ? c->R64 : nullptr;
+  m.vol = (1.0 / c->desc.nx) * (1.0 / c->desc.ny) * (1.0 / c->desc.nz);
   fill_scales(m);
   return m;
 }
@@ -353,6 +360,8 @@ MeshArgs<float> args32(const dg_ctx* c) {
   m.G = c->G32;
   m.vert = c->vert32;
   m.tab = c->tab32;
+  m.R = c->reaction ? c->R32 : nullptr;
+  m.vol = (float)((1.0 / c->desc.nx) * (1.0 / c->desc.ny) * (1.0 / c->desc.nz));
   fill_scales(m);
   return m;
 }
@@ -422,6 +431,9 @@ int dg_setup(const dg_mesh_desc* mesh, dg_ctx** out, void* stream) {
   c->K32 = (float*)(w + L.K32);
   c->G64 = (double*)(w + L.G64);
   c->G32 = (float*)(w + L.G32);
+  c->R64 = (double*)(w + L.R64);
+  c->R32 = (float*)(w + L.R32);
+  c->reaction = false;
   c->vert64 = c->trilinear ? (double*)(w + L.vert64) : nullptr;
   c->vert32 = c->trilinear ? (float*)(w + L.vert32) : nullptr;
   c->dinv64 = (double*)(w + L.dinv64);
@@ -475,6 +487,19 @@ int dg_set_theta(dg_ctx* c, const double* theta, void* stream) {
   if (!theta) return fail(c, DG_ERR_ARG, "theta is NULL");
   hipStream_t s = (hipStream_t)stream;
   HIP_TRY(c, coef_setup(c, theta, s));
+  HIP_TRY(c, compute_dinv(c, s));
+  return DG_OK;
+}
+
+int dg_set_reaction(dg_ctx* c, const double* r, void* stream) {
+  if (!c) return fail(nullptr, DG_ERR_ARG, "ctx is NULL");
+  if (r && !aligned(r, 8)) return fail(c, DG_ERR_ARG, "misaligned reaction coefficients");
+  hipStream_t s = (hipStream_t)stream;
+  if (r) {
+    HIP_TRY(c, hipMemcpyAsync(c->R64, r, c->E * sizeof(double), hipMemcpyDeviceToDevice, s));
+    HIP_TRY(c, launch_to_f32(c->E, c->R64, c->R32, s));
+  }
+  c->reaction = r != nullptr;
   HIP_TRY(c, compute_dinv(c, s));
   return DG_OK;
 }

@@ -44,6 +44,8 @@ struct MeshArgs {
   T sg[3];              // sigma_e = sig_hat / h_d
   T At[3];              // face area h_t1 h_t2 of faces normal to d
   T vs[3];              // At_d / h_d (volume stiffness scale along d, without K)
+  const T* R;           // E reaction coefficients c_T, or nullptr (no reaction term)
+  T vol;                // h_x h_y h_z (affine element volume)
 };
 
 // Block -> logical tile: consecutive logical tiles go to the same XCD (the

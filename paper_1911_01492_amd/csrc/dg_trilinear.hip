@@ -6,7 +6,8 @@
 //   v    = (B (x) B (x) B) u                      interpolation GLL -> Gauss
 //   gr_d = Dg along axis d applied to v            reference gradient
 //   g    = G_q gr,  G_q = w_q K |det J| J^{-1} J^{-T} = w_q K adj(J) adj(J)^T / |det J|
-//   y    = (B^T (x) B^T (x) B^T) sum_d Dg_d^T g_d
+//   y    = (B^T (x) B^T (x) B^T) (sum_d Dg_d^T g_d + c w_q |det J| v)
+// (the last term is the optional reaction, c = 0 without it)
 // Faces (Sec. 4.1 face form b_h^e, with its readings as in the affine path):
 // at the n^2 face Gauss points, traces and reference gradients of both sides
 // (normal derivative from each side's lines, tangential interpolation and
@@ -288,22 +289,22 @@ __global__ __launch_bounds__(kBlock) void k_apply_trilinear(MeshArgs<TC> m, cons
   }
   __syncthreads();
   if (act) {  // phase Z': d/dxi_2, geometry, g = G gr, Dg_z^T g_2
-    TC d1[N], d2[N], d3[N], wz[N];
-    {
-      TC v[N];
-      lds_get<N, 2>(A, t1, t2, v);
-      contract<N, TC, false>(T.Dg, v, d3);
-    }
+    TC d1[N], d2[N], d3[N], wz[N], v[N];
+    lds_get<N, 2>(A, t1, t2, v);
+    contract<N, TC, false>(T.Dg, v, d3);
     lds_get<N, 2>(C, t1, t2, d1);
     lds_get<N, 2>(B, t1, t2, d2);
     const TC wq12 = T.gw[t1] * T.gw[t2] * K;
+    const TC cw12 = m.R ? m.R[e] * T.gw[t1] * T.gw[t2] : TC(0);  // reaction weight
 #pragma unroll
     for (int q = 0; q < N; ++q) {
       const TC xi[3] = {T.gx[t1], T.gx[t2], T.gx[q]};
       TC J[3][3], Aj[3][3];
       trilinear_jacobian(X, xi, J);
       adj3(J, Aj);
-      const TC c = wq12 * T.gw[q] / fabs(det3(J));
+      const TC dJ = fabs(det3(J));
+      const TC c = wq12 * T.gw[q] / dJ;
+      v[q] *= cw12 * T.gw[q] * dJ;  // reaction c w |det J| u at the point
       // G = c adj adj^T (symmetric)
       TC Gm[3][3];
 #pragma unroll
@@ -320,6 +321,8 @@ __global__ __launch_bounds__(kBlock) void k_apply_trilinear(MeshArgs<TC> m, cons
       d3[q] = Gm[2][0] * a1 + Gm[2][1] * a2 + Gm[2][2] * a3;
     }
     contract<N, TC, true>(T.Dg, d3, wz);
+#pragma unroll
+    for (int q = 0; q < N; ++q) wz[q] += v[q];
     lds_put<N, 2>(A, t1, t2, wz);
     lds_put<N, 2>(C, t1, t2, d1);
     lds_put<N, 2>(B, t1, t2, d2);
@@ -396,7 +399,7 @@ __global__ __launch_bounds__(kBlock) void k_apply_trilinear(MeshArgs<TC> m, cons
 template <int N>
 __global__ __launch_bounds__(512) void k_diag_trilinear(MeshArgs<double> m, double* __restrict__ d) {
   constexpr int NN = N * N, N3 = NN * N;
-  __shared__ double G[N3][6];
+  __shared__ double G[N3][7];
   const int64_t e = blockIdx.x;
   const int t = threadIdx.x;
   const Tables<double>& T = *m.tab;
@@ -414,6 +417,7 @@ __global__ __launch_bounds__(512) void k_diag_trilinear(MeshArgs<double> m, doub
     for (int r = 0; r < 3; ++r)
       for (int cc = r; cc < 3; ++cc)
         G[t][k++] = c * (Aj[r][0] * Aj[cc][0] + Aj[r][1] * Aj[cc][1] + Aj[r][2] * Aj[cc][2]);
+    G[t][6] = m.R ? m.R[e] * T.gw[q1] * T.gw[q2] * T.gw[q3] * fabs(det3(J)) : 0.0;  // reaction
   }
   __syncthreads();
   if (t >= N3) return;
@@ -429,7 +433,7 @@ __global__ __launch_bounds__(512) void k_diag_trilinear(MeshArgs<double> m, doub
         const double g2 = b1 * b2 * T.D[q3 * kMaxN + i3];
         const double* Gq = G[q1 + N * (q2 + N * q3)];
         acc += Gq[0] * g0 * g0 + Gq[3] * g1 * g1 + Gq[5] * g2 * g2 +
-               2.0 * (Gq[1] * g0 * g1 + Gq[2] * g0 * g2 + Gq[4] * g1 * g2);
+               2.0 * (Gq[1] * g0 * g1 + Gq[2] * g0 * g2 + Gq[4] * g1 * g2) + Gq[6] * (b1 * b2 * b3) * (b1 * b2 * b3);
       }
   const int ex = (int)(e % m.nx), ey = (int)((e / m.nx) % m.ny), ez = (int)(e / ((int64_t)m.nx * m.ny));
   for (int D = 0; D < 3; ++D) {

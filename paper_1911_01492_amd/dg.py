@@ -30,7 +30,7 @@ _IN_DTYPE = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16}
 _OUT_DTYPE = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.float32}
 
 #: every function declared in include/dg.h
-ABI_FUNCTIONS = ["dg_query_workspace", "dg_setup", "dg_set_theta", "dg_apply", "dg_apply_transpose",
+ABI_FUNCTIONS = ["dg_query_workspace", "dg_setup", "dg_set_theta", "dg_set_reaction", "dg_apply", "dg_apply_transpose",
                  "dg_dA_dtheta", "dg_diagonal", "dg_quadrature_points", "dg_load_vector", "dg_cg_solve",
                  "dg_num_dofs", "dg_num_elements", "dg_nodes_per_dir", "dg_destroy", "dg_last_error"]
 
@@ -79,6 +79,7 @@ def lib() -> ctypes.CDLL:
     L.dg_query_workspace.argtypes = [P(MeshDesc), P(ctypes.c_size_t)]
     L.dg_setup.argtypes = [P(MeshDesc), P(vp), vp]
     L.dg_set_theta.argtypes = [vp, vp, vp]
+    L.dg_set_reaction.argtypes = [vp, vp, vp]
     L.dg_apply.argtypes = [vp, ctypes.c_int, vp, vp, vp]
     L.dg_apply_transpose.argtypes = [vp, ctypes.c_int, vp, vp, vp]
     L.dg_dA_dtheta.argtypes = [vp, vp, vp, vp, vp]
@@ -175,6 +176,12 @@ class DGOperator:
         if theta.numel() != self.E or theta.dtype != torch.float64 or not theta.is_cuda:
             raise ValueError("theta must be a CUDA float64 tensor with one entry per element")
         self._check(lib().dg_set_theta(self._h, _ptr(theta.contiguous()), _stream(stream)))
+
+    def set_reaction(self, c: Optional[torch.Tensor], stream=None):
+        """Reaction coefficients c_T (CUDA float64, one per element) or None to remove the term."""
+        if c is not None and (c.numel() != self.E or c.dtype != torch.float64 or not c.is_cuda):
+            raise ValueError("c must be a CUDA float64 tensor with one entry per element")
+        self._check(lib().dg_set_reaction(self._h, _ptr(None if c is None else c.contiguous()), _stream(stream)))
 
     def apply(self, x: torch.Tensor, prec: str = "f64", out: Optional[torch.Tensor] = None,
               transpose: bool = False, stream=None) -> torch.Tensor:

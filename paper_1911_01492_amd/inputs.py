@@ -15,6 +15,7 @@ import numpy as np
 
 # seeds of the synthetic workloads
 S_X, S_K, S_B, S_OBS, S_NOISE, S_PERT, S_FD = 0, 1, 2, 3, 4, 5, 6
+S_REACT = 7
 
 DIRICHLET = 0
 PERIODIC = 1
@@ -36,6 +37,21 @@ def rng(seed: int) -> np.random.Generator:
 def theta(E: int, seed: int = S_K) -> np.ndarray:
     """theta_T ~ N(0, 1) i.i.d. per element, K_T = exp(theta_T)."""
     return rng(seed).standard_normal(E)
+
+
+def reaction(E: int, lo: float = 0.5, hi: float = 2.0, seed: int = S_REACT) -> np.ndarray:
+    """Per-element reaction coefficients c_T ~ U(lo, hi) (element order)."""
+    return rng(seed).uniform(lo, hi, E)
+
+
+def sheared_vertices(nx: int, ny: int, nz: int, s: float = 0.25) -> np.ndarray:
+    """Vertices of the uniform grid under the affine map x -> x + s y + s z / 2,
+    y -> y + s z (every element is the same parallelepiped)."""
+    V = uniform_vertices(nx, ny, nz).copy()
+    x, y, z = V[:, 0].copy(), V[:, 1].copy(), V[:, 2].copy()
+    V[:, 0] = x + s * y + 0.5 * s * z
+    V[:, 1] = y + s * z
+    return V
 
 
 def uniform_vector(n: int, seed: int = S_X) -> np.ndarray:
