@@ -382,6 +382,37 @@ def main():
             log(f"trilinear: {ex}")
         torch.cuda.empty_cache()
 
+    # ------------------------------------------------------------ the paper's table (Sec. 3.3)
+    if want("paper_table"):
+        # full operator application, diffusion-reaction with coefficients per cell:
+        # problem A on axis-parallel cells (affine kernel), problem B on affine
+        # (here: sheared parallelepiped) cells (trilinear kernel); DOF/s of the
+        # paper's 32-core Xeon run quoted next to each degree as context only
+        paper_A = {1: 170158953.8, 2: 392974786.3, 3: 537750268.0, 4: 595014243.3, 5: 617156313.6,
+                   6: 598962766.1, 7: 570054393.2}
+        paper_B = {1: 118979587.7, 2: 252483269.1, 3: 330453992.0, 4: 388214296.4, 5: 403296404.4,
+                   6: 406075144.9, 7: 398006289.99}
+        rows = []
+        for p in range(1, 8):
+            Np = max(4, int(round((4.0e6) ** (1 / 3) / (p + 1))))
+            E = Np ** 3
+            th = dev(I.theta(E))
+            cr = dev(I.reaction(E))
+            ent = {"p": p, "elements": f"{Np}^3"}
+            for name, V in (("A", None), ("B", I.sheared_vertices(Np, Np, Np))):
+                opp = DGOperator(Np, Np, Np, p, "dirichlet", theta=th, vertices=None if V is None else dev(V))
+                opp.set_reaction(cr)
+                xp = dev(I.uniform_vector(opp.ndof))
+                tt, yy = time_apply(opp, xp, "f64", 20, 5, torch)
+                ent[f"gdofs_{name}"] = round(opp.ndof * 20 / tt / 1e9, 3)
+                ent[f"paper_gdofs_{name}"] = round((paper_A if name == "A" else paper_B)[p] / 1e9, 4)
+                del opp, xp, yy
+            ent["ndof"] = E * (p + 1) ** 3
+            rows.append(ent)
+            log(f"paper table p={p}: {ent}")
+        extras["paper_table_fp64"] = rows
+        torch.cuda.empty_cache()
+
     if extras:
         result["extras"] = extras
     if not args.no_cpu_baseline:
