@@ -56,6 +56,11 @@ def test_query_workspace_validates():
     assert q(degree=8) == dg.DG_ERR_UNSUPPORTED
     assert q(bc=7) == dg.DG_ERR_ARG
     assert q(reserved=1) == dg.DG_ERR_ARG
+    assert q(nx=-3) == dg.DG_ERR_ARG
+    # N_dof must stay below 2^31 (32-bit element offsets in the kernels)
+    assert q(nx=161, ny=161, nz=161, degree=7) == dg.DG_OK      # 2.137e9 DOF
+    assert q(nx=162, ny=162, nz=162, degree=7) == dg.DG_ERR_ARG  # 2.177e9 DOF
+    assert b"2^31" in L.dg_last_error(None)
     assert L.dg_query_workspace(None, ctypes.byref(n)) == dg.DG_ERR_ARG
     assert b"NULL" in L.dg_last_error(None)
     # the workspace of the 64^3 Q4 workload holds the FP64 and FP32 CG vectors

@@ -87,6 +87,28 @@ def test_full_size_sampled_rows(wl):
     assert rel_l2(got, ref) <= 1e-12
 
 
+def test_large_mesh_byte_offsets():
+    """168^3 Q3 (303.5M DOF, 2.4 GB per FP64 vector): element data beyond byte
+    offset 2^31; sampled element rows (first, last, spread) against the oracle."""
+    N, k = 168, 3
+    banner("apply 168^3 Q3 (byte offsets > 2^31)")
+    theta = I.theta(N ** 3)
+    m = O.Mesh(N, N, N, k, theta=theta)
+    op = DGOperator(N, N, N, k, "dirichlet", theta=dev(theta))
+    x = I.uniform_vector(m.ndof)
+    X = dev(x)
+    el = np.unique(np.r_[0, N - 1, N ** 3 // 2, N ** 3 - N * N, N ** 3 - 1,
+                         np.random.default_rng(11).choice(N ** 3, 6, replace=False)]).astype(np.int64)
+    ref = O.apply_rows(m, x, el)
+    for trans in (False, True):
+        y = op.apply(X, transpose=trans)
+        got = host(y.view(-1, m.n3)[torch.as_tensor(el, device="cuda")])
+        assert rel_l2(got, ref) <= 1e-12, trans
+        del y
+    del X, op
+    torch.cuda.empty_cache()
+
+
 def test_low_precision_errors():
     """FP32 and BF16 (FP32 accumulation) applies against the FP64 oracle.
     FP32: relative error a modest multiple of 2^-24 times the operator's
