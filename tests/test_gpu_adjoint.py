@@ -57,7 +57,9 @@ def test_sensitivity_full_size():
     el = I.fd_elements(N ** 3)
     el = np.unique(np.r_[el, 0, N ** 3 - 1, N - 1])
     ref = O.dA_dtheta_elems(m, u, v, el)
-    assert np.max(np.abs(g[el] - ref)) <= 1e-12 * np.max(np.abs(ref))
+    e = np.max(np.abs(g[el] - ref)) / np.max(np.abs(ref))
+    print(f"dA/dtheta 32^3 Q3 sampled elements: max rel err {e:.3e}")
+    assert e <= 1e-12
     Av = host(op.apply(dev(v)))
     assert abs(g.sum() - u @ Av) <= 1e-11 * abs(u @ Av)
 
@@ -95,7 +97,9 @@ def test_adjoint_gradient_small_vs_oracle_and_fd():
     lam = spla.spsolve(A0.T.tocsc(), u0 - u_obs)
     g_ora = -O.dA_dtheta(m, lam, u0)
     assert abs(float(loss.detach()) - J0) <= 1e-10 * J0
-    assert np.max(np.abs(g_gpu - g_ora)) <= 1e-8 * np.max(np.abs(g_ora))
+    e = np.max(np.abs(g_gpu - g_ora)) / np.max(np.abs(g_ora))
+    print(f"adjoint gradient 4^3 Q3 vs oracle adjoint: max rel err {e:.3e}")
+    assert e <= 1e-8
     h = 1e-6
     for T in I.fd_elements(N ** 3, m=8):
         tp, tm = theta.copy(), theta.copy()

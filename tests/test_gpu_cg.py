@@ -61,7 +61,10 @@ def test_solution_matches_oracle(small, prec, mode):
     # the oracle's matrix measures the true residual of the GPU solution
     assert np.linalg.norm(bs - A @ xs) <= 1.2e-10 * np.linalg.norm(bs)
     x_ref, it, rr = O.pcg(A, bs, rtol=1e-13)
-    assert rel_l2(xs, x_ref) <= 1e-7
+    err = rel_l2(xs, x_ref)
+    print(f"cg {prec} {mode}: true rel residual (oracle CSR) "
+          f"{np.linalg.norm(bs - A @ xs) / np.linalg.norm(bs):.3e}, solution rel err vs oracle {err:.3e}")
+    assert err <= 1e-7
     if prec == "f64":
         assert info["outer_iters"] == 0
     else:
@@ -127,4 +130,6 @@ def test_full_size_exact_solution():
         print(prec, mode, info)
         assert info["status"] == DG_OK
         x_ex = O.fast_diag_solve(N, N, N, k, O.DIRICHLET, host(b))
-        assert rel_l2(host(x), x_ex) <= 1e-7
+        err = rel_l2(host(x), x_ex)
+        print(f"cg {prec} {mode} 32^3 Q3 K=1: solution rel err vs exact solve {err:.3e}")
+        assert err <= 1e-7

@@ -85,7 +85,9 @@ def test_full_size_sampled_rows():
     y = host(op.apply(dev(x)))
     el = np.array([0, N - 1, N * N * N - 1, (N // 2) * (1 + N + N * N), 12345, 70000], dtype=np.int64)
     ref = O.apply_rows(m, x, el)
-    assert rel_l2(y.reshape(-1, m.n3)[el], ref) <= 1e-12
+    e64 = rel_l2(y.reshape(-1, m.n3)[el], ref)
+    print(f"fp64 trilinear 48^3 Q7 sampled rows: rel err {e64:.3e}")
+    assert e64 <= 1e-12
     y32 = host(op.apply(dev(I.to_f32(x), torch.float32), prec="f32"))
     e32 = rel_l2(y32.reshape(-1, m.n3)[el], ref)
     print(f"fp32 trilinear error on sampled rows {e32:.3e}")
