@@ -186,8 +186,8 @@ def main():
                     help="also run a plain 256 MiB device copy (reference for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the sharding design is described in DESIGN.md).", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(--gpus must be 1).", file=sys.stderr)
         sys.exit(2)
 
     import torch
