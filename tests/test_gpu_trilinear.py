@@ -94,6 +94,28 @@ def test_full_size_sampled_rows():
     assert e32 <= 1e-4
 
 
+def test_low_precision_applies():
+    """FP32 and BF16-in applies on a perturbed trilinear mesh: arithmetic error
+    against the oracle applied to the rounded input, total error against the
+    FP64 input (bars from the FP32 / BF16 unit roundoff)."""
+    from tests.gpu_util import bf16_dev
+    shape, k = (3, 3, 2), 4
+    V = box_vertices(*shape, seed=5)
+    banner("trilinear fp32 / bf16")
+    m, op, x = _run(shape, k, "dirichlet", V, seed=6)
+    A = O.assemble(m)
+    y = A @ x
+    x32 = I.to_f32(x).astype(np.float64)
+    y32 = host(op.apply(dev(I.to_f32(x), torch.float32), prec="f32").double())
+    assert rel_l2(y32, A @ x32) <= 2e-5
+    bits = I.to_bf16_bits(x)
+    xb = I.bf16_bits_to_f64(bits)
+    yb = host(op.apply(bf16_dev(bits), prec="bf16").double())
+    e_ar, e_tot = rel_l2(yb, A @ xb), rel_l2(yb, y)
+    print(f"trilinear bf16 arithmetic err {e_ar:.3e}, total err {e_tot:.3e}")
+    assert e_ar <= 2e-5 and e_tot <= 2e-2
+
+
 def test_diagonal_and_cg():
     banner("trilinear diagonal and CG")
     shape, k = (4, 4, 4), 3
@@ -102,8 +124,9 @@ def test_diagonal_and_cg():
     A = O.assemble(m)
     assert rel_l2(host(op.diagonal()), A.diagonal()) <= 1e-13
     b = dev(I.uniform_vector(m.ndof, seed=9))
-    for prec in ("f64", "f32"):
-        u, info = op.cg_solve(b, prec_inner=prec, rtol=1e-10)
+    for prec, mode in (("f64", "restart"), ("f32", "restart"), ("f32", "keep"), ("bf16", "keep")):
+        u, info = op.cg_solve(b, prec_inner=prec, rtol=1e-10, dc_mode=mode)
+        print(prec, mode, info)
         assert info["status"] == DG_OK
         bs = host(b)
         assert np.linalg.norm(bs - A @ host(u)) <= 1.2e-10 * np.linalg.norm(bs)
