@@ -187,13 +187,13 @@ struct AxisNeighbours {
   int64_t eL, eH;
   TC gL[N], gH[N];
   __device__ __forceinline__ void locate(int nx, int ny, const int (&c)[3], const int (&o)[3],
-                                         const int (&Nd)[3], int periodic) {
+                                         const int (&Nd)[3], int periodic, bool slot = true) {
     constexpr int Bd = D == 0 ? BX : (D == 1 ? BY : BZ);
     constexpr int sD = D == 0 ? 1 : (D == 1 ? BX : BX * BY);
     const int el = (c[0] - o[0]) + BX * ((c[1] - o[1]) + BY * (c[2] - o[2]));
     const int cl = nb_coord(c[D], 0, Nd[D], periodic), ch = nb_coord(c[D], 1, Nd[D], periodic);
-    hasL = cl >= 0;
-    hasH = ch >= 0;
+    hasL = slot && cl >= 0;
+    hasH = slot && ch >= 0;
     const int ll = cl - o[D], lh = ch - o[D];
     inL = hasL && ll >= 0 && ll < Bd;
     inH = hasH && lh >= 0 && lh < Bd;
@@ -246,7 +246,9 @@ struct AxisNeighbours {
 // One face-aware direction of the affine apply: b = L_D u on this thread's
 // line along axis D (own line from HBM, neighbour face scalars from the
 // brick's exchange area F or from HBM).  Contains one barrier; every thread
-// of the block calls it.
+// of the block calls it.  act == false: a thread without an element of its
+// own (it computes on a clamped element, sees no neighbours, and its result
+// is discarded).
 template <int N, int D, int BX, int BY, int BZ, typename TC, typename TIN, bool TRANS>
 __device__ __forceinline__ void face_phase(const MeshArgs<TC>& m, const Tables<TC>& T, const TIN* __restrict__ x,
                                            bool act, int64_t e, const int (&c)[3], const int (&o)[3],
@@ -254,9 +256,9 @@ __device__ __forceinline__ void face_phase(const MeshArgs<TC>& m, const Tables<T
                                            TC GH, TC cr, TC (&b)[N]) {
   constexpr int NN = N * N;
   AxisNeighbours<N, D, BX, BY, BZ, TC, TIN> nb;
-  TC u[N], g0 = TC(0), g1 = TC(0);
-  if (act) {
-    nb.locate(m.nx, m.ny, c, o, Nd, m.periodic);
+  TC u[N], g0, g1;
+  {
+    nb.locate(m.nx, m.ny, c, o, Nd, m.periodic, act);
     nb.fetch(x, t1, t2);
     glb_get<N, D, TC, TIN>(x, e, t1, t2, u);
     nb.reduce(T);
@@ -268,7 +270,7 @@ __device__ __forceinline__ void face_phase(const MeshArgs<TC>& m, const Tables<T
     Fe[3 * NN + t] = g1;
   }
   __syncthreads();
-  if (act) {
+  {
     TC UL, GLr, UH, GHr;
     nb.scalars(F, t, UL, GLr, UH, GHr);
     line_op_s<N, TC, TRANS>(T, u, g0, g1, UL, GLr, UH, GHr, nb.hasL, nb.hasH, GL, GH, K * m.vs[D], m.ih[D],
@@ -307,8 +309,9 @@ __global__ __launch_bounds__(apply_block(N)) void k_apply_affine(MeshArgs<TC> m,
   constexpr bool F_IN_S2 = 4 * NN <= PE;
   constexpr int BLOCK = apply_block(N);
   static_assert(TE * NN <= BLOCK && BLOCK <= kBlock, "brick too large");
-  __shared__ TC sS1[TE * PE], sS2[TE * PE];
-  __shared__ TC sFx[F_IN_S2 ? 1 : TE * 4 * NN];
+  // one spare element slot takes the writes of threads without an element
+  __shared__ TC sS1[(TE + 1) * PE], sS2[(TE + 1) * PE];
+  __shared__ TC sFx[F_IN_S2 ? 1 : (TE + 1) * 4 * NN];
   __shared__ double red[BLOCK / 64];
   if (skip != nullptr && *skip) return;
   TC* F = F_IN_S2 ? sS2 : sFx;
@@ -320,39 +323,41 @@ __global__ __launch_bounds__(apply_block(N)) void k_apply_affine(MeshArgs<TC> m,
   const int Nd[3] = {m.nx, m.ny, m.nz};
   const int tid = threadIdx.x, el = tid / NN, t = tid - el * NN, t1 = t % N, t2 = t / N;
   const int lx = el % BX, ly = (el / BX) % BY, lz = el / (BX * BY);
-  const int c[3] = {o[0] + lx, o[1] + ly, o[2] + lz};
-  const bool act = el < TE && c[0] < m.nx && c[1] < m.ny && c[2] < m.nz;
-  const int le = act ? el : 0;
+  const int cu[3] = {o[0] + lx, o[1] + ly, o[2] + lz};
+  // act: the thread owns an element of the mesh.  The others (padding lanes,
+  // bricks overhanging the mesh) compute on the nearest mesh element, write
+  // only their own or the spare LDS slot, and store nothing.
+  const bool act = el < TE && cu[0] < m.nx && cu[1] < m.ny && cu[2] < m.nz;
+  const int c[3] = {min(cu[0], m.nx - 1), min(cu[1], m.ny - 1), min(cu[2], m.nz - 1)};
+  const int le = el < TE ? el : TE;
   TC* S1 = sS1 + le * PE;
   TC* S2 = sS2 + le * PE;
   TC* Fe = F + le * 4 * NN;
   const int64_t e = c[0] + (int64_t)m.nx * (c[1] + (int64_t)m.ny * c[2]);
-  TC K = TC(1), G[6], cr = TC(0);
-  if (act) {
-    K = m.K[e];
+  TC K, G[6], cr = TC(0);
+  K = m.K[e];
 #pragma unroll
-    for (int f = 0; f < 6; ++f) G[f] = m.G[6 * e + f];
-    if (m.R) cr = m.R[e] * m.vol;
-  }
+  for (int f = 0; f < 6; ++f) G[f] = m.G[6 * e + f];
+  if (m.R) cr = m.R[e] * m.vol;
   TC b[N], v[N], w[N];
   // ---------------- X: b_x -> S1
   face_phase<N, 0, BX, BY, BZ, TC, TIN, TRANS>(m, T, x, act, e, c, o, Nd, t, t1, t2, F, Fe, K, G[0], G[1], TC(0), b);
-  if (act) lds_put<N, 0>(S1, t1, t2, b);
+  lds_put<N, 0>(S1, t1, t2, b);
   __syncthreads();  // F is rewritten by the next phase
   // ---------------- Y: b_y -> S2, M_y b_x -> S1
   face_phase<N, 1, BX, BY, BZ, TC, TIN, TRANS>(m, T, x, act, e, c, o, Nd, t, t1, t2, F, Fe, K, G[2], G[3], TC(0), b);
-  if (act) {
+  {
     lds_get<N, 1>(S1, t1, t2, v);
     mass_line<N, TC, TRANS>(T, v, w);
   }
   if (F_IN_S2) __syncthreads();  // the face scalars in S2 have been read
-  if (act) {
+  {
     lds_put<N, 1>(S2, t1, t2, b);
     lds_put<N, 1>(S1, t1, t2, w);
   }
   __syncthreads();
   // ---------------- X2: M_y b_x + M_x b_y -> S1
-  if (act) {
+  {
     lds_get<N, 0>(S2, t1, t2, v);
     lds_get<N, 0>(S1, t1, t2, w);
     mass_line<N, TC, TRANS>(T, v, b);
@@ -364,21 +369,21 @@ __global__ __launch_bounds__(apply_block(N)) void k_apply_affine(MeshArgs<TC> m,
   // ---------------- Z: b_z -> S2, r = M_z S1
   TC r[N];
   face_phase<N, 2, BX, BY, BZ, TC, TIN, TRANS>(m, T, x, act, e, c, o, Nd, t, t1, t2, F, Fe, K, G[4], G[5], cr, b);
-  if (act) {
+  {
     lds_get<N, 2>(S1, t1, t2, v);
     mass_line<N, TC, TRANS>(T, v, r);
   }
   if (F_IN_S2) __syncthreads();
-  if (act) lds_put<N, 2>(S2, t1, t2, b);
+  lds_put<N, 2>(S2, t1, t2, b);
   __syncthreads();
   // ---------------- X3, Y3: S2 <- M_y M_x S2
-  if (act) {
+  {
     lds_get<N, 0>(S2, t1, t2, v);
     mass_line<N, TC, TRANS>(T, v, w);
     lds_put<N, 0>(S2, t1, t2, w);
   }
   __syncthreads();
-  if (act) {
+  {
     lds_get<N, 1>(S2, t1, t2, v);
     mass_line<N, TC, TRANS>(T, v, w);
     lds_put<N, 1>(S2, t1, t2, w);
@@ -386,8 +391,8 @@ __global__ __launch_bounds__(apply_block(N)) void k_apply_affine(MeshArgs<TC> m,
   __syncthreads();
   // ---------------- Z2: y = r + S2
   double part = 0.0;
+  lds_get<N, 2>(S2, t1, t2, v);
   if (act) {
-    lds_get<N, 2>(S2, t1, t2, v);
     TOUT* py = y + e * N3;
     if (DOT) glb_get<N, 2, TC, TIN>(x, e, t1, t2, w);
 #pragma unroll
