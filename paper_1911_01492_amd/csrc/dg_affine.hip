@@ -309,9 +309,10 @@ __global__ __launch_bounds__(apply_block(N)) void k_apply_affine(MeshArgs<TC> m,
   constexpr bool F_IN_S2 = 4 * NN <= PE;
   constexpr int BLOCK = apply_block(N);
   static_assert(TE * NN <= BLOCK && BLOCK <= kBlock, "brick too large");
-  // one spare element slot takes the writes of threads without an element
-  __shared__ TC sS1[(TE + 1) * PE], sS2[(TE + 1) * PE];
-  __shared__ TC sFx[F_IN_S2 ? 1 : (TE + 1) * 4 * NN];
+  // a spare element slot takes the writes of padding threads (if the block has any)
+  constexpr int SLOTS = TE * NN < BLOCK ? TE + 1 : TE;
+  __shared__ TC sS1[SLOTS * PE], sS2[SLOTS * PE];
+  __shared__ TC sFx[F_IN_S2 ? 1 : SLOTS * 4 * NN];
   __shared__ double red[BLOCK / 64];
   if (skip != nullptr && *skip) return;
   TC* F = F_IN_S2 ? sS2 : sFx;
