@@ -1,7 +1,8 @@
 /*
  * dg.h -- C ABI of libdg: matrix-free, sum-factorised application of the
  * symmetric weighted interior-penalty (SWIPDG) operator for
- * -div(K grad u) = f on structured hexahedral meshes of the unit cube, with a
+ * -div(K grad u) = f (optionally -div(K grad u) + c u = f, dg_set_reaction)
+ * on structured hexahedral meshes of the unit cube, with a
  * tensor-product Q_k Lagrange basis on Gauss-Lobatto nodes, on one AMD
  * Instinct MI355X (gfx950).
  *
@@ -106,8 +107,10 @@ int dg_set_reaction(dg_ctx* ctx, const double* c, void* stream);
  * `prec` (enum dg_precision); x == y is rejected (DG_ERR_ARG). */
 int dg_apply(dg_ctx* ctx, int prec, const void* x, void* y, void* stream);
 
-/* y = A^T x, evaluated from the transposed 1D operators (equal to A x up to
- * rounding since the form is symmetric). */
+/* y = A^T x.  Affine meshes: evaluated from the transposed 1D operators and
+ * the transposed face algebra (equal to A x up to rounding since the form is
+ * symmetric); trilinear meshes: the apply itself (the discrete form is
+ * symmetric).  Arguments and errors as dg_apply. */
 int dg_apply_transpose(dg_ctx* ctx, int prec, const void* x, void* y, void* stream);
 
 /* g_T = u^T (dA / dtheta_T) v for every element T (device: u, v N_dof
