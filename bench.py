@@ -314,6 +314,7 @@ def main():
         torch.cuda.empty_cache()
         b3 = dev(I.uniform_vector(op3.ndof, seed=I.S_B))
         for prec, mode in CG_VARIANTS:
+            op3.cg_solve(b3, prec_inner=prec, rtol=1e-10, dc_mode=mode, maxit=30)  # warm
             u3, info = op3.cg_solve(b3, prec_inner=prec, rtol=1e-10, dc_mode=mode)
             tag = prec if prec == "f64" else f"{prec}_{mode}"
             extras[f"cg_{tag}_{wl3}"] = info
