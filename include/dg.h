@@ -116,7 +116,10 @@ int dg_apply_transpose(dg_ctx* ctx, int prec, const void* x, void* y, void* stre
 /* g_T = u^T (dA / dtheta_T) v for every element T (device: u, v N_dof
  * doubles, g nx*ny*nz doubles): the volume form with K_T and each face form
  * of T with d gamma_e / d theta_T = gamma_e K_other / (K^- + K^+) (boundary:
- * K_T).  FP64.  Affine meshes only (DG_ERR_UNSUPPORTED on trilinear ones). */
+ * K_T); the reaction term does not depend on theta.  FP64, affine and
+ * trilinear meshes (on trilinear meshes the context's CG work space holds
+ * per-element partial forms, so the call must not overlap a dg_cg_solve on
+ * the same context). */
 int dg_dA_dtheta(dg_ctx* ctx, const double* u, const double* v, double* g, void* stream);
 
 /* d = diag(A) (device, N_dof doubles), FP64. */

@@ -531,8 +531,10 @@ int dg_apply_transpose(dg_ctx* c, int prec, const void* x, void* y, void* stream
 int dg_dA_dtheta(dg_ctx* c, const double* u, const double* v, double* g, void* stream) {
   if (!c) return fail(nullptr, DG_ERR_ARG, "ctx is NULL");
   if (!u || !v || !g) return fail(c, DG_ERR_ARG, "u, v or g is NULL");
-  if (c->trilinear) return fail(c, DG_ERR_UNSUPPORTED, "dA/dtheta is implemented for affine meshes only");
-  HIP_TRY(c, launch_dA_affine(c->n, args64(c), u, v, g, (hipStream_t)stream));
+  if (c->trilinear)  // the 7 per-element parts go to the FP64 CG work vector r (7 E <= N_dof)
+    HIP_TRY(c, launch_dA_trilinear(c->n, args64(c), u, v, c->r64, g, (hipStream_t)stream));
+  else
+    HIP_TRY(c, launch_dA_affine(c->n, args64(c), u, v, g, (hipStream_t)stream));
   return DG_OK;
 }
 

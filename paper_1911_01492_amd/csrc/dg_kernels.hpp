@@ -49,6 +49,9 @@ hipError_t launch_apply_trilinear(int n, int prec, int trans, int dot, const Mes
                                   const MeshArgs<float>& m32, const void* x, void* y, double* partials,
                                   CgState* st, int par, const int* skip, hipStream_t s);
 hipError_t launch_diag_trilinear(int n, const MeshArgs<double>& m, double* d, hipStream_t s);
+// g_T = u^T dA/dtheta_T v on trilinear meshes; parts: 7 E doubles of scratch
+hipError_t launch_dA_trilinear(int n, const MeshArgs<double>& m, const double* u, const double* v, double* parts,
+                               double* g, hipStream_t s);
 
 // geometry / load vector (any mesh)
 hipError_t launch_quad_points(int n, const MeshArgs<double>& m, double* xq, hipStream_t s);

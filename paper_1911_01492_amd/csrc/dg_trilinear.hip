@@ -47,9 +47,11 @@ __device__ __forceinline__ void corner_of(const MeshArgs<TC>& m, int64_t e, int 
 }
 
 // Face contributions of the face normal to axis D on side s of the thread's
-// element, added into the element's accumulator tile Y.  All threads of the
+// element, added into the element's accumulator tile Y.  UNIT: with the face
+// coefficient set to 1 (gamma_e on interior faces, K_T on boundary faces),
+// for the sensitivity dA/dtheta.  All threads of the
 // block call this (it synchronises); act marks threads owning an element.
-template <int N, int D, typename TC, typename TIN>
+template <int N, int D, typename TC, typename TIN, bool UNIT = false>
 __device__ void face_term(const MeshArgs<TC>& m, const Tables<TC>& T, const TIN* __restrict__ x, int64_t e,
                           int ex, int ey, int ez, const TC (&X)[8][3], TC (&Xn)[8][3], TC K, int t1, int t2,
                           TC* Y, TC (*F)[N * N], bool act, int s) {
@@ -165,7 +167,7 @@ __device__ void face_term(const MeshArgs<TC>& m, const Tables<TC>& T, const TIN*
       Nv[2] = Jm[0][c1] * Jm[1][c2] - Jm[1][c1] * Jm[0][c2];
       const TC area = sqrt(Nv[0] * Nv[0] + Nv[1] * Nv[1] + Nv[2] * Nv[2]);
       const TC Kn = m.K[nb];
-      const TC gam = TC(2) * K * Kn / (K + Kn);
+      const TC gam = UNIT ? TC(1) : TC(2) * K * Kn / (K + Kn);
       const TC Jq = s ? uo - un : un - uo;
       const TC Fq = TC(0.5) * gam * w * ((go[0] + gn[0]) * Nv[0] + (go[1] + gn[1]) * Nv[1] + (go[2] + gn[2]) * Nv[2]);
       const TC pen = sig * gam * area * w * Jq;
@@ -184,8 +186,9 @@ __device__ void face_term(const MeshArgs<TC>& m, const Tables<TC>& T, const TIN*
       Nv[1] = sg * (Jo[2][c1] * Jo[0][c2] - Jo[0][c1] * Jo[2][c2]);
       Nv[2] = sg * (Jo[0][c1] * Jo[1][c2] - Jo[1][c1] * Jo[0][c2]);
       const TC area = sqrt(Nv[0] * Nv[0] + Nv[1] * Nv[1] + Nv[2] * Nv[2]);
-      P = -K * w * (go[0] * Nv[0] + go[1] * Nv[1] + go[2] * Nv[2]) + sig * K * area * w * uo;
-      const TC cr = -K * w * uo / deto;
+      const TC Kb = UNIT ? TC(1) : K;
+      P = -Kb * w * (go[0] * Nv[0] + go[1] * Nv[1] + go[2] * Nv[2]) + sig * Kb * area * w * uo;
+      const TC cr = -Kb * w * uo / deto;
       TC R[3];
 #pragma unroll
       for (int c = 0; c < 3; ++c) R[c] = cr * (Ao[c][0] * Nv[0] + Ao[c][1] * Nv[1] + Ao[c][2] * Nv[2]);
@@ -230,41 +233,25 @@ __device__ void face_term(const MeshArgs<TC>& m, const Tables<TC>& T, const TIN*
   }
 }
 
-template <int N, typename TIN, typename TOUT, typename TC, bool DOT>
-__global__ __launch_bounds__(kBlock) void k_apply_trilinear(MeshArgs<TC> m, const TIN* __restrict__ x,
-                                                            TOUT* __restrict__ y, double* partials,
-                                                            const int* skip) {
-  constexpr int NN = N * N, N3 = NN * N, EPB = elems_per_block(N), PE = Lay<N, TC>::PE;
-  __shared__ TC sA[EPB * PE], sB[EPB * PE], sC[EPB * PE];
-  __shared__ TC sX[EPB][8][3], sXn[EPB][8][3];
-  __shared__ TC sF[EPB][10][NN];
-  __shared__ double red[kBlock / 64];
-  if (skip != nullptr && *skip) return;
-  const Tables<TC>& T = *m.tab;
-  const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
-  const int tid = threadIdx.x, el = tid / NN, t = tid % NN, t1 = t % N, t2 = t / N;
-  const int64_t e = blk * EPB + el;
-  const bool act = (el < EPB) && (e < m.E);
-  const int le = act ? el : 0;
-  TC* A = sA + le * PE;
-  TC* B = sB + le * PE;
-  TC* C = sC + le * PE;
-  int ex = 0, ey = 0, ez = 0;
-  TC K = TC(1);
+// Volume part of the trilinear apply for the thread's element: the element
+// tile C receives (B^T (x) B^T (x) B^T)(sum_d Dg_d^T g_d + c w |det J| v) of
+// the input x (see the file header), with coefficient K (and the reaction
+// coefficients of m, if any).  Xs: the element's corner slot in LDS (filled
+// here).  All threads of the block call this (it synchronises).
+template <int N, typename TC, typename TIN>
+__device__ void tri_volume(const MeshArgs<TC>& m, const Tables<TC>& T, const TIN* __restrict__ x, int64_t e,
+                           bool act, int t, int t1, int t2, TC K, TC (&Xs)[8][3], TC* A, TC* B, TC* C) {
+  constexpr int NN = N * N;
   if (act) {
     TC uz[N];
-    ex = (int)(e % m.nx);
-    ey = (int)((e / m.nx) % m.ny);
-    ez = (int)(e / ((int64_t)m.nx * m.ny));
-    K = m.K[e];
-    for (int q = t; q < 24; q += NN) corner_of(m, e, q / 3, q % 3, sX[le][q / 3][q % 3]);
+    for (int q = t; q < 24; q += NN) corner_of(m, e, q / 3, q % 3, Xs[q / 3][q % 3]);
     glb_get<N, 2, TC, TIN>(x, e, t1, t2, uz);
     TC a[N];
     contract<N, TC, false>(T.B, uz, a);  // phase Z: interpolate along z
     lds_put<N, 2>(A, t1, t2, a);
   }
   __syncthreads();
-  const TC (&X)[8][3] = sX[le];
+  const TC (&X)[8][3] = Xs;
   if (act) {  // phase Y
     TC a[N], b[N];
     lds_get<N, 1>(A, t1, t2, a);
@@ -362,6 +349,37 @@ __global__ __launch_bounds__(kBlock) void k_apply_trilinear(MeshArgs<TC> m, cons
     contract<N, TC, true>(T.B, w, o);
     lds_put<N, 2>(C, t1, t2, o);
   }
+}
+
+template <int N, typename TIN, typename TOUT, typename TC, bool DOT>
+__global__ __launch_bounds__(kBlock) void k_apply_trilinear(MeshArgs<TC> m, const TIN* __restrict__ x,
+                                                            TOUT* __restrict__ y, double* partials,
+                                                            const int* skip) {
+  constexpr int NN = N * N, N3 = NN * N, EPB = elems_per_block(N), PE = Lay<N, TC>::PE;
+  __shared__ TC sA[EPB * PE], sB[EPB * PE], sC[EPB * PE];
+  __shared__ TC sX[EPB][8][3], sXn[EPB][8][3];
+  __shared__ TC sF[EPB][10][NN];
+  __shared__ double red[kBlock / 64];
+  if (skip != nullptr && *skip) return;
+  const Tables<TC>& T = *m.tab;
+  const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
+  const int tid = threadIdx.x, el = tid / NN, t = tid % NN, t1 = t % N, t2 = t / N;
+  const int64_t e = blk * EPB + el;
+  const bool act = (el < EPB) && (e < m.E);
+  const int le = act ? el : 0;
+  TC* A = sA + le * PE;
+  TC* B = sB + le * PE;
+  TC* C = sC + le * PE;
+  int ex = 0, ey = 0, ez = 0;
+  TC K = TC(1);
+  if (act) {
+    ex = (int)(e % m.nx);
+    ey = (int)((e / m.nx) % m.ny);
+    ez = (int)(e / ((int64_t)m.nx * m.ny));
+    K = m.K[e];
+  }
+  tri_volume<N, TC, TIN>(m, T, x, e, act, t, t1, t2, K, sX[le], A, B, C);
+  const TC (&X)[8][3] = sX[le];
   // faces (each call synchronises before touching shared buffers)
   face_term<N, 0, TC, TIN>(m, T, x, e, ex, ey, ez, X, sXn[le], K, t1, t2, C, sF[le], act, 0);
   face_term<N, 0, TC, TIN>(m, T, x, e, ex, ey, ez, X, sXn[le], K, t1, t2, C, sF[le], act, 1);
@@ -390,6 +408,107 @@ __global__ __launch_bounds__(kBlock) void k_apply_trilinear(MeshArgs<TC> m, cons
     const double mine[1] = {block_sum<kBlock>(part, red)};
     store_partials<1>(mine, partials, blockIdx.x);
   }
+}
+
+// ---------------------------------------------------------------- dA / dtheta
+// Per element T, with u and v: parts[7 T] = u_T . (volume form of T with
+// K = 1) v_T and parts[7 T + 1 + 2 d + s] = u_T . (rows of T of the face form
+// of face (d, s) with unit coefficient) v.  The reaction term does not depend
+// on theta and is left out.
+template <int N>
+__global__ __launch_bounds__(kBlock) void k_dA_parts_trilinear(MeshArgs<double> m, const double* __restrict__ u,
+                                                               const double* __restrict__ v,
+                                                               double* __restrict__ parts) {
+  constexpr int NN = N * N, EPB = elems_per_block(N), PE = Lay<N, double>::PE;
+  __shared__ double sA[EPB * PE], sB[EPB * PE], sC[EPB * PE];
+  __shared__ double sX[EPB][8][3], sXn[EPB][8][3];
+  __shared__ double sF[EPB][10][NN];
+  __shared__ double sRed[kBlock];
+  const Tables<double>& T = *m.tab;
+  const int tid = threadIdx.x, el = tid / NN, t = tid % NN, t1 = t % N, t2 = t / N;
+  const int64_t e = (int64_t)blockIdx.x * EPB + el;
+  const bool act = (el < EPB) && (e < m.E);
+  const int le = act ? el : 0;
+  double* A = sA + le * PE;
+  double* B = sB + le * PE;
+  double* C = sC + le * PE;
+  int ex = 0, ey = 0, ez = 0;
+  if (act) {
+    ex = (int)(e % m.nx);
+    ey = (int)((e / m.nx) % m.ny);
+    ez = (int)(e / ((int64_t)m.nx * m.ny));
+  }
+  MeshArgs<double> m1 = m;
+  m1.R = nullptr;
+  tri_volume<N, double, double>(m1, T, v, e, act, t, t1, t2, 1.0, sX[le], A, B, C);
+  const double (&X)[8][3] = sX[le];
+  double uz[N];
+  if (act) glb_get<N, 2, double, double>(u, e, t1, t2, uz);
+  // u_T . C for the thread's element, then C = 0 (deterministic: per-thread
+  // partial sums, added in thread order by the element's first thread)
+  auto take = [&](int slot) {
+    __syncthreads();
+    double p = 0.0;
+    if (act) {
+      double c[N], z[N];
+      lds_get<N, 2>(C, t1, t2, c);
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        p += uz[i] * c[i];
+        z[i] = 0.0;
+      }
+      lds_put<N, 2>(C, t1, t2, z);
+    }
+    sRed[tid] = p;
+    __syncthreads();
+    if (act && t == 0) {
+      double s = 0.0;
+      for (int j = 0; j < NN; ++j) s += sRed[el * NN + j];
+      parts[7 * e + slot] = s;
+    }
+  };
+  take(0);
+  face_term<N, 0, double, double, true>(m1, T, v, e, ex, ey, ez, X, sXn[le], 1.0, t1, t2, C, sF[le], act, 0);
+  take(1);
+  face_term<N, 0, double, double, true>(m1, T, v, e, ex, ey, ez, X, sXn[le], 1.0, t1, t2, C, sF[le], act, 1);
+  take(2);
+  face_term<N, 1, double, double, true>(m1, T, v, e, ex, ey, ez, X, sXn[le], 1.0, t1, t2, C, sF[le], act, 0);
+  take(3);
+  face_term<N, 1, double, double, true>(m1, T, v, e, ex, ey, ez, X, sXn[le], 1.0, t1, t2, C, sF[le], act, 1);
+  take(4);
+  face_term<N, 2, double, double, true>(m1, T, v, e, ex, ey, ez, X, sXn[le], 1.0, t1, t2, C, sF[le], act, 0);
+  take(5);
+  face_term<N, 2, double, double, true>(m1, T, v, e, ex, ey, ez, X, sXn[le], 1.0, t1, t2, C, sF[le], act, 1);
+  take(6);
+}
+
+// g_T = K_T parts[T][0] + sum over faces (d, s) of dgamma/dtheta_T times the
+// whole unit-coefficient face form: the rows of T (parts of T) plus the rows
+// of the neighbour N (parts of N for its face (d, 1 - s)).
+// dgamma/dtheta_T = gamma K_N / (K_T + K_N) on interior faces, K_T on boundary faces.
+__global__ __launch_bounds__(256) void k_dA_combine_trilinear(MeshArgs<double> m, const double* __restrict__ parts,
+                                                              double* __restrict__ g) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= m.E) return;
+  const int ex = (int)(e % m.nx), ey = (int)((e / m.nx) % m.ny), ez = (int)(e / ((int64_t)m.nx * m.ny));
+  const double K = m.K[e];
+  double acc = K * parts[7 * e];
+  for (int d = 0; d < 3; ++d)
+    for (int s = 0; s < 2; ++s) {
+      int64_t nb;
+      if (d == 0) nb = neighbour<0>(m, ex, ey, ez, s);
+      else if (d == 1) nb = neighbour<1>(m, ex, ey, ez, s);
+      else nb = neighbour<2>(m, ex, ey, ez, s);
+      const double own = parts[7 * e + 1 + 2 * d + s];
+      if (nb < 0) {
+        acc += K * own;
+      } else {
+        const double Kn = m.K[nb];
+        const double gam = 2.0 * K * Kn / (K + Kn);
+        acc += gam * Kn / (K + Kn) * (own + parts[7 * nb + 1 + 2 * d + (1 - s)]);
+      }
+    }
+  g[e] = acc;
 }
 
 // ---------------------------------------------------------------- diagonal
@@ -559,6 +678,31 @@ static hipError_t run_tri_diag(const MeshArgs<double>& m, double* d, hipStream_t
   hipLaunchKernelGGL((k_diag_trilinear<N>), dim3((unsigned)m.E), dim3(th), 0, s, m, d);
   return hipGetLastError();
 }
+template <int N>
+static hipError_t run_dA_tri(const MeshArgs<double>& m, const double* u, const double* v, double* parts, double* g,
+                             hipStream_t s) {
+  const int64_t nb = element_blocks(N, m.E);
+  hipLaunchKernelGGL((k_dA_parts_trilinear<N>), dim3((unsigned)nb), dim3(kBlock), 0, s, m, u, v, parts);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_dA_combine_trilinear, dim3((unsigned)((m.E + 255) / 256)), dim3(256), 0, s, m, parts, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_dA_trilinear(int n, const MeshArgs<double>& m, const double* u, const double* v, double* parts,
+                               double* g, hipStream_t s) {
+  switch (n) {
+    case 2: return run_dA_tri<2>(m, u, v, parts, g, s);
+    case 3: return run_dA_tri<3>(m, u, v, parts, g, s);
+    case 4: return run_dA_tri<4>(m, u, v, parts, g, s);
+    case 5: return run_dA_tri<5>(m, u, v, parts, g, s);
+    case 6: return run_dA_tri<6>(m, u, v, parts, g, s);
+    case 7: return run_dA_tri<7>(m, u, v, parts, g, s);
+    case 8: return run_dA_tri<8>(m, u, v, parts, g, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 hipError_t launch_diag_trilinear(int n, const MeshArgs<double>& m, double* d, hipStream_t s) {
   switch (n) {
     case 2: return run_tri_diag<2>(m, d, s);

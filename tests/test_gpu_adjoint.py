@@ -44,6 +44,56 @@ def test_sensitivity_kernel(case, k):
     assert np.max(np.abs(g - ref)) <= 1e-12 * np.max(np.abs(ref))
 
 
+@pytest.mark.parametrize("case", [((2, 2, 2), "dirichlet"), ((3, 2, 2), "periodic"), ((1, 2, 2), "periodic"),
+                                  ((3, 3, 2), "dirichlet")])
+@pytest.mark.parametrize("k", [1, 2, 3, 4])
+def test_sensitivity_kernel_trilinear(case, k):
+    """Curved (perturbed trilinear) meshes, with a reaction term that the
+    sensitivity must ignore."""
+    from tests.test_gpu_trilinear import box_vertices
+    shape, bc = case
+    banner(f"dA/dtheta trilinear {shape} {bc} k={k}")
+    E = int(np.prod(shape))
+    theta = I.theta(E, seed=41)
+    V = box_vertices(*shape, seed=42)
+    m = O.Mesh(*shape, k, bc=BCS[bc], theta=theta, vertices=V)
+    op = DGOperator(*shape, k, bc, theta=dev(theta), vertices=dev(V))
+    op.set_reaction(dev(I.reaction(E)))
+    u = I.uniform_vector(m.ndof, seed=43)
+    v = I.uniform_vector(m.ndof, seed=44)
+    g = host(op.dA_dtheta(dev(u), dev(v)))
+    ref = O.dA_dtheta(m, u, v)
+    err = np.max(np.abs(g - ref)) / np.max(np.abs(ref))
+    print(f"dA/dtheta trilinear {shape} {bc} k={k}: max rel err {err:.3e}")
+    assert err <= 1e-12
+
+
+def test_adjoint_gradient_trilinear():
+    """Autograd gradient on a curved 3^3 Q2 mesh against the oracle's adjoint
+    gradient from direct solves."""
+    from tests.test_gpu_trilinear import box_vertices
+    banner("adjoint trilinear")
+    N, k = 3, 2
+    E = N ** 3
+    theta = I.theta(E, seed=51)
+    V = box_vertices(N, N, N, seed=52)
+    m = O.Mesh(N, N, N, k, theta=theta, vertices=V)
+    op = DGOperator(N, N, N, k, "dirichlet", theta=dev(theta), vertices=dev(V))
+    bs = I.uniform_vector(m.ndof, seed=I.S_B)
+    u_obs = I.noise(m.ndof, std=1.0, seed=53)
+    th = dev(theta).requires_grad_(True)
+    u = DGSolve.apply(th, dev(bs), op, {"rtol": 1e-13})
+    loss = 0.5 * torch.sum((u - dev(u_obs)) ** 2)
+    loss.backward()
+    A = O.assemble(m).tocsc()
+    u0 = spla.spsolve(A, bs)
+    lam = spla.spsolve(A.T.tocsc(), u0 - u_obs)
+    g_ora = -O.dA_dtheta(m, lam, u0)
+    e = np.max(np.abs(host(th.grad) - g_ora)) / np.max(np.abs(g_ora))
+    print(f"adjoint gradient trilinear 3^3 Q2 vs oracle adjoint: max rel err {e:.3e}")
+    assert e <= 1e-8
+
+
 def test_sensitivity_full_size():
     """32^3 Q3: sampled elements by the oracle, and sum_T g_T = u^T A v."""
     banner("dA/dtheta full size")
