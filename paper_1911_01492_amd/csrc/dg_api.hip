@@ -34,6 +34,7 @@ struct dg_ctx {
   double* R64;           // reaction coefficients, 1 per element (used when `reaction`)
   float* R32;
   bool reaction;
+  bool affine_geom;      // trilinear mesh whose elements are all parallelepipeds
   double* vert64;
   float* vert32;
   double* dinv64;
@@ -342,6 +343,7 @@ MeshArgs<double> args64(const dg_ctx* c) {
   m.tab = c->tab64;
   m.R = c->reaction ? c->R64 : nullptr;
   m.vol = (1.0 / c->desc.nx) * (1.0 / c->desc.ny) * (1.0 / c->desc.nz);
+  m.affg = c->affine_geom ? 1 : 0;
   fill_scales(m);
   return m;
 }
@@ -362,6 +364,7 @@ MeshArgs<float> args32(const dg_ctx* c) {
   m.tab = c->tab32;
   m.R = c->reaction ? c->R32 : nullptr;
   m.vol = (float)((1.0 / c->desc.nx) * (1.0 / c->desc.ny) * (1.0 / c->desc.nz));
+  m.affg = c->affine_geom ? 1 : 0;
   fill_scales(m);
   return m;
 }
@@ -407,6 +410,29 @@ int dg_query_workspace(const dg_mesh_desc* mesh, size_t* bytes) {
   return DG_OK;
 }
 
+// True when the trilinear map of every element is affine: the coefficients of
+// xi1 xi2, xi1 xi3, xi2 xi3 and xi1 xi2 xi3 vanish (to a few ulps of the
+// element size), i.e. every element is a parallelepiped.
+static bool all_parallelepipeds(int nx, int ny, int nz, const std::vector<double>& v) {
+  const double h = 1.0 / std::max(nx, std::max(ny, nz));
+  const double tol = 64.0 * 2.220446049250313e-16 * std::max(1.0, h);
+  auto X = [&](int ix, int iy, int iz, int a) { return v[3 * (ix + (size_t)(nx + 1) * (iy + (size_t)(ny + 1) * iz)) + a]; };
+  for (int z = 0; z < nz; ++z)
+    for (int y = 0; y < ny; ++y)
+      for (int x = 0; x < nx; ++x)
+        for (int a = 0; a < 3; ++a) {
+          const double c000 = X(x, y, z, a), c100 = X(x + 1, y, z, a), c010 = X(x, y + 1, z, a),
+                       c110 = X(x + 1, y + 1, z, a), c001 = X(x, y, z + 1, a), c101 = X(x + 1, y, z + 1, a),
+                       c011 = X(x, y + 1, z + 1, a), c111 = X(x + 1, y + 1, z + 1, a);
+          const double b12 = c110 - c100 - c010 + c000, b13 = c101 - c100 - c001 + c000,
+                       b23 = c011 - c010 - c001 + c000,
+                       b123 = c111 - c110 - c101 - c011 + c100 + c010 + c001 - c000;
+          if (std::fabs(b12) > tol || std::fabs(b13) > tol || std::fabs(b23) > tol || std::fabs(b123) > tol)
+            return false;
+        }
+  return true;
+}
+
 int dg_setup(const dg_mesh_desc* mesh, dg_ctx** out, void* stream) {
   if (!out) return fail(nullptr, DG_ERR_ARG, "out is NULL");
   *out = nullptr;
@@ -434,6 +460,7 @@ int dg_setup(const dg_mesh_desc* mesh, dg_ctx** out, void* stream) {
   c->R64 = (double*)(w + L.R64);
   c->R32 = (float*)(w + L.R32);
   c->reaction = false;
+  c->affine_geom = false;
   c->vert64 = c->trilinear ? (double*)(w + L.vert64) : nullptr;
   c->vert32 = c->trilinear ? (float*)(w + L.vert32) : nullptr;
   c->dinv64 = (double*)(w + L.dinv64);
@@ -472,6 +499,10 @@ int dg_setup(const dg_mesh_desc* mesh, dg_ctx** out, void* stream) {
     const int64_t nv3 = (int64_t)(mesh->nx + 1) * (mesh->ny + 1) * (mesh->nz + 1) * 3;
     SETUP_TRY(hipMemcpyAsync(c->vert64, mesh->vertices, nv3 * sizeof(double), hipMemcpyDeviceToDevice, s));
     SETUP_TRY(launch_to_f32(nv3, c->vert64, c->vert32, s));
+    std::vector<double> hv((size_t)nv3);
+    SETUP_TRY(hipMemcpyAsync(hv.data(), mesh->vertices, nv3 * sizeof(double), hipMemcpyDeviceToHost, s));
+    SETUP_TRY(hipStreamSynchronize(s));
+    c->affine_geom = all_parallelepipeds(mesh->nx, mesh->ny, mesh->nz, hv);
   }
   SETUP_TRY(compute_dinv(c, s));
   SETUP_TRY(hipStreamSynchronize(s));

@@ -46,6 +46,7 @@ struct MeshArgs {
   T vs[3];              // At_d / h_d (volume stiffness scale along d, without K)
   const T* R;           // E reaction coefficients c_T, or nullptr (no reaction term)
   T vol;                // h_x h_y h_z (affine element volume)
+  int affg;             // trilinear meshes: 1 when every element is a parallelepiped
 };
 
 // Block -> logical tile: consecutive logical tiles go to the same XCD (the

@@ -49,12 +49,13 @@ __device__ __forceinline__ void corner_of(const MeshArgs<TC>& m, int64_t e, int 
 // Face contributions of the face normal to axis D on side s of the thread's
 // element, added into the element's accumulator tile Y.  UNIT: with the face
 // coefficient set to 1 (gamma_e on interior faces, K_T on boundary faces),
-// for the sensitivity dA/dtheta.  All threads of the
+// for the sensitivity dA/dtheta.  AFF: the element is a parallelepiped and
+// Gc holds its constant J, adj J and det J.  All threads of the
 // block call this (it synchronises); act marks threads owning an element.
-template <int N, int D, typename TC, typename TIN, bool UNIT = false>
+template <int N, int D, typename TC, typename TIN, bool UNIT = false, bool AFF = false>
 __device__ void face_term(const MeshArgs<TC>& m, const Tables<TC>& T, const TIN* __restrict__ x, int64_t e,
                           int ex, int ey, int ez, const TC (&X)[8][3], TC (&Xn)[8][3], TC K, int t1, int t2,
-                          TC* Y, TC (*F)[N * N], bool act, int s) {
+                          TC* Y, TC (*F)[N * N], bool act, int s, const TC* Gc = nullptr) {
   constexpr int NN = N * N;
   const int t = t1 + N * t2;
   const int ax = (D == 0) ? 1 : 0;  // reference axis of t1
@@ -128,10 +129,21 @@ __device__ void face_term(const MeshArgs<TC>& m, const Tables<TC>& T, const TIN*
     xi[D] = TC(s);
     xi[ax] = T.gx[t1];
     xi[bx] = T.gx[t2];
-    TC Jo[3][3], Ao[3][3];
-    trilinear_jacobian(X, xi, Jo);
-    adj3(Jo, Ao);
-    const TC deto = det3(Jo);
+    TC Jo[3][3], Ao[3][3], deto;
+    if (AFF) {  // parallelepiped: the element's constant J, adj J, det J (Gc = 9 + 9 + 1 values)
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) {
+          Jo[r][cc] = Gc[3 * r + cc];
+          Ao[r][cc] = Gc[9 + 3 * r + cc];
+        }
+      deto = Gc[18];
+    } else {
+      trilinear_jacobian(X, xi, Jo);
+      adj3(Jo, Ao);
+      deto = det3(Jo);
+    }
     TC gro[3];
     gro[D] = gdo;
     gro[ax] = gao;
@@ -238,7 +250,7 @@ __device__ void face_term(const MeshArgs<TC>& m, const Tables<TC>& T, const TIN*
 // the input x (see the file header), with coefficient K (and the reaction
 // coefficients of m, if any).  Xs: the element's corner slot in LDS (filled
 // here).  All threads of the block call this (it synchronises).
-template <int N, typename TC, typename TIN>
+template <int N, typename TC, typename TIN, bool AFF = false>
 __device__ void tri_volume(const MeshArgs<TC>& m, const Tables<TC>& T, const TIN* __restrict__ x, int64_t e,
                            bool act, int t, int t1, int t2, TC K, TC (&Xs)[8][3], TC* A, TC* B, TC* C) {
   constexpr int NN = N * N;
@@ -283,25 +295,49 @@ __device__ void tri_volume(const MeshArgs<TC>& m, const Tables<TC>& T, const TIN
     lds_get<N, 2>(B, t1, t2, d2);
     const TC wq12 = T.gw[t1] * T.gw[t2] * K;
     const TC cw12 = m.R ? m.R[e] * T.gw[t1] * T.gw[t2] : TC(0);  // reaction weight
-#pragma unroll
-    for (int q = 0; q < N; ++q) {
-      const TC xi[3] = {T.gx[t1], T.gx[t2], T.gx[q]};
+    TC G0[3][3], dJ0 = TC(1);
+    if (AFF) {  // parallelepiped: adj adj^T / |det J| and |det J| are the same at every point
+      const TC xi[3] = {TC(0.5), TC(0.5), TC(0.5)};
       TC J[3][3], Aj[3][3];
       trilinear_jacobian(X, xi, J);
       adj3(J, Aj);
-      const TC dJ = fabs(det3(J));
-      const TC c = wq12 * T.gw[q] / dJ;
-      v[q] *= cw12 * T.gw[q] * dJ;  // reaction c w |det J| u at the point
-      // G = c adj adj^T (symmetric)
-      TC Gm[3][3];
+      dJ0 = fabs(det3(J));
 #pragma unroll
       for (int r = 0; r < 3; ++r)
 #pragma unroll
         for (int cc = r; cc < 3; ++cc) {
-          const TC sgm = Aj[r][0] * Aj[cc][0] + Aj[r][1] * Aj[cc][1] + Aj[r][2] * Aj[cc][2];
-          Gm[r][cc] = c * sgm;
-          Gm[cc][r] = c * sgm;
+          G0[r][cc] = (Aj[r][0] * Aj[cc][0] + Aj[r][1] * Aj[cc][1] + Aj[r][2] * Aj[cc][2]) / dJ0;
+          G0[cc][r] = G0[r][cc];
         }
+    }
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+      TC Gm[3][3];
+      if (AFF) {
+        const TC c = wq12 * T.gw[q];
+        v[q] *= cw12 * T.gw[q] * dJ0;  // reaction c w |det J| u at the point
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+          for (int cc = 0; cc < 3; ++cc) Gm[r][cc] = c * G0[r][cc];
+      } else {
+        const TC xi[3] = {T.gx[t1], T.gx[t2], T.gx[q]};
+        TC J[3][3], Aj[3][3];
+        trilinear_jacobian(X, xi, J);
+        adj3(J, Aj);
+        const TC dJ = fabs(det3(J));
+        const TC c = wq12 * T.gw[q] / dJ;
+        v[q] *= cw12 * T.gw[q] * dJ;  // reaction c w |det J| u at the point
+        // G = c adj adj^T (symmetric)
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+          for (int cc = r; cc < 3; ++cc) {
+            const TC sgm = Aj[r][0] * Aj[cc][0] + Aj[r][1] * Aj[cc][1] + Aj[r][2] * Aj[cc][2];
+            Gm[r][cc] = c * sgm;
+            Gm[cc][r] = c * sgm;
+          }
+      }
       const TC a1 = d1[q], a2 = d2[q], a3 = d3[q];  // G gr in place of gr
       d1[q] = Gm[0][0] * a1 + Gm[0][1] * a2 + Gm[0][2] * a3;
       d2[q] = Gm[1][0] * a1 + Gm[1][1] * a2 + Gm[1][2] * a3;
@@ -351,7 +387,7 @@ __device__ void tri_volume(const MeshArgs<TC>& m, const Tables<TC>& T, const TIN
   }
 }
 
-template <int N, typename TIN, typename TOUT, typename TC, bool DOT>
+template <int N, typename TIN, typename TOUT, typename TC, bool DOT, bool AFF>
 __global__ __launch_bounds__(kBlock) void k_apply_trilinear(MeshArgs<TC> m, const TIN* __restrict__ x,
                                                             TOUT* __restrict__ y, double* partials,
                                                             const int* skip) {
@@ -378,17 +414,32 @@ __global__ __launch_bounds__(kBlock) void k_apply_trilinear(MeshArgs<TC> m, cons
     ez = (int)(e / ((int64_t)m.nx * m.ny));
     K = m.K[e];
   }
-  tri_volume<N, TC, TIN>(m, T, x, e, act, t, t1, t2, K, sX[le], A, B, C);
+  tri_volume<N, TC, TIN, AFF>(m, T, x, e, act, t, t1, t2, K, sX[le], A, B, C);
   const TC (&X)[8][3] = sX[le];
+  TC Gc[19];  // AFF: constant J, adj J, det J of the element
+  if (AFF) {
+    const TC xi[3] = {TC(0.5), TC(0.5), TC(0.5)};
+    TC J[3][3], Aj[3][3];
+    trilinear_jacobian(X, xi, J);
+    adj3(J, Aj);
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int cc = 0; cc < 3; ++cc) {
+        Gc[3 * r + cc] = J[r][cc];
+        Gc[9 + 3 * r + cc] = Aj[r][cc];
+      }
+    Gc[18] = det3(J);
+  }
   // faces (each call synchronises before touching shared buffers)
-  face_term<N, 0, TC, TIN>(m, T, x, e, ex, ey, ez, X, sXn[le], K, t1, t2, C, sF[le], act, 0);
-  face_term<N, 0, TC, TIN>(m, T, x, e, ex, ey, ez, X, sXn[le], K, t1, t2, C, sF[le], act, 1);
+  face_term<N, 0, TC, TIN, false, AFF>(m, T, x, e, ex, ey, ez, X, sXn[le], K, t1, t2, C, sF[le], act, 0, Gc);
+  face_term<N, 0, TC, TIN, false, AFF>(m, T, x, e, ex, ey, ez, X, sXn[le], K, t1, t2, C, sF[le], act, 1, Gc);
   __syncthreads();
-  face_term<N, 1, TC, TIN>(m, T, x, e, ex, ey, ez, X, sXn[le], K, t1, t2, C, sF[le], act, 0);
-  face_term<N, 1, TC, TIN>(m, T, x, e, ex, ey, ez, X, sXn[le], K, t1, t2, C, sF[le], act, 1);
+  face_term<N, 1, TC, TIN, false, AFF>(m, T, x, e, ex, ey, ez, X, sXn[le], K, t1, t2, C, sF[le], act, 0, Gc);
+  face_term<N, 1, TC, TIN, false, AFF>(m, T, x, e, ex, ey, ez, X, sXn[le], K, t1, t2, C, sF[le], act, 1, Gc);
   __syncthreads();
-  face_term<N, 2, TC, TIN>(m, T, x, e, ex, ey, ez, X, sXn[le], K, t1, t2, C, sF[le], act, 0);
-  face_term<N, 2, TC, TIN>(m, T, x, e, ex, ey, ez, X, sXn[le], K, t1, t2, C, sF[le], act, 1);
+  face_term<N, 2, TC, TIN, false, AFF>(m, T, x, e, ex, ey, ez, X, sXn[le], K, t1, t2, C, sF[le], act, 0, Gc);
+  face_term<N, 2, TC, TIN, false, AFF>(m, T, x, e, ex, ey, ez, X, sXn[le], K, t1, t2, C, sF[le], act, 1, Gc);
   __syncthreads();
   double part = 0.0;
   if (act) {
@@ -630,8 +681,12 @@ template <int N, typename TIN, typename TOUT, typename TC, bool DOT>
 static hipError_t run_tri(const MeshArgs<TC>& m, const void* x, void* y, double* partials, CgState* st, int par,
                           const int* skip, hipStream_t s) {
   const int64_t nb = element_blocks(N, m.E);
-  hipLaunchKernelGGL((k_apply_trilinear<N, TIN, TOUT, TC, DOT>), dim3((unsigned)nb), dim3(kBlock), 0, s, m,
-                     (const TIN*)x, (TOUT*)y, partials, skip);
+  if (m.affg)
+    hipLaunchKernelGGL((k_apply_trilinear<N, TIN, TOUT, TC, DOT, true>), dim3((unsigned)nb), dim3(kBlock), 0, s, m,
+                       (const TIN*)x, (TOUT*)y, partials, skip);
+  else
+    hipLaunchKernelGGL((k_apply_trilinear<N, TIN, TOUT, TC, DOT, false>), dim3((unsigned)nb), dim3(kBlock), 0, s, m,
+                       (const TIN*)x, (TOUT*)y, partials, skip);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !DOT) return e;
   return launch_finish_dot(partials, nb, st, par, s);
