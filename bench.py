@@ -36,7 +36,8 @@ FP32_PEAK_TFS = 157.3
 
 # pure FP64 PCG, then the FP64 defect correction with FP32 / BF16 inner solves,
 # restarted per correction or keeping the search direction
-CG_VARIANTS = (("f64", "restart"), ("f32", "restart"), ("bf16", "restart"), ("f32", "keep"), ("bf16", "keep"))
+CG_VARIANTS = (("f64", "restart"), ("f32", "restart"), ("bf16", "restart"), ("f32", "keep"), ("bf16", "keep"),
+               ("f64", "single_reduction"))
 
 
 def log(msg: str):
@@ -268,9 +269,10 @@ def main():
             torch.sin(math.pi * xq[:, 2])
         b = op.load_vector(fq.contiguous())
         for prec, mode in CG_VARIANTS:
-            op.cg_solve(b, prec_inner=prec, rtol=1e-10, dc_mode=mode)  # warm
-            u, info = op.cg_solve(b, prec_inner=prec, rtol=1e-10, dc_mode=mode)
-            tag = prec if prec == "f64" else f"{prec}_{mode}"
+            kw = {"variant": "single_reduction"} if mode == "single_reduction" else {"dc_mode": mode}
+            op.cg_solve(b, prec_inner=prec, rtol=1e-10, **kw)  # warm
+            u, info = op.cg_solve(b, prec_inner=prec, rtol=1e-10, **kw)
+            tag = (prec if mode == "restart" else f"{prec}_{mode}") if prec == "f64" else f"{prec}_{mode}"
             extras[f"cg_{tag}_q3_32"] = info
             log(f"cg {tag} q3_32: {info}")
         del u, b, fq, xq
@@ -314,12 +316,13 @@ def main():
         torch.cuda.empty_cache()
         b3 = dev(I.uniform_vector(op3.ndof, seed=I.S_B))
         for prec, mode in CG_VARIANTS:
-            op3.cg_solve(b3, prec_inner=prec, rtol=1e-10, dc_mode=mode, maxit=30)  # warm
-            u3, info = op3.cg_solve(b3, prec_inner=prec, rtol=1e-10, dc_mode=mode)
-            tag = prec if prec == "f64" else f"{prec}_{mode}"
+            kw = {"variant": "single_reduction"} if mode == "single_reduction" else {"dc_mode": mode}
+            op3.cg_solve(b3, prec_inner=prec, rtol=1e-10, maxit=30, **kw)  # warm
+            u3, info = op3.cg_solve(b3, prec_inner=prec, rtol=1e-10, **kw)
+            tag = (prec if mode == "restart" else f"{prec}_{mode}") if prec == "f64" else f"{prec}_{mode}"
             extras[f"cg_{tag}_{wl3}"] = info
             log(f"cg {tag} {wl3}: {info}")
-            if prec == "f64":
+            if tag == "f64":
                 u64 = u3
             else:
                 extras[f"cg_{tag}_{wl3}"]["rel_diff_vs_f64_solution"] = float(

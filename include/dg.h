@@ -145,6 +145,14 @@ int dg_load_vector(dg_ctx* ctx, const double* fq, double* b, void* stream);
  *                 after an inner breakdown. */
 enum dg_dc_mode { DG_DC_RESTART = 0, DG_DC_KEEP = 1 };
 
+/* DG_CG_STANDARD: Alg. "PCG" of Sec. 2.4 with the norm check merged into the
+ * <z, r> reduction (two reductions per iteration).  DG_CG_SINGLE_REDUCTION:
+ * the same iterates (up to rounding) from the single-reduction recurrences of
+ * Chronopoulos and Gear cited in Sec. 2.4 (s = A p carried by recurrence, w = A z
+ * applied; one reduction of {<r, z>, <r, r>, <z, w>} per iteration, two more
+ * streamed vectors).  FP64 solves only. */
+enum dg_cg_variant { DG_CG_STANDARD = 0, DG_CG_SINGLE_REDUCTION = 1 };
+
 typedef struct {
   int prec_inner;     /* DG_F64: FP64 PCG.  DG_F32 / DG_BF16: FP64 defect correction  *
                        * whose inner PCG runs on FP32 vectors with that apply          */
@@ -157,6 +165,7 @@ typedef struct {
   int check_every;    /* host looks at the device convergence flag every this many     *
                        * iterations (>= 1; <= 0: default 8)                            */
   int dc_mode;        /* enum dg_dc_mode (mixed precision only; must be valid always)  */
+  int cg_variant;     /* enum dg_cg_variant (prec_inner DG_F64 only for the second)   */
 } dg_cg_opts;
 
 typedef struct {

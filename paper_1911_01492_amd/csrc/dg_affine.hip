@@ -681,7 +681,7 @@ static hipError_t run_apply(const MeshArgs<TC>& m, const void* x, void* y, doubl
   hipLaunchKernelGGL((k_apply_affine<N, TIN, TOUT, TC, TRANS, DOT>), dim3((unsigned)nb), dim3(apply_block(N)), 0, s, m,
                      (const TIN*)x, (TOUT*)y, partials, skip);
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess || !DOT) return e;
+  if (e != hipSuccess || !DOT || st == nullptr) return e;  // st == nullptr: partials only
   return launch_finish_dot(partials, nb, st, par, s);
 }
 

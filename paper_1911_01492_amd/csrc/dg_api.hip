@@ -40,6 +40,7 @@ struct dg_ctx {
   double* dinv64;
   float* dinv32;
   double *r64, *p64, *q64;
+  double *z64, *s64, *w64;   // single-reduction CG
   float *r32, *d32, *p32, *q32;
   uint16_t* p16;
   double* partials;
@@ -252,7 +253,7 @@ void tables_to_f32(const Tables<double>& a, Tables<float>& b) {
 // ------------------------------------------------------------------ workspace
 struct Layout {
   size_t tab64, tab32, K64, K32, G64, G32, R64, R32, vert64, vert32, dinv64, dinv32, r64, p64, q64, r32, d32, p32,
-      q32, p16, partials, st, total;
+      q32, p16, z64, s64, w64, partials, st, total;
 };
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
@@ -304,6 +305,9 @@ Layout layout(const dg_mesh_desc* m) {
   L.p32 = take(nd * sizeof(float));
   L.q32 = take(nd * sizeof(float));
   L.p16 = take(nd * sizeof(uint16_t));
+  L.z64 = take(nd * sizeof(double));
+  L.s64 = take(nd * sizeof(double));
+  L.w64 = take(nd * sizeof(double));
   const int64_t nb = std::max<int64_t>(std::max<int64_t>(element_blocks(n, E), vec_blocks(nd)),
                                        affine_tiles(n, m->nx, m->ny, m->nz));
   L.partials = take((size_t)nb * 3 * sizeof(double));
@@ -372,12 +376,13 @@ MeshArgs<float> args32(const dg_ctx* c) {
 // dot != 0: <x, A x> into st->pq (st must then be given; par selects rho for the
 // breakdown check)
 hipError_t apply_any(dg_ctx* c, int prec, int trans, int dot, const void* x, void* y, CgState* st, int par,
-                     const int* skip, hipStream_t s) {
+                     const int* skip, hipStream_t s, double* partials = nullptr) {
   const MeshArgs<double> m64 = args64(c);
   const MeshArgs<float> m32 = args32(c);
+  double* part = partials ? partials : c->partials;
   if (c->trilinear)
-    return launch_apply_trilinear(c->n, prec, trans, dot, m64, m32, x, y, c->partials, st, par, skip, s);
-  return launch_apply_affine(c->n, prec, trans, dot, m64, m32, x, y, c->partials, st, par, skip, s);
+    return launch_apply_trilinear(c->n, prec, trans, dot, m64, m32, x, y, part, st, par, skip, s);
+  return launch_apply_affine(c->n, prec, trans, dot, m64, m32, x, y, part, st, par, skip, s);
 }
 
 hipError_t coef_setup(dg_ctx* c, const double* theta, hipStream_t s) {
@@ -473,6 +478,9 @@ int dg_setup(const dg_mesh_desc* mesh, dg_ctx** out, void* stream) {
   c->p32 = (float*)(w + L.p32);
   c->q32 = (float*)(w + L.q32);
   c->p16 = (uint16_t*)(w + L.p16);
+  c->z64 = (double*)(w + L.z64);
+  c->s64 = (double*)(w + L.s64);
+  c->w64 = (double*)(w + L.w64);
   c->partials = (double*)(w + L.partials);
   c->st = (CgState*)(w + L.st);
   hipStream_t s = (hipStream_t)stream;
@@ -639,6 +647,47 @@ int pcg64(dg_ctx* c, const dg_cg_opts* o, const double* b, double* x, int maxit,
   return DG_OK;
 }
 
+// Single-reduction PCG in FP64 (Chronopoulos-Gear recurrences): per iteration
+// one fused vector kernel, the apply w = A z with <z, w>, and one finish over
+// both partial sets (the other sums of Alg. PCG are carried by recurrences).
+int pcg64_single(dg_ctx* c, const dg_cg_opts* o, const double* b, double* x, int maxit, int& iters, bool& broke,
+                 hipStream_t s) {
+  const int64_t n = c->ndof;
+  const double* dinv = o->precond == DG_PC_JACOBI ? c->dinv64 : nullptr;
+  CgState* st = &c->st[0];
+  const int check = o->check_every > 0 ? o->check_every : 8;
+  const int64_t nvb = vec_blocks(n);
+  double* partA = c->partials;             // <r, z>, <r, r> of the update (2 per vector block)
+  double* partB = c->partials + 2 * nvb;   // <z, w> of the apply
+  const int64_t nbB = c->trilinear ? element_blocks(c->n, c->E) : affine_tiles(c->n, c->desc.nx, c->desc.ny,
+                                                                                c->desc.nz);
+  HIP_TRY(c, apply_any(c, DG_F64, o->transpose, 0, x, c->q64, nullptr, 0, nullptr, s));
+  // r = b - A x0, z = Dinv r (into z), gamma = <r, z>, <r, r>, <b, b>
+  HIP_TRY(c, (launch_cg_init<double, double, double, double>(n, b, c->q64, c->r64, c->z64, dinv, o->rtol, st,
+                                                            c->partials, s)));
+  HIP_TRY(c, hipMemsetAsync(c->p64, 0, n * sizeof(double), s));
+  HIP_TRY(c, hipMemsetAsync(c->s64, 0, n * sizeof(double), s));
+  HIP_TRY(c, apply_any(c, DG_F64, o->transpose, 1, c->z64, c->w64, nullptr, 0, &st->done, s, partB));
+  HIP_TRY(c, launch_cg2_finish(partA, nvb, partB, nbB, st, 0, s));
+  CgState hs;
+  int rc = read_state(c, 0, hs, s);
+  if (rc != DG_OK) return rc;
+  int it = 0;
+  while (!hs.done && it < maxit) {
+    const int chunk = std::min(check, maxit - it);
+    for (int j = 0; j < chunk; ++j, ++it) {
+      HIP_TRY(c, launch_cg2_update(n, x, c->r64, c->z64, c->p64, c->s64, c->w64, dinv, st, partA, s));
+      HIP_TRY(c, apply_any(c, DG_F64, o->transpose, 1, c->z64, c->w64, nullptr, 0, &st->done, s, partB));
+      HIP_TRY(c, launch_cg2_finish(partA, nvb, partB, nbB, st, 1, s));
+    }
+    rc = read_state(c, 0, hs, s);
+    if (rc != DG_OK) return rc;
+  }
+  iters = hs.iters;
+  broke = hs.breakdown != 0;
+  return DG_OK;
+}
+
 int true_residual(dg_ctx* c, int transpose, const double* b, const double* x, double& rel, hipStream_t s) {
   HIP_TRY(c, apply_any(c, DG_F64, transpose, 0, x, c->q64, nullptr, 0, nullptr, s));
   HIP_TRY(c, launch_resid_norm(c->ndof, b, c->q64, &c->st[0], c->partials, s));
@@ -768,6 +817,10 @@ int dg_cg_solve(dg_ctx* c, const dg_cg_opts* o, const double* b, double* x, dg_c
     return fail(c, DG_ERR_UNSUPPORTED, "unknown inner precision");
   if (o->precond != DG_PC_NONE && o->precond != DG_PC_JACOBI) return fail(c, DG_ERR_ARG, "unknown preconditioner");
   if (o->dc_mode != DG_DC_RESTART && o->dc_mode != DG_DC_KEEP) return fail(c, DG_ERR_ARG, "unknown dc_mode");
+  if (o->cg_variant != DG_CG_STANDARD && o->cg_variant != DG_CG_SINGLE_REDUCTION)
+    return fail(c, DG_ERR_ARG, "unknown cg_variant");
+  if (o->cg_variant == DG_CG_SINGLE_REDUCTION && o->prec_inner != DG_F64)
+    return fail(c, DG_ERR_UNSUPPORTED, "the single-reduction variant is built for FP64 solves only");
   if (!(o->rtol > 0) || o->maxit < 1) return fail(c, DG_ERR_ARG, "rtol must be > 0 and maxit >= 1");
   if (!aligned(b, 8) || !aligned(x, 8)) return fail(c, DG_ERR_ARG, "misaligned b or x");
   hipStream_t s = (hipStream_t)stream;
@@ -782,7 +835,8 @@ int dg_cg_solve(dg_ctx* c, const dg_cg_opts* o, const double* b, double* x, dg_c
     // restarted from the current iterate if the check fails
     for (int attempt = 0;; ++attempt) {
       int its = 0;
-      rc = pcg64(c, o, b, x, o->maxit - total, its, broke, s);
+      rc = o->cg_variant == DG_CG_SINGLE_REDUCTION ? pcg64_single(c, o, b, x, o->maxit - total, its, broke, s)
+                                                   : pcg64(c, o, b, x, o->maxit - total, its, broke, s);
       if (rc != DG_OK) return rc;
       total += its;
       rc = true_residual(c, o->transpose, b, x, rel, s);

@@ -20,7 +20,9 @@ struct CgState {
   int iters;        // iterations completed
   int xpend;        // 1 after an update: the deferred x += lambda p of that iteration is due
   unsigned counter; // arrival counter of the grid reductions (reset by the last block)
-  unsigned pad1[3];
+  unsigned pad1;
+  double alpha;     // single-reduction CG: step length and direction coefficient of the next update
+  double beta;
 };
 
 constexpr int kMaxVecBlocks = 2048;
@@ -74,6 +76,13 @@ hipError_t launch_cg_pupdate(int64_t n, TX* x, const TV* r, TP* p, const TD* din
 hipError_t launch_dc_residual(int64_t n, const double* b, const double* q, float* r32, CgState* st,
                               double* partials, hipStream_t s);
 hipError_t launch_dc_update(int64_t n, double* x, float* d, hipStream_t s);
+// single-reduction (Chronopoulos-Gear) PCG in FP64: fused update of p, s, x, r, z
+// with the partials {<r, z>, <r, r>}, and the finish over these and the <z, w>
+// partials of the apply (mode 0: after the first apply, 1: every iteration)
+hipError_t launch_cg2_update(int64_t n, double* x, double* r, double* z, double* p, double* s, const double* w,
+                             const double* dinv, const CgState* st, double* partials, hipStream_t st_);
+hipError_t launch_cg2_finish(const double* partA, int64_t nbA, const double* partB, int64_t nbB, CgState* st,
+                             int mode, hipStream_t s);
 hipError_t launch_dc_replace(int64_t n, const double* b, const double* q, const float* dinv, float* r32,
                              CgState* st, int par, double rtol, double reduction, double* partials,
                              hipStream_t s);

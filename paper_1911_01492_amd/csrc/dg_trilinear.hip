@@ -688,7 +688,7 @@ static hipError_t run_tri(const MeshArgs<TC>& m, const void* x, void* y, double*
     hipLaunchKernelGGL((k_apply_trilinear<N, TIN, TOUT, TC, DOT, false>), dim3((unsigned)nb), dim3(kBlock), 0, s, m,
                        (const TIN*)x, (TOUT*)y, partials, skip);
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess || !DOT) return e;
+  if (e != hipSuccess || !DOT || st == nullptr) return e;  // st == nullptr: partials only
   return launch_finish_dot(partials, nb, st, par, s);
 }
 

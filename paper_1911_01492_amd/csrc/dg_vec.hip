@@ -193,6 +193,72 @@ __global__ __launch_bounds__(kBlock) void k_resid_norm(int64_t n, const double* 
   store_partials<2>(mine, partials, blockIdx.x);
 }
 
+// Single-reduction PCG (Chronopoulos-Gear form of the CG recurrences): with
+// alpha, beta from the previous finish,
+//   p = z + beta p,  s = w + beta s  (s = A p by recurrence),  x += alpha p,
+//   r -= alpha s,  z = Dinv r;  partials {<r, z>, <r, r>}.
+__global__ __launch_bounds__(kBlock) void k_cg2_update(int64_t n, double* __restrict__ x, double* __restrict__ r,
+                                                       double* __restrict__ z, double* __restrict__ p,
+                                                       double* __restrict__ s, const double* __restrict__ w,
+                                                       const double* __restrict__ dinv, const CgState* st,
+                                                       double* partials) {
+  __shared__ double red[kBlock / 64];
+  if (st->done) return;
+  const double al = st->alpha, be = st->beta;
+  double zr = 0.0, rr = 0.0;
+  DG_VEC_LOOP(i, k, n) {
+    const double pi = z[i] + be * p[i];
+    const double si = w[i] + be * s[i];
+    p[i] = pi;
+    s[i] = si;
+    x[i] += al * pi;
+    const double ri = r[i] - al * si;
+    r[i] = ri;
+    const double zi = dinv ? dinv[i] * ri : ri;
+    z[i] = zi;
+    zr += zi * ri;
+    rr += ri * ri;
+  }
+  const double mine[2] = {block_sum<kBlock>(zr, red), block_sum<kBlock>(rr, red)};
+  store_partials<2>(mine, partials, blockIdx.x);
+}
+
+// mode 0 (after the first apply): delta = <z, w> (partB) -> alpha = gamma / delta,
+// beta = 0 (gamma = rho[0] from the initial residual).  mode 1: gamma' = <r, z>,
+// <r, r> (partA) and delta = <z, w> (partB): iteration count, convergence on
+// <r, r>, beta = gamma' / gamma, alpha = gamma' / (delta - beta gamma' / alpha).
+__global__ __launch_bounds__(1024) void k_cg2_finish(const double* partA, int64_t nbA, const double* partB,
+                                                     int64_t nbB, CgState* st, int mode) {
+  if (st->done) return;
+  double tA[2] = {0.0, 0.0}, tB[1];
+  if (mode == 1) sum_partials<2, 1024>(partA, nbA, tA);
+  __syncthreads();
+  sum_partials<1, 1024>(partB, nbB, tB);
+  if (threadIdx.x != 0) return;
+  const double delta = tB[0];
+  double gam, be, den;
+  if (mode == 0) {
+    gam = st->rho[0];
+    be = 0.0;
+    den = delta;
+  } else {
+    gam = tA[0];
+    st->rr = tA[1];
+    st->iters += 1;
+    be = gam / st->rho[0];
+    den = delta - be * gam / st->alpha;
+    if (tA[1] <= st->tol2) st->done = 1;
+  }
+  const double al = gam / den;
+  st->rho[0] = gam;
+  st->alpha = al;
+  st->beta = be;
+  if (!st->done && (!(den > 0.0) || !finite_d(al) || !finite_d(be))) {
+    st->breakdown = 1;
+    st->done = 1;
+  }
+}
+
 // ---------------------------------------------------------------- finish kernels
 // mode: what the totals mean and which state fields they set
 enum FinishMode {
@@ -373,6 +439,17 @@ hipError_t launch_dc_replace(int64_t n, const double* b, const double* q, const 
   hipLaunchKernelGGL(k_dc_replace, dim3((unsigned)nb), dim3(kBlock), 0, s, n, b, q, dinv, r32, partials);
   DG_TRY(hipGetLastError());
   return finish<3, FIN_REPLACE>(partials, nb, st, par, rtol, s, reduction);
+}
+hipError_t launch_cg2_update(int64_t n, double* x, double* r, double* z, double* p, double* s, const double* w,
+                             const double* dinv, const CgState* st, double* partials, hipStream_t st_) {
+  hipLaunchKernelGGL(k_cg2_update, dim3((unsigned)vec_blocks(n)), dim3(kBlock), 0, st_, n, x, r, z, p, s, w, dinv, st,
+                     partials);
+  return hipGetLastError();
+}
+hipError_t launch_cg2_finish(const double* partA, int64_t nbA, const double* partB, int64_t nbB, CgState* st,
+                             int mode, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg2_finish, dim3(1), dim3(1024), 0, s, partA, nbA, partB, nbB, st, mode);
+  return hipGetLastError();
 }
 hipError_t launch_resid_norm(int64_t n, const double* b, const double* q, CgState* st, double* partials,
                              hipStream_t s) {

@@ -50,12 +50,14 @@ class MeshDesc(ctypes.Structure):
 
 
 DC_MODE = {"restart": 0, "keep": 1}
+CG_VARIANT = {"standard": 0, "single_reduction": 1}
 
 
 class CgOpts(ctypes.Structure):
     _fields_ = [("prec_inner", ctypes.c_int), ("precond", ctypes.c_int), ("transpose", ctypes.c_int),
                 ("rtol", ctypes.c_double), ("inner_rtol", ctypes.c_double), ("maxit", ctypes.c_int),
-                ("max_outer", ctypes.c_int), ("check_every", ctypes.c_int), ("dc_mode", ctypes.c_int)]
+                ("max_outer", ctypes.c_int), ("check_every", ctypes.c_int), ("dc_mode", ctypes.c_int),
+                ("cg_variant", ctypes.c_int)]
 
 
 class CgInfo(ctypes.Structure):
@@ -222,7 +224,7 @@ class DGOperator:
     def cg_solve(self, b: torch.Tensor, x: Optional[torch.Tensor] = None, prec_inner: str = "f64",
                  precond: str = "jacobi", rtol: float = 1e-10, maxit: int = 100000,
                  inner_rtol: float = 0.0, max_outer: int = 0, transpose: bool = False,
-                 check_every: int = 8, dc_mode: str = "restart", stream=None):
+                 check_every: int = 8, dc_mode: str = "restart", variant: str = "standard", stream=None):
         """Solve A x = b (A^T x = b).  Returns (x, info dict).
 
         prec_inner "f32" / "bf16" selects the FP64 defect correction; dc_mode
@@ -232,7 +234,7 @@ class DGOperator:
         self._vec(b, torch.float64)
         x = torch.zeros_like(b) if x is None else self._vec(x, torch.float64)
         o = CgOpts(PREC[prec_inner], PRECOND[precond], 1 if transpose else 0, rtol, inner_rtol, maxit,
-                   max_outer, check_every, DC_MODE[dc_mode])
+                   max_outer, check_every, DC_MODE[dc_mode], CG_VARIANT[variant])
         info = CgInfo()
         rc = lib().dg_cg_solve(self._h, ctypes.byref(o), _ptr(b), _ptr(x), ctypes.byref(info),
                                _stream(stream))

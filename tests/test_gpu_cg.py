@@ -88,17 +88,53 @@ def test_unpreconditioned_and_transposed(small):
         assert np.linalg.norm(bs - A @ host(x3)) <= 1.2e-10 * np.linalg.norm(bs)
 
 
+def test_single_reduction_variant(small):
+    """Chronopoulos-Gear recurrences (one reduction per iteration): the oracle's
+    residual and solution, iteration counts within a few of Alg. PCG, also on a
+    trilinear mesh and for the transposed solve."""
+    banner("cg single reduction")
+    m, A, op = small
+    b = _sine_rhs(op)
+    bs = host(b)
+    x0, i0 = op.cg_solve(b, rtol=1e-10)
+    x1, i1 = op.cg_solve(b, rtol=1e-10, variant="single_reduction")
+    x2, i2 = op.cg_solve(b, rtol=1e-10, variant="single_reduction", transpose=True, precond="none")
+    print(i0, i1, i2)
+    for x, info in ((x1, i1), (x2, i2)):
+        assert info["status"] == DG_OK
+        assert np.linalg.norm(bs - A @ host(x)) <= 1.2e-10 * np.linalg.norm(bs)
+    x_ref, it, rr = O.pcg(A, bs, rtol=1e-13)
+    assert rel_l2(host(x1), x_ref) <= 1e-7
+    assert abs(i1["iters"] - i0["iters"]) <= 0.05 * i0["iters"] + 2
+    from tests.test_gpu_trilinear import box_vertices
+    V = box_vertices(3, 3, 3, seed=8)
+    th = I.theta(27, seed=9)
+    mt = O.Mesh(3, 3, 3, 2, theta=th, vertices=V)
+    At = O.assemble(mt)
+    opt = DGOperator(3, 3, 3, 2, "dirichlet", theta=dev(th), vertices=dev(V))
+    bt = I.uniform_vector(mt.ndof, seed=10)
+    xt, it_ = opt.cg_solve(dev(bt), rtol=1e-10, variant="single_reduction")
+    assert it_["status"] == DG_OK
+    assert np.linalg.norm(bt - At @ host(xt)) <= 1.2e-10 * np.linalg.norm(bt)
+
+
 def test_dc_mode_argument_checked(small):
     from paper_1911_01492_amd.dg import DG_ERR_ARG, CgInfo, CgOpts, _ptr, _stream, lib
     import ctypes
     m, A, op = small
     b = _sine_rhs(op)
     x = torch.zeros_like(b)
-    o = CgOpts(1, 1, 0, 1e-10, 0.0, 100, 0, 8, 7)
+    o = CgOpts(1, 1, 0, 1e-10, 0.0, 100, 0, 8, 7, 0)
     info = CgInfo()
     rc = lib().dg_cg_solve(op._h, ctypes.byref(o), _ptr(b), _ptr(x), ctypes.byref(info), _stream(None))
     assert rc == DG_ERR_ARG
     assert b"dc_mode" in lib().dg_last_error(op._h)
+    o = CgOpts(0, 1, 0, 1e-10, 0.0, 100, 0, 8, 0, 5)
+    assert lib().dg_cg_solve(op._h, ctypes.byref(o), _ptr(b), _ptr(x), ctypes.byref(info), _stream(None)) == DG_ERR_ARG
+    from paper_1911_01492_amd.dg import DG_ERR_UNSUPPORTED
+    o = CgOpts(1, 1, 0, 1e-10, 0.0, 100, 0, 8, 0, 1)
+    assert lib().dg_cg_solve(op._h, ctypes.byref(o), _ptr(b), _ptr(x), ctypes.byref(info),
+                             _stream(None)) == DG_ERR_UNSUPPORTED
 
 
 def test_warm_start_and_limits(small):
@@ -125,11 +161,13 @@ def test_full_size_exact_solution():
     N, k = 32, 3
     op = DGOperator(N, N, N, k, "dirichlet")
     b = _sine_rhs(op)
-    for prec, mode in (("f64", "restart"), ("f32", "restart"), ("f32", "keep"), ("bf16", "keep")):
-        x, info = op.cg_solve(b, prec_inner=prec, rtol=1e-10, dc_mode=mode)
-        print(prec, mode, info)
+    for prec, mode, var in (("f64", "restart", "standard"), ("f64", "restart", "single_reduction"),
+                            ("f32", "restart", "standard"), ("f32", "keep", "standard"),
+                            ("bf16", "keep", "standard")):
+        x, info = op.cg_solve(b, prec_inner=prec, rtol=1e-10, dc_mode=mode, variant=var)
+        print(prec, mode, var, info)
         assert info["status"] == DG_OK
         x_ex = O.fast_diag_solve(N, N, N, k, O.DIRICHLET, host(b))
         err = rel_l2(host(x), x_ex)
-        print(f"cg {prec} {mode} 32^3 Q3 K=1: solution rel err vs exact solve {err:.3e}")
+        print(f"cg {prec} {mode} {var} 32^3 Q3 K=1: solution rel err vs exact solve {err:.3e}")
         assert err <= 1e-7
