@@ -77,3 +77,27 @@ def test_setup_rejects_missing_workspace():
     assert L.dg_setup(ctypes.byref(desc), ctypes.byref(h), None) == dg.DG_ERR_ARG
     assert not h.value
     assert L.dg_setup(None, ctypes.byref(h), None) == dg.DG_ERR_ARG
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """The ctypes structures of the binding have the field offsets and sizes of
+    the C structures in include/dg.h (compiled here with gcc)."""
+    structs = {"dg_mesh_desc": dg.MeshDesc, "dg_cg_opts": dg.CgOpts, "dg_cg_info": dg.CgInfo}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "dg.h"', "int main(void) {"]
+    for cname, cls in structs.items():
+        lines.append(f'  printf("{cname} sizeof %zu\\n", sizeof({cname}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = {}
+    for line in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.splitlines():
+        cname, key, val = line.split()
+        got[(cname, key)] = int(val)
+    for cname, cls in structs.items():
+        assert got[(cname, "sizeof")] == ctypes.sizeof(cls), cname
+        for fname, _ in cls._fields_:
+            assert got[(cname, fname)] == getattr(cls, fname).offset, (cname, fname)
