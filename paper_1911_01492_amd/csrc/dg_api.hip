@@ -195,6 +195,42 @@ struct Bary {
   }
 };
 
+// Even-odd halves of an n x n matrix A (row-major, stride n) with
+// A[n-1-i][n-1-j] = sign A[i][j]; false if A lacks that symmetry (beyond
+// rounding), which would make the halves describe another matrix.
+bool even_odd(int n, const std::vector<double>& A, int sign, EvenOdd<double>& eo) {
+  double amax = 0.0;
+  for (double a : A) amax = std::max(amax, std::fabs(a));
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j)
+      if (std::fabs(A[(n - 1 - i) * n + (n - 1 - j)] - sign * A[i * n + j]) > 1e-13 * amax) return false;
+  const int h = n / 2, m = h;
+  for (int i = 0; i < h; ++i) {
+    for (int j = 0; j < h; ++j) {
+      eo.E[i * kMaxH + j] = 0.5 * (A[i * n + j] + A[i * n + (n - 1 - j)]);
+      eo.O[i * kMaxH + j] = 0.5 * (A[i * n + j] - A[i * n + (n - 1 - j)]);
+    }
+    if (n & 1) {
+      eo.C[i] = A[i * n + m];
+      eo.R[i] = A[m * n + i];
+    }
+  }
+  if (n & 1) eo.mm = A[m * n + m];
+  return true;
+}
+
+void even_odd_to_f32(const EvenOdd<double>& a, EvenOdd<float>& b) {
+  for (int i = 0; i < kMaxH * kMaxH; ++i) {
+    b.E[i] = (float)a.E[i];
+    b.O[i] = (float)a.O[i];
+  }
+  for (int i = 0; i < kMaxH; ++i) {
+    b.C[i] = (float)a.C[i];
+    b.R[i] = (float)a.R[i];
+  }
+  b.mm = (float)a.mm;
+}
+
 bool build_tables(int n, Tables<double>& T) {
   std::memset(&T, 0, sizeof(T));
   std::vector<double> gll, gx, gw;
@@ -231,7 +267,14 @@ bool build_tables(int n, Tables<double>& T) {
     T.gw[i] = gw[i];
     T.gx[i] = gx[i];
   }
-  return true;
+  std::vector<double> Bt((size_t)n * n), Dgt((size_t)n * n);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      Bt[i * n + j] = B[j * n + i];
+      Dgt[i * n + j] = Dg[j * n + i];
+    }
+  return even_odd(n, B, 1, T.eB) && even_odd(n, Bt, 1, T.eBt) && even_odd(n, Dg, -1, T.eDg) &&
+         even_odd(n, Dgt, -1, T.eDgt);
 }
 
 void tables_to_f32(const Tables<double>& a, Tables<float>& b) {
@@ -248,6 +291,10 @@ void tables_to_f32(const Tables<double>& a, Tables<float>& b) {
     b.gw[i] = (float)a.gw[i];
     b.gx[i] = (float)a.gx[i];
   }
+  even_odd_to_f32(a.eB, b.eB);
+  even_odd_to_f32(a.eBt, b.eBt);
+  even_odd_to_f32(a.eDg, b.eDg);
+  even_odd_to_f32(a.eDgt, b.eDgt);
 }
 
 // ------------------------------------------------------------------ workspace

@@ -14,6 +14,23 @@ namespace dg {
 constexpr int kMaxN = 8;  // k <= 7
 
 // 1D reference operators on [0,1] (n GLL nodes, n Gauss points).
+// An n x n matrix A with A[n-1-i][n-1-j] = SIGN A[i][j] (centro-symmetric,
+// SIGN = +1, or centro-antisymmetric, SIGN = -1), as the 1D tables on the
+// symmetric Gauss-Lobatto and Gauss points are, stored by its even-odd halves
+// (h = n / 2; m = h is the middle index when n is odd):
+//   E[i][j] = (A[i][j] + A[i][n-1-j]) / 2,  O[i][j] = (A[i][j] - A[i][n-1-j]) / 2  (i, j < h),
+//   C[i] = A[i][m],  R[j] = A[m][j],  mm = A[m][m]                                 (n odd).
+// A contraction then needs half the table and about 3/4 of the operations.
+constexpr int kMaxH = kMaxN / 2;
+template <typename T>
+struct EvenOdd {
+  T E[kMaxH * kMaxH];
+  T O[kMaxH * kMaxH];
+  T C[kMaxH];
+  T R[kMaxH];
+  T mm;
+};
+
 template <typename T>
 struct Tables {
   T M[kMaxN * kMaxN];   // mass       M_ij = sum_q w_q l_i(x_q) l_j(x_q)
@@ -25,6 +42,8 @@ struct Tables {
   T d1[kMaxN];          // l_i'(1)
   T gw[kMaxN];          // Gauss weights on [0,1]
   T gx[kMaxN];          // Gauss points on [0,1]
+  EvenOdd<T> eB, eBt;   // B and B^T (centro-symmetric)
+  EvenOdd<T> eDg, eDgt; // Dg and Dg^T (centro-antisymmetric)
 };
 
 // Mesh data passed by value to the kernels.

@@ -38,6 +38,56 @@ __device__ __forceinline__ void contract(const TC* A, const TC (&a)[N], TC (&out
   }
 }
 
+// Synchronisation of the n^2 threads of one element: every exchange through
+// LDS in these kernels stays inside one element (its tiles, face buffers and
+// corner slots).  When n^2 divides 64 an element lies inside one wavefront,
+// whose lanes execute together and whose LDS operations complete in order, so
+// only the compiler has to be kept from moving LDS accesses across this
+// point; otherwise the element may span two wavefronts and the workgroup
+// barrier is used.
+template <int N>
+__device__ __forceinline__ void elem_sync() {
+  if constexpr (64 % (N * N) == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
+// out = A a for A given by its even-odd halves (SIGN: A[n-1-i][n-1-j] = SIGN A[i][j]):
+// with a_e = a_j + a_{n-1-j}, a_o = a_j - a_{n-1-j} (j < n/2),
+//   P_i = E a_e (+ C_i a_m), Q_i = O a_o,  out_i = P_i + Q_i,  out_{n-1-i} = SIGN (P_i - Q_i),
+// and for odd n the middle row R a_e + mm a_m (SIGN = +1) or R a_o (SIGN = -1).
+template <int N, typename TC, int SIGN>
+__device__ __forceinline__ void contract_eo(const EvenOdd<TC>& A, const TC (&a)[N], TC (&out)[N]) {
+  constexpr int H = N / 2;
+  TC ae[H], ao[H];
+#pragma unroll
+  for (int j = 0; j < H; ++j) {
+    ae[j] = a[j] + a[N - 1 - j];
+    ao[j] = a[j] - a[N - 1 - j];
+  }
+#pragma unroll
+  for (int i = 0; i < H; ++i) {
+    TC P = (N & 1) ? A.C[i] * a[H] : TC(0), Q = TC(0);
+#pragma unroll
+    for (int j = 0; j < H; ++j) {
+      P += A.E[i * kMaxH + j] * ae[j];
+      Q += A.O[i * kMaxH + j] * ao[j];
+    }
+    out[i] = P + Q;
+    out[N - 1 - i] = SIGN > 0 ? P - Q : Q - P;
+  }
+  if (N & 1) {
+    TC s = SIGN > 0 ? A.mm * a[H] : TC(0);
+#pragma unroll
+    for (int j = 0; j < H; ++j) s += A.R[j] * (SIGN > 0 ? ae[j] : ao[j]);
+    out[H] = s;
+  }
+}
+
 template <typename TC>
 __device__ __forceinline__ void corner_of(const MeshArgs<TC>& m, int64_t e, int c, int a, TC& out) {
   const int ex = (int)(e % m.nx), ey = (int)((e / m.nx) % m.ny), ez = (int)(e / ((int64_t)m.nx * m.ny));
@@ -82,14 +132,14 @@ __device__ void face_term(const MeshArgs<TC>& m, const Tables<TC>& T, const TIN*
       for (int i = 0; i < N; ++i) Gn += dN[i] * nl[i];
     }
   }
-  __syncthreads();  // face buffers free
+  elem_sync<N>();  // face buffers free
   if (act) {
     F[0][t] = Uo;
     F[1][t] = Go;
     F[2][t] = Un;
     F[3][t] = Gn;
   }
-  __syncthreads();
+  elem_sync<N>();
   if (act) {  // interpolation / derivative along t1 (axis ax)
     TC bu = 0, du = 0, bg = 0, bun = 0, dun = 0, bgn = 0;
 #pragma unroll
@@ -109,7 +159,7 @@ __device__ void face_term(const MeshArgs<TC>& m, const Tables<TC>& T, const TIN*
     F[8][t] = dun;
     F[9][t] = bgn;
   }
-  __syncthreads();
+  elem_sync<N>();
   TC P = 0, Ra = 0, Rb = 0, Rd = 0;
   if (act) {  // along t2 (axis bx): values at face Gauss point (qa, qb) = (t1, t2)
     TC uo = 0, gao = 0, gbo = 0, gdo = 0, un = 0, gan = 0, gbn = 0, gdn = 0;
@@ -148,9 +198,10 @@ __device__ void face_term(const MeshArgs<TC>& m, const Tables<TC>& T, const TIN*
     gro[D] = gdo;
     gro[ax] = gao;
     gro[bx] = gbo;
+    const TC ideto = TC(1) / deto;
     TC go[3];  // physical gradient, own side: adj^T gr / det
 #pragma unroll
-    for (int c = 0; c < 3; ++c) go[c] = (Ao[0][c] * gro[0] + Ao[1][c] * gro[1] + Ao[2][c] * gro[2]) / deto;
+    for (int c = 0; c < 3; ++c) go[c] = (Ao[0][c] * gro[0] + Ao[1][c] * gro[1] + Ao[2][c] * gro[2]) * ideto;
     const TC w = T.gw[t1] * T.gw[t2];
     const TC h = D == 0 ? m.hx : (D == 1 ? m.hy : m.hz);
     const TC sig = m.sig_hat / h;
@@ -164,14 +215,14 @@ __device__ void face_term(const MeshArgs<TC>& m, const Tables<TC>& T, const TIN*
       TC Jn[3][3], An[3][3];
       trilinear_jacobian(Xn, xin, Jn);
       adj3(Jn, An);
-      const TC detn = det3(Jn);
+      const TC idetn = TC(1) / det3(Jn);
       TC grn[3];
       grn[D] = gdn;
       grn[ax] = gan;
       grn[bx] = gbn;
       TC gn[3];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) gn[c] = (An[0][c] * grn[0] + An[1][c] * grn[1] + An[2][c] * grn[2]) / detn;
+      for (int c = 0; c < 3; ++c) gn[c] = (An[0][c] * grn[0] + An[1][c] * grn[1] + An[2][c] * grn[2]) * idetn;
       // n dS from T^-: the own element on the upper face, the neighbour on the lower face
       const TC (&Jm)[3][3] = s ? Jo : Jn;
       Nv[0] = Jm[1][c1] * Jm[2][c2] - Jm[2][c1] * Jm[1][c2];
@@ -184,7 +235,7 @@ __device__ void face_term(const MeshArgs<TC>& m, const Tables<TC>& T, const TIN*
       const TC Fq = TC(0.5) * gam * w * ((go[0] + gn[0]) * Nv[0] + (go[1] + gn[1]) * Nv[1] + (go[2] + gn[2]) * Nv[2]);
       const TC pen = sig * gam * area * w * Jq;
       P = s ? (pen - Fq) : (Fq - pen);
-      const TC cr = -TC(0.5) * gam * w * Jq / deto;
+      const TC cr = -TC(0.5) * gam * w * Jq * ideto;
       TC R[3];
 #pragma unroll
       for (int c = 0; c < 3; ++c) R[c] = cr * (Ao[c][0] * Nv[0] + Ao[c][1] * Nv[1] + Ao[c][2] * Nv[2]);
@@ -200,7 +251,7 @@ __device__ void face_term(const MeshArgs<TC>& m, const Tables<TC>& T, const TIN*
       const TC area = sqrt(Nv[0] * Nv[0] + Nv[1] * Nv[1] + Nv[2] * Nv[2]);
       const TC Kb = UNIT ? TC(1) : K;
       P = -Kb * w * (go[0] * Nv[0] + go[1] * Nv[1] + go[2] * Nv[2]) + sig * Kb * area * w * uo;
-      const TC cr = -Kb * w * uo / deto;
+      const TC cr = -Kb * w * uo * ideto;
       TC R[3];
 #pragma unroll
       for (int c = 0; c < 3; ++c) R[c] = cr * (Ao[c][0] * Nv[0] + Ao[c][1] * Nv[1] + Ao[c][2] * Nv[2]);
@@ -213,7 +264,7 @@ __device__ void face_term(const MeshArgs<TC>& m, const Tables<TC>& T, const TIN*
     F[2][t] = Rb;
     F[3][t] = Rd;
   }
-  __syncthreads();
+  elem_sync<N>();
   if (act) {  // transposed tangential operators, contraction over qb: thread (qa, b) = (t1, t2)
     TC xs = 0, ys = 0, zs = 0;
 #pragma unroll
@@ -227,7 +278,7 @@ __device__ void face_term(const MeshArgs<TC>& m, const Tables<TC>& T, const TIN*
     F[5][t2 * N + t1] = ys;
     F[6][t2 * N + t1] = zs;
   }
-  __syncthreads();
+  elem_sync<N>();
   if (act) {  // contraction over qa: thread (a, b) = (t1, t2) owns face node (a, b) of its line
     TC out = 0, z = 0;
 #pragma unroll
@@ -259,38 +310,38 @@ __device__ void tri_volume(const MeshArgs<TC>& m, const Tables<TC>& T, const TIN
     for (int q = t; q < 24; q += NN) corner_of(m, e, q / 3, q % 3, Xs[q / 3][q % 3]);
     glb_get<N, 2, TC, TIN>(x, e, t1, t2, uz);
     TC a[N];
-    contract<N, TC, false>(T.B, uz, a);  // phase Z: interpolate along z
+    contract_eo<N, TC, 1>(T.eB, uz, a);  // phase Z: interpolate along z
     lds_put<N, 2>(A, t1, t2, a);
   }
-  __syncthreads();
+  elem_sync<N>();
   const TC (&X)[8][3] = Xs;
   if (act) {  // phase Y
     TC a[N], b[N];
     lds_get<N, 1>(A, t1, t2, a);
-    contract<N, TC, false>(T.B, a, b);
+    contract_eo<N, TC, 1>(T.eB, a, b);
     lds_put<N, 1>(B, t1, t2, b);
   }
-  __syncthreads();
+  elem_sync<N>();
   if (act) {  // phase X: v and d/dxi_0
     TC a[N], v[N], d1[N];
     lds_get<N, 0>(B, t1, t2, a);
-    contract<N, TC, false>(T.B, a, v);
-    contract<N, TC, false>(T.Dg, v, d1);
+    contract_eo<N, TC, 1>(T.eB, a, v);
+    contract_eo<N, TC, -1>(T.eDg, v, d1);
     lds_put<N, 0>(A, t1, t2, v);
     lds_put<N, 0>(C, t1, t2, d1);
   }
-  __syncthreads();
+  elem_sync<N>();
   if (act) {  // phase Y': d/dxi_1
     TC v[N], d2[N];
     lds_get<N, 1>(A, t1, t2, v);
-    contract<N, TC, false>(T.Dg, v, d2);
+    contract_eo<N, TC, -1>(T.eDg, v, d2);
     lds_put<N, 1>(B, t1, t2, d2);
   }
-  __syncthreads();
+  elem_sync<N>();
   if (act) {  // phase Z': d/dxi_2, geometry, g = G gr, Dg_z^T g_2
     TC d1[N], d2[N], d3[N], wz[N], v[N];
     lds_get<N, 2>(A, t1, t2, v);
-    contract<N, TC, false>(T.Dg, v, d3);
+    contract_eo<N, TC, -1>(T.eDg, v, d3);
     lds_get<N, 2>(C, t1, t2, d1);
     lds_get<N, 2>(B, t1, t2, d2);
     const TC wq12 = T.gw[t1] * T.gw[t2] * K;
@@ -343,46 +394,46 @@ __device__ void tri_volume(const MeshArgs<TC>& m, const Tables<TC>& T, const TIN
       d2[q] = Gm[1][0] * a1 + Gm[1][1] * a2 + Gm[1][2] * a3;
       d3[q] = Gm[2][0] * a1 + Gm[2][1] * a2 + Gm[2][2] * a3;
     }
-    contract<N, TC, true>(T.Dg, d3, wz);
+    contract_eo<N, TC, -1>(T.eDgt, d3, wz);
 #pragma unroll
     for (int q = 0; q < N; ++q) wz[q] += v[q];
     lds_put<N, 2>(A, t1, t2, wz);
     lds_put<N, 2>(C, t1, t2, d1);
     lds_put<N, 2>(B, t1, t2, d2);
   }
-  __syncthreads();
+  elem_sync<N>();
   if (act) {  // phase Y'': += Dg_y^T g_1
     TC g2[N], w[N], r[N];
     lds_get<N, 1>(B, t1, t2, g2);
     lds_get<N, 1>(A, t1, t2, w);
-    contract<N, TC, true>(T.Dg, g2, r);
+    contract_eo<N, TC, -1>(T.eDgt, g2, r);
 #pragma unroll
     for (int i = 0; i < N; ++i) w[i] += r[i];
     lds_put<N, 1>(A, t1, t2, w);
   }
-  __syncthreads();
+  elem_sync<N>();
   if (act) {  // phase X'': += Dg_x^T g_0, then B_x^T
     TC g1[N], w[N], r[N], o[N];
     lds_get<N, 0>(C, t1, t2, g1);
     lds_get<N, 0>(A, t1, t2, w);
-    contract<N, TC, true>(T.Dg, g1, r);
+    contract_eo<N, TC, -1>(T.eDgt, g1, r);
 #pragma unroll
     for (int i = 0; i < N; ++i) w[i] += r[i];
-    contract<N, TC, true>(T.B, w, o);
+    contract_eo<N, TC, 1>(T.eBt, w, o);
     lds_put<N, 0>(A, t1, t2, o);
   }
-  __syncthreads();
+  elem_sync<N>();
   if (act) {  // phase Y''': B_y^T
     TC w[N], o[N];
     lds_get<N, 1>(A, t1, t2, w);
-    contract<N, TC, true>(T.B, w, o);
+    contract_eo<N, TC, 1>(T.eBt, w, o);
     lds_put<N, 1>(A, t1, t2, o);
   }
-  __syncthreads();
+  elem_sync<N>();
   if (act) {  // phase Z''': B_z^T -> accumulator C
     TC w[N], o[N];
     lds_get<N, 2>(A, t1, t2, w);
-    contract<N, TC, true>(T.B, w, o);
+    contract_eo<N, TC, 1>(T.eBt, w, o);
     lds_put<N, 2>(C, t1, t2, o);
   }
 }
@@ -434,13 +485,13 @@ __global__ __launch_bounds__(kBlock) void k_apply_trilinear(MeshArgs<TC> m, cons
   // faces (each call synchronises before touching shared buffers)
   face_term<N, 0, TC, TIN, false, AFF>(m, T, x, e, ex, ey, ez, X, sXn[le], K, t1, t2, C, sF[le], act, 0, Gc);
   face_term<N, 0, TC, TIN, false, AFF>(m, T, x, e, ex, ey, ez, X, sXn[le], K, t1, t2, C, sF[le], act, 1, Gc);
-  __syncthreads();
+  elem_sync<N>();
   face_term<N, 1, TC, TIN, false, AFF>(m, T, x, e, ex, ey, ez, X, sXn[le], K, t1, t2, C, sF[le], act, 0, Gc);
   face_term<N, 1, TC, TIN, false, AFF>(m, T, x, e, ex, ey, ez, X, sXn[le], K, t1, t2, C, sF[le], act, 1, Gc);
-  __syncthreads();
+  elem_sync<N>();
   face_term<N, 2, TC, TIN, false, AFF>(m, T, x, e, ex, ey, ez, X, sXn[le], K, t1, t2, C, sF[le], act, 0, Gc);
   face_term<N, 2, TC, TIN, false, AFF>(m, T, x, e, ex, ey, ez, X, sXn[le], K, t1, t2, C, sF[le], act, 1, Gc);
-  __syncthreads();
+  elem_sync<N>();
   double part = 0.0;
   if (act) {
     TC o[N];
@@ -498,7 +549,7 @@ __global__ __launch_bounds__(kBlock) void k_dA_parts_trilinear(MeshArgs<double> 
   // u_T . C for the thread's element, then C = 0 (deterministic: per-thread
   // partial sums, added in thread order by the element's first thread)
   auto take = [&](int slot) {
-    __syncthreads();
+    elem_sync<N>();
     double p = 0.0;
     if (act) {
       double c[N], z[N];
@@ -511,7 +562,7 @@ __global__ __launch_bounds__(kBlock) void k_dA_parts_trilinear(MeshArgs<double> 
       lds_put<N, 2>(C, t1, t2, z);
     }
     sRed[tid] = p;
-    __syncthreads();
+    elem_sync<N>();
     if (act && t == 0) {
       double s = 0.0;
       for (int j = 0; j < NN; ++j) s += sRed[el * NN + j];
@@ -589,7 +640,7 @@ __global__ __launch_bounds__(512) void k_diag_trilinear(MeshArgs<double> m, doub
         G[t][k++] = c * (Aj[r][0] * Aj[cc][0] + Aj[r][1] * Aj[cc][1] + Aj[r][2] * Aj[cc][2]);
     G[t][6] = m.R ? m.R[e] * T.gw[q1] * T.gw[q2] * T.gw[q3] * fabs(det3(J)) : 0.0;  // reaction
   }
-  __syncthreads();
+  __syncthreads();  // G is shared by the whole block
   if (t >= N3) return;
   const int i1 = t % N, i2 = (t / N) % N, i3 = t / NN;
   const int ii[3] = {i1, i2, i3};
