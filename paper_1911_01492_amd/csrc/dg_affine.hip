@@ -133,8 +133,9 @@ __device__ __forceinline__ int nb_coord(int c, int s, int Nd, int periodic) {
 
 // Line operator with the neighbour data reduced to the two scalars the face
 // terms need: the neighbour's trace at the shared end (U) and its raw normal
-// derivative at that end (Gr = l'(end) . line, without 1/h).  Own face
-// scalars: u[0], g0 = d0.u, u[n-1], g1 = d1.u.  Same algebra as line_op.
+// derivative at that end (Gr = l'(end) . line, without 1/h), both zero on a
+// side without neighbour (Dirichlet face).  Own face scalars: u[0],
+// g0 = d0.u, u[n-1], g1 = d1.u.  Same algebra as line_op.
 template <int N, typename TC, bool TRANS>
 __device__ __forceinline__ void line_op_s(const Tables<TC>& T, const TC (&u)[N], TC g0, TC g1, TC UL, TC GLr,
                                           TC UH, TC GHr, bool hasL, bool hasH, TC GL, TC GH, TC vs, TC ih,
@@ -147,8 +148,8 @@ __device__ __forceinline__ void line_op_s(const Tables<TC>& T, const TC (&u)[N],
     b[i] = vs * s;
   }
   {  // upper face: this element is T^-
-    const TC g = g1 + (hasH ? GHr : TC(0));
-    const TC J = u[N - 1] - (hasH ? UH : TC(0));
+    const TC g = g1 + GHr;
+    const TC J = u[N - 1] - UH;
     const TC aP = sig * GH * (hasH ? TC(2) : TC(1));
     const TC GAi = At * GH * ih;
     b[N - 1] += At * aP * J - GAi * g;
@@ -157,8 +158,8 @@ __device__ __forceinline__ void line_op_s(const Tables<TC>& T, const TC (&u)[N],
     for (int i = 0; i < N; ++i) b[i] -= cj * T.d1[i];
   }
   {  // lower face: this element is T^+
-    const TC g = g0 + (hasL ? GLr : TC(0));
-    const TC J = (hasL ? UL : TC(0)) - u[0];
+    const TC g = g0 + GLr;
+    const TC J = UL - u[0];
     const TC aP = sig * GL * (hasL ? TC(2) : TC(1));
     const TC GAi = At * GL * ih;
     b[0] += GAi * g - At * aP * J;

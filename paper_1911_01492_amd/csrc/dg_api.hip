@@ -259,7 +259,6 @@ bool build_tables(int n, Tables<double>& T) {
       T.S[i * kMaxN + j] = s;
       T.B[i * kMaxN + j] = B[i * n + j];
       T.D[i * kMaxN + j] = D[i * n + j];
-      T.Dg[i * kMaxN + j] = Dg[i * n + j];
     }
   for (int i = 0; i < n; ++i) {
     T.d0[i] = Dn[0 * n + i];
@@ -283,7 +282,6 @@ void tables_to_f32(const Tables<double>& a, Tables<float>& b) {
     b.S[i] = (float)a.S[i];
     b.B[i] = (float)a.B[i];
     b.D[i] = (float)a.D[i];
-    b.Dg[i] = (float)a.Dg[i];
   }
   for (int i = 0; i < kMaxN; ++i) {
     b.d0[i] = (float)a.d0[i];

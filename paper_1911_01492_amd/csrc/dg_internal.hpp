@@ -37,13 +37,13 @@ struct Tables {
   T S[kMaxN * kMaxN];   // stiffness  S_ij = sum_q w_q l_i'(x_q) l_j'(x_q)
   T B[kMaxN * kMaxN];   // interpolation GLL -> Gauss, B_qi = l_i(x_q)
   T D[kMaxN * kMaxN];   // derivative at the Gauss points, D_qi = l_i'(x_q)
-  T Dg[kMaxN * kMaxN];  // collocation derivative on the Gauss points (Dg B = D)
   T d0[kMaxN];          // l_i'(0)
   T d1[kMaxN];          // l_i'(1)
   T gw[kMaxN];          // Gauss weights on [0,1]
   T gx[kMaxN];          // Gauss points on [0,1]
   EvenOdd<T> eB, eBt;   // B and B^T (centro-symmetric)
-  EvenOdd<T> eDg, eDgt; // Dg and Dg^T (centro-antisymmetric)
+  EvenOdd<T> eDg, eDgt; // Dg and Dg^T, Dg the collocation derivative on the Gauss
+                        // points (Dg B = D; centro-antisymmetric)
 };
 
 // Mesh data passed by value to the kernels.

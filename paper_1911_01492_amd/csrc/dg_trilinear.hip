@@ -26,18 +26,6 @@
 
 namespace dg {
 
-// out_i = sum_j A[i][j] a_j  (TA: A[j][i]), A with row stride kMaxN
-template <int N, typename TC, bool TA>
-__device__ __forceinline__ void contract(const TC* A, const TC (&a)[N], TC (&out)[N]) {
-#pragma unroll
-  for (int i = 0; i < N; ++i) {
-    TC s = TC(0);
-#pragma unroll
-    for (int j = 0; j < N; ++j) s += (TA ? A[j * kMaxN + i] : A[i * kMaxN + j]) * a[j];
-    out[i] = s;
-  }
-}
-
 // Synchronisation of the n^2 threads of one element: every exchange through
 // LDS in these kernels stays inside one element (its tiles, face buffers and
 // corner slots).  When n^2 divides 64 an element lies inside one wavefront,
