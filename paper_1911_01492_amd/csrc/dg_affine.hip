@@ -98,16 +98,29 @@ __device__ __forceinline__ void line_op(const Tables<TC>& T, const TC (&u)[N], c
   }
 }
 
-// out = A1 a (+ add), A1 = M (TRANS: M^T) along the line
+// out = A a along the line for the symmetric, centro-symmetric 1D matrix A
+// (M or S, so A^T a = A a) given in full (Af) and by its even-odd halves
+// (Ae): the halves from n = 5 on, where they save operations (n^2/2 + 2n
+// against n^2 at even n), the full matrix below.
+template <int N, typename TC>
+__device__ __forceinline__ void sym_line(const TC* Af, const EvenOdd<TC>& Ae, const TC (&a)[N], TC (&out)[N]) {
+  if constexpr (N >= 5) {
+    contract_eo<N, TC, 1>(Ae, a, out);
+  } else {
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      TC s = TC(0);
+#pragma unroll
+      for (int j = 0; j < N; ++j) s += Af[i * kMaxN + j] * a[j];
+      out[i] = s;
+    }
+  }
+}
+
+// out = M a along the line (M is symmetric: also M^T a)
 template <int N, typename TC, bool TRANS>
 __device__ __forceinline__ void mass_line(const Tables<TC>& T, const TC (&a)[N], TC (&out)[N]) {
-#pragma unroll
-  for (int i = 0; i < N; ++i) {
-    TC s = TC(0);
-#pragma unroll
-    for (int j = 0; j < N; ++j) s += (TRANS ? T.M[j * kMaxN + i] : T.M[i * kMaxN + j]) * a[j];
-    out[i] = s;
-  }
+  sym_line<N, TC>(T.M, T.eM, a, out);
 }
 
 // Brick of elements per workgroup for n nodes per direction (BX x BY x BZ,
@@ -140,12 +153,11 @@ template <int N, typename TC, bool TRANS>
 __device__ __forceinline__ void line_op_s(const Tables<TC>& T, const TC (&u)[N], TC g0, TC g1, TC UL, TC GLr,
                                           TC UH, TC GHr, bool hasL, bool hasH, TC GL, TC GH, TC vs, TC ih,
                                           TC sig, TC At, TC (&b)[N]) {
+  {  // volume: vs S u (S is symmetric: also the transpose)
+    TC su[N];
+    sym_line<N, TC>(T.S, T.eS, u, su);
 #pragma unroll
-  for (int i = 0; i < N; ++i) {
-    TC s = TC(0);
-#pragma unroll
-    for (int j = 0; j < N; ++j) s += (TRANS ? T.S[j * kMaxN + i] : T.S[i * kMaxN + j]) * u[j];
-    b[i] = vs * s;
+    for (int i = 0; i < N; ++i) b[i] = vs * su[i];
   }
   {  // upper face: this element is T^-
     const TC g = g1 + GHr;

@@ -248,6 +248,7 @@ bool build_tables(int n, Tables<double>& T) {
       for (int k = 0; k < n; ++k) D[q * n + i] += l[k] * Dn[k * n + i];
     }
   }
+  std::vector<double> Mv((size_t)n * n), Sv((size_t)n * n);
   for (int i = 0; i < n; ++i)
     for (int j = 0; j < n; ++j) {
       double m = 0.0, s = 0.0;
@@ -257,6 +258,8 @@ bool build_tables(int n, Tables<double>& T) {
       }
       T.M[i * kMaxN + j] = m;
       T.S[i * kMaxN + j] = s;
+      Mv[i * n + j] = m;
+      Sv[i * n + j] = s;
       T.B[i * kMaxN + j] = B[i * n + j];
       T.D[i * kMaxN + j] = D[i * n + j];
     }
@@ -272,8 +275,8 @@ bool build_tables(int n, Tables<double>& T) {
       Bt[i * n + j] = B[j * n + i];
       Dgt[i * n + j] = Dg[j * n + i];
     }
-  return even_odd(n, B, 1, T.eB) && even_odd(n, Bt, 1, T.eBt) && even_odd(n, Dg, -1, T.eDg) &&
-         even_odd(n, Dgt, -1, T.eDgt);
+  return even_odd(n, Mv, 1, T.eM) && even_odd(n, Sv, 1, T.eS) && even_odd(n, B, 1, T.eB) &&
+         even_odd(n, Bt, 1, T.eBt) && even_odd(n, Dg, -1, T.eDg) && even_odd(n, Dgt, -1, T.eDgt);
 }
 
 void tables_to_f32(const Tables<double>& a, Tables<float>& b) {
@@ -289,6 +292,8 @@ void tables_to_f32(const Tables<double>& a, Tables<float>& b) {
     b.gw[i] = (float)a.gw[i];
     b.gx[i] = (float)a.gx[i];
   }
+  even_odd_to_f32(a.eM, b.eM);
+  even_odd_to_f32(a.eS, b.eS);
   even_odd_to_f32(a.eB, b.eB);
   even_odd_to_f32(a.eBt, b.eBt);
   even_odd_to_f32(a.eDg, b.eDg);

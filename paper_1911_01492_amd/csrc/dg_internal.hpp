@@ -41,6 +41,7 @@ struct Tables {
   T d1[kMaxN];          // l_i'(1)
   T gw[kMaxN];          // Gauss weights on [0,1]
   T gx[kMaxN];          // Gauss points on [0,1]
+  EvenOdd<T> eM, eS;    // M and S (symmetric, centro-symmetric)
   EvenOdd<T> eB, eBt;   // B and B^T (centro-symmetric)
   EvenOdd<T> eDg, eDgt; // Dg and Dg^T, Dg the collocation derivative on the Gauss
                         // points (Dg B = D; centro-antisymmetric)

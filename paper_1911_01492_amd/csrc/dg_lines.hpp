@@ -80,4 +80,36 @@ __device__ __forceinline__ void glb_get(const TIN* __restrict__ x, int64_t e, in
   for (int i = 0; i < N; ++i) v[i] = load_as<TC, TIN>(x + (base + (uint32_t)(lidx<N, D>(0, 0, i))));
 }
 
+// out = A a for A given by its even-odd halves (SIGN: A[n-1-i][n-1-j] = SIGN A[i][j]):
+// with a_e = a_j + a_{n-1-j}, a_o = a_j - a_{n-1-j} (j < n/2),
+//   P_i = E a_e (+ C_i a_m), Q_i = O a_o,  out_i = P_i + Q_i,  out_{n-1-i} = SIGN (P_i - Q_i),
+// and for odd n the middle row R a_e + mm a_m (SIGN = +1) or R a_o (SIGN = -1).
+template <int N, typename TC, int SIGN>
+__device__ __forceinline__ void contract_eo(const EvenOdd<TC>& A, const TC (&a)[N], TC (&out)[N]) {
+  constexpr int H = N / 2;
+  TC ae[H], ao[H];
+#pragma unroll
+  for (int j = 0; j < H; ++j) {
+    ae[j] = a[j] + a[N - 1 - j];
+    ao[j] = a[j] - a[N - 1 - j];
+  }
+#pragma unroll
+  for (int i = 0; i < H; ++i) {
+    TC P = (N & 1) ? A.C[i] * a[H] : TC(0), Q = TC(0);
+#pragma unroll
+    for (int j = 0; j < H; ++j) {
+      P += A.E[i * kMaxH + j] * ae[j];
+      Q += A.O[i * kMaxH + j] * ao[j];
+    }
+    out[i] = P + Q;
+    out[N - 1 - i] = SIGN > 0 ? P - Q : Q - P;
+  }
+  if (N & 1) {
+    TC s = SIGN > 0 ? A.mm * a[H] : TC(0);
+#pragma unroll
+    for (int j = 0; j < H; ++j) s += A.R[j] * (SIGN > 0 ? ae[j] : ao[j]);
+    out[H] = s;
+  }
+}
+
 }  // namespace dg
