@@ -256,6 +256,22 @@ struct AxisNeighbours {
   }
 };
 
+// Barrier over the threads that exchange data through LDS at one point of
+// the apply.  WAVE: every thread whose LDS writes the readers depend on lies
+// in the reader's wavefront (the lanes of a wavefront execute together and
+// its LDS operations complete in order), so only the compiler has to be kept
+// from moving LDS accesses across it; otherwise the workgroup barrier.
+template <bool WAVE>
+__device__ __forceinline__ void lds_sync() {
+  if constexpr (WAVE) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
 // One face-aware direction of the affine apply: b = L_D u on this thread's
 // line along axis D (own line from HBM, neighbour face scalars from the
 // brick's exchange area F or from HBM).  Contains one barrier; every thread
@@ -282,7 +298,8 @@ __device__ __forceinline__ void face_phase(const MeshArgs<TC>& m, const Tables<T
     Fe[2 * NN + t] = u[N - 1];
     Fe[3 * NN + t] = g1;
   }
-  __syncthreads();
+  // x-neighbours inside the brick share the wavefront when a brick row does
+  lds_sync<D == 0 && 64 % (BX * NN) == 0>();
   {
     TC UL, GLr, UH, GHr;
     nb.scalars(F, t, UL, GLr, UH, GHr);
@@ -322,6 +339,10 @@ __global__ __launch_bounds__(apply_block(N)) void k_apply_affine(MeshArgs<TC> m,
   constexpr bool F_IN_S2 = 4 * NN <= PE;
   constexpr int BLOCK = apply_block(N);
   static_assert(TE * NN <= BLOCK && BLOCK <= kBlock, "brick too large");
+  // an element's threads lie in one wavefront (ELEM), and so does each x-row
+  // of the brick (XROW, which implies ELEM): those exchanges need only
+  // wavefront-level synchronisation
+  constexpr bool ELEM = 64 % NN == 0, XROW = 64 % (BX * NN) == 0;
   // a spare element slot takes the writes of padding threads (if the block has any)
   constexpr int SLOTS = TE * NN < BLOCK ? TE + 1 : TE;
   __shared__ TC sS1[SLOTS * PE], sS2[SLOTS * PE];
@@ -357,7 +378,7 @@ __global__ __launch_bounds__(apply_block(N)) void k_apply_affine(MeshArgs<TC> m,
   // ---------------- X: b_x -> S1
   face_phase<N, 0, BX, BY, BZ, TC, TIN, TRANS>(m, T, x, act, e, c, o, Nd, t, t1, t2, F, Fe, K, G[0], G[1], TC(0), b);
   lds_put<N, 0>(S1, t1, t2, b);
-  __syncthreads();  // F is rewritten by the next phase
+  lds_sync<XROW>();  // F (read by the x-neighbours) is rewritten by the next phase
   // ---------------- Y: b_y -> S2, M_y b_x -> S1
   face_phase<N, 1, BX, BY, BZ, TC, TIN, TRANS>(m, T, x, act, e, c, o, Nd, t, t1, t2, F, Fe, K, G[2], G[3], TC(0), b);
   {
@@ -369,7 +390,7 @@ __global__ __launch_bounds__(apply_block(N)) void k_apply_affine(MeshArgs<TC> m,
     lds_put<N, 1>(S2, t1, t2, b);
     lds_put<N, 1>(S1, t1, t2, w);
   }
-  __syncthreads();
+  lds_sync<ELEM>();
   // ---------------- X2: M_y b_x + M_x b_y -> S1
   {
     lds_get<N, 0>(S2, t1, t2, v);
@@ -379,7 +400,7 @@ __global__ __launch_bounds__(apply_block(N)) void k_apply_affine(MeshArgs<TC> m,
     for (int i = 0; i < N; ++i) w[i] += b[i];
     lds_put<N, 0>(S1, t1, t2, w);
   }
-  __syncthreads();
+  lds_sync<ELEM>();
   // ---------------- Z: b_z -> S2, r = M_z S1
   TC r[N];
   face_phase<N, 2, BX, BY, BZ, TC, TIN, TRANS>(m, T, x, act, e, c, o, Nd, t, t1, t2, F, Fe, K, G[4], G[5], cr, b);
@@ -389,20 +410,20 @@ __global__ __launch_bounds__(apply_block(N)) void k_apply_affine(MeshArgs<TC> m,
   }
   if (F_IN_S2) __syncthreads();
   lds_put<N, 2>(S2, t1, t2, b);
-  __syncthreads();
+  lds_sync<ELEM>();
   // ---------------- X3, Y3: S2 <- M_y M_x S2
   {
     lds_get<N, 0>(S2, t1, t2, v);
     mass_line<N, TC, TRANS>(T, v, w);
     lds_put<N, 0>(S2, t1, t2, w);
   }
-  __syncthreads();
+  lds_sync<ELEM>();
   {
     lds_get<N, 1>(S2, t1, t2, v);
     mass_line<N, TC, TRANS>(T, v, w);
     lds_put<N, 1>(S2, t1, t2, w);
   }
-  __syncthreads();
+  lds_sync<ELEM>();
   // ---------------- Z2: y = r + S2
   double part = 0.0;
   lds_get<N, 2>(S2, t1, t2, v);
