@@ -282,7 +282,7 @@ template <int N, int D, int BX, int BY, int BZ, typename TC, typename TIN, bool 
 __device__ __forceinline__ void face_phase(const MeshArgs<TC>& m, const Tables<TC>& T, const TIN* __restrict__ x,
                                            bool act, int64_t e, const int (&c)[3], const int (&o)[3],
                                            const int (&Nd)[3], int t, int t1, int t2, TC* F, TC* Fe, TC K, TC GL,
-                                           TC GH, TC cr, TC (&b)[N]) {
+                                           TC GH, TC cr, TC (&b)[N], TC* own = nullptr) {
   constexpr int NN = N * N;
   AxisNeighbours<N, D, BX, BY, BZ, TC, TIN> nb;
   TC u[N], g0, g1;
@@ -305,6 +305,10 @@ __device__ __forceinline__ void face_phase(const MeshArgs<TC>& m, const Tables<T
     nb.scalars(F, t, UL, GLr, UH, GHr);
     line_op_s<N, TC, TRANS>(T, u, g0, g1, UL, GLr, UH, GHr, nb.hasL, nb.hasH, GL, GH, K * m.vs[D], m.ih[D],
                             m.sg[D], m.At[D], b);
+    if (own != nullptr) {  // the caller keeps the line (x along D at (t1, t2))
+#pragma unroll
+      for (int i = 0; i < N; ++i) own[i] = u[i];
+    }
     if (cr != TC(0)) {  // reaction c |T| M u along this line (the other two masses follow)
       TC mu[N];
       mass_line<N, TC, false>(T, u, mu);
@@ -402,8 +406,9 @@ __global__ __launch_bounds__(apply_block(N)) void k_apply_affine(MeshArgs<TC> m,
   }
   lds_sync<ELEM>();
   // ---------------- Z: b_z -> S2, r = M_z S1
-  TC r[N];
-  face_phase<N, 2, BX, BY, BZ, TC, TIN, TRANS>(m, T, x, act, e, c, o, Nd, t, t1, t2, F, Fe, K, G[4], G[5], cr, b);
+  TC r[N], xz[N];  // xz: the thread's z-line of x, for the fused <x, y>
+  face_phase<N, 2, BX, BY, BZ, TC, TIN, TRANS>(m, T, x, act, e, c, o, Nd, t, t1, t2, F, Fe, K, G[4], G[5], cr, b,
+                                               DOT ? xz : nullptr);
   {
     lds_get<N, 2>(S1, t1, t2, v);
     mass_line<N, TC, TRANS>(T, v, r);
@@ -429,12 +434,11 @@ __global__ __launch_bounds__(apply_block(N)) void k_apply_affine(MeshArgs<TC> m,
   lds_get<N, 2>(S2, t1, t2, v);
   if (act) {
     TOUT* py = y + e * N3;
-    if (DOT) glb_get<N, 2, TC, TIN>(x, e, t1, t2, w);
 #pragma unroll
     for (int i = 0; i < N; ++i) {
       const TOUT yv = (TOUT)(r[i] + v[i]);
       py[lidx<N, 2>(t1, t2, i)] = yv;
-      if (DOT) part += (double)w[i] * (double)yv;
+      if (DOT) part += (double)xz[i] * (double)yv;
     }
   }
   if (DOT) {
