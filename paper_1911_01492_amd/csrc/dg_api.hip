@@ -43,6 +43,7 @@ struct dg_ctx {
   double *z64, *s64, *w64;   // single-reduction CG
   float *r32, *d32, *p32, *q32;
   uint16_t* p16;
+  void* fb;              // trilinear meshes: lower-face line scalars between the two apply passes
   double* partials;
   CgState* st;           // [0]: outer / FP64 solve, [1]: inner solve
   std::string err;
@@ -303,7 +304,7 @@ void tables_to_f32(const Tables<double>& a, Tables<float>& b) {
 // ------------------------------------------------------------------ workspace
 struct Layout {
   size_t tab64, tab32, K64, K32, G64, G32, R64, R32, vert64, vert32, dinv64, dinv32, r64, p64, q64, r32, d32, p32,
-      q32, p16, z64, s64, w64, partials, st, total;
+      q32, p16, z64, s64, w64, fb, partials, st, total;
 };
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
@@ -358,6 +359,7 @@ Layout layout(const dg_mesh_desc* m) {
   L.z64 = take(nd * sizeof(double));
   L.s64 = take(nd * sizeof(double));
   L.w64 = take(nd * sizeof(double));
+  L.fb = take(tri ? (size_t)E * 3 * 2 * n * n * sizeof(double) : 0);  // FP64 size, shared by the FP32 applies
   const int64_t nb = std::max<int64_t>(std::max<int64_t>(element_blocks(n, E), vec_blocks(nd)),
                                        affine_tiles(n, m->nx, m->ny, m->nz));
   L.partials = take((size_t)nb * 3 * sizeof(double));
@@ -398,6 +400,7 @@ MeshArgs<double> args64(const dg_ctx* c) {
   m.R = c->reaction ? c->R64 : nullptr;
   m.vol = (1.0 / c->desc.nx) * (1.0 / c->desc.ny) * (1.0 / c->desc.nz);
   m.affg = c->affine_geom ? 1 : 0;
+  m.fb = (double*)c->fb;
   fill_scales(m);
   return m;
 }
@@ -419,6 +422,7 @@ MeshArgs<float> args32(const dg_ctx* c) {
   m.R = c->reaction ? c->R32 : nullptr;
   m.vol = (float)((1.0 / c->desc.nx) * (1.0 / c->desc.ny) * (1.0 / c->desc.nz));
   m.affg = c->affine_geom ? 1 : 0;
+  m.fb = (float*)c->fb;
   fill_scales(m);
   return m;
 }
@@ -531,6 +535,7 @@ int dg_setup(const dg_mesh_desc* mesh, dg_ctx** out, void* stream) {
   c->z64 = (double*)(w + L.z64);
   c->s64 = (double*)(w + L.s64);
   c->w64 = (double*)(w + L.w64);
+  c->fb = c->trilinear ? (void*)(w + L.fb) : nullptr;
   c->partials = (double*)(w + L.partials);
   c->st = (CgState*)(w + L.st);
   hipStream_t s = (hipStream_t)stream;

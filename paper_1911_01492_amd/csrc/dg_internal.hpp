@@ -67,6 +67,9 @@ struct MeshArgs {
   const T* R;           // E reaction coefficients c_T, or nullptr (no reaction term)
   T vol;                // h_x h_y h_z (affine element volume)
   int affg;             // trilinear meshes: 1 when every element is a parallelepiped
+  T* fb;                // trilinear meshes: per element and axis d, the 2 n^2 line scalars of
+                        // its lower face (d, 0), written by the neighbour that evaluates the
+                        // face in the first pass of the apply ([(3 e + d) 2 + k] n^2 + t)
 };
 
 // Block -> logical tile: consecutive logical tiles go to the same XCD (the

@@ -56,9 +56,12 @@ __device__ __forceinline__ void corner_of(const MeshArgs<TC>& m, int64_t e, int 
 // element, added into the element's accumulator tile Y.  UNIT: with the face
 // coefficient set to 1 (gamma_e on interior faces, K_T on boundary faces),
 // for the sensitivity dA/dtheta.  AFF: the element is a parallelepiped and
-// Gc holds its constant J, adj J and det J.  All threads of the
-// block call this (it synchronises); act marks threads owning an element.
-template <int N, int D, typename TC, typename TIN, bool UNIT = false, bool AFF = false>
+// Gc holds its constant J, adj J and det J.  PAIR (upper faces, s = 1): the
+// face is evaluated once for both elements; the neighbour's side (T^+, whose
+// lower face it is) is projected as well and its two line scalars per face
+// node go to m.fb for the second pass.  All threads of the block call this
+// (it synchronises); act marks threads owning an element.
+template <int N, int D, typename TC, typename TIN, bool UNIT = false, bool AFF = false, bool PAIR = false>
 __device__ void face_term(const MeshArgs<TC>& m, const Tables<TC>& T, const TIN* __restrict__ x, int64_t e,
                           int ex, int ey, int ez, const TC (&X)[8][3], TC (&Xn)[8][3], TC K, int t1, int t2,
                           TC* Y, TC (*F)[N * N], bool act, int s, const TC* Gc = nullptr) {
@@ -117,6 +120,7 @@ __device__ void face_term(const MeshArgs<TC>& m, const Tables<TC>& T, const TIN*
   }
   elem_sync<N>();
   TC P = 0, Ra = 0, Rb = 0, Rd = 0;
+  TC Pn = 0, Ran = 0, Rbn = 0, Rdn = 0;  // PAIR: the neighbour's side (T^+)
   if (act) {  // along t2 (axis bx): values at face Gauss point (qa, qb) = (t1, t2)
     TC uo = 0, gao = 0, gbo = 0, gdo = 0, un = 0, gan = 0, gbn = 0, gdn = 0;
 #pragma unroll
@@ -198,6 +202,16 @@ __device__ void face_term(const MeshArgs<TC>& m, const Tables<TC>& T, const TIN*
       Ra = R[ax];
       Rb = R[bx];
       Rd = R[D];
+      if (PAIR) {  // T^+ side of the same face: the opposite flux-minus-penalty term, and
+                   // its symmetry term with its own adj J and det J
+        Pn = -P;
+        const TC crn = -TC(0.5) * gam * w * Jq * idetn;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) R[c] = crn * (An[c][0] * Nv[0] + An[c][1] * Nv[1] + An[c][2] * Nv[2]);
+        Ran = R[ax];
+        Rbn = R[bx];
+        Rdn = R[D];
+      }
     } else {
       // weak Dirichlet: -K grad u.n v - K grad v.n u + sigma K u v, outward n
       const TC sg = s ? TC(1) : TC(-1);
@@ -219,29 +233,57 @@ __device__ void face_term(const MeshArgs<TC>& m, const Tables<TC>& T, const TIN*
     F[1][t] = Ra;
     F[2][t] = Rb;
     F[3][t] = Rd;
+    if (PAIR) {
+      F[4][t] = Pn;
+      F[5][t] = Ran;
+      F[6][t] = Rbn;
+      F[7][t] = Rdn;
+    }
   }
   elem_sync<N>();
-  if (act) {  // transposed tangential operators, contraction over qb: thread (qa, b) = (t1, t2)
-    TC xs = 0, ys = 0, zs = 0;
+  // transposed tangential operators, contraction over qb: thread (qa, b) = (t1, t2);
+  // rows: own side F[4..6] (PAIR: F[0..2]), neighbour side F[3..5]
+  constexpr int O = PAIR ? 0 : 4;
+  {
+    TC xs = 0, ys = 0, zs = 0, xn = 0, yn = 0, zn = 0;
+    if (act) {
 #pragma unroll
-    for (int qb = 0; qb < N; ++qb) {
-      const TC B = T.B[qb * kMaxN + t2], Dd = T.D[qb * kMaxN + t2];
-      xs += B * F[0][qb * N + t1] + Dd * F[2][qb * N + t1];
-      ys += B * F[1][qb * N + t1];
-      zs += B * F[3][qb * N + t1];
+      for (int qb = 0; qb < N; ++qb) {
+        const TC B = T.B[qb * kMaxN + t2], Dd = T.D[qb * kMaxN + t2];
+        xs += B * F[0][qb * N + t1] + Dd * F[2][qb * N + t1];
+        ys += B * F[1][qb * N + t1];
+        zs += B * F[3][qb * N + t1];
+        if (PAIR) {
+          xn += B * F[4][qb * N + t1] + Dd * F[6][qb * N + t1];
+          yn += B * F[5][qb * N + t1];
+          zn += B * F[7][qb * N + t1];
+        }
+      }
     }
-    F[4][t2 * N + t1] = xs;
-    F[5][t2 * N + t1] = ys;
-    F[6][t2 * N + t1] = zs;
+    if (PAIR) elem_sync<N>();  // the inputs are overwritten below
+    if (act) {
+      F[O + 0][t2 * N + t1] = xs;
+      F[O + 1][t2 * N + t1] = ys;
+      F[O + 2][t2 * N + t1] = zs;
+      if (PAIR) {
+        F[3][t2 * N + t1] = xn;
+        F[4][t2 * N + t1] = yn;
+        F[5][t2 * N + t1] = zn;
+      }
+    }
   }
   elem_sync<N>();
   if (act) {  // contraction over qa: thread (a, b) = (t1, t2) owns face node (a, b) of its line
-    TC out = 0, z = 0;
+    TC out = 0, z = 0, outn = 0, zn = 0;
 #pragma unroll
     for (int qa = 0; qa < N; ++qa) {
       const TC B = T.B[qa * kMaxN + t1], Dd = T.D[qa * kMaxN + t1];
-      out += B * F[4][t2 * N + qa] + Dd * F[5][t2 * N + qa];
-      z += B * F[6][t2 * N + qa];
+      out += B * F[O + 0][t2 * N + qa] + Dd * F[O + 1][t2 * N + qa];
+      z += B * F[O + 2][t2 * N + qa];
+      if (PAIR) {
+        outn += B * F[3][t2 * N + qa] + Dd * F[4][t2 * N + qa];
+        zn += B * F[5][t2 * N + qa];
+      }
     }
     TC yl[N];
     lds_get<N, D>(Y, t1, t2, yl);
@@ -249,6 +291,11 @@ __device__ void face_term(const MeshArgs<TC>& m, const Tables<TC>& T, const TIN*
     for (int i = 0; i < N; ++i) yl[i] += dS[i] * z;
     yl[s ? N - 1 : 0] += out;
     lds_put<N, D>(Y, t1, t2, yl);
+    if (PAIR && nb >= 0) {  // the neighbour's line (t1, t2) along D, added by its second pass
+      TC* fbn = m.fb + ((int64_t)nb * 3 + D) * 2 * NN;
+      fbn[t] = outn;
+      fbn[NN + t] = zn;
+    }
   }
 }
 
@@ -394,15 +441,35 @@ __device__ void tri_volume(const MeshArgs<TC>& m, const Tables<TC>& T, const TIN
   }
 }
 
-template <int N, typename TIN, typename TOUT, typename TC, bool DOT, bool AFF>
+// The T^+ side of the lower face (D, 0) of element e on the thread's line
+// along D at (t1, t2), added to the element tile C: z l'(0) on the line, the
+// trace term on node 0 (the two scalars left in m.fb by the first pass).
+template <int N, int D, typename TC>
+__device__ __forceinline__ void lower_line(const MeshArgs<TC>& m, const Tables<TC>& T, int64_t e, int t1, int t2,
+                                           TC* C) {
+  constexpr int NN = N * N;
+  const TC* fb = m.fb + ((int64_t)e * 3 + D) * 2 * NN;
+  const int t = t1 + N * t2;
+  const TC out = fb[t], z = fb[NN + t];
+  TC yl[N];
+  lds_get<N, D>(C, t1, t2, yl);
+#pragma unroll
+  for (int i = 0; i < N; ++i) yl[i] += T.d0[i] * z;
+  yl[0] += out;
+  lds_put<N, D>(C, t1, t2, yl);
+}
+
+// First pass of the trilinear apply: y_T = volume part + the element's three
+// upper faces (evaluated once for both of their elements; the T^+ side goes
+// to m.fb) + its lower faces on a Dirichlet boundary.  The second pass
+// (k_tri_lower) adds the lower interior faces from m.fb.
+template <int N, typename TIN, typename TOUT, typename TC, bool AFF>
 __global__ __launch_bounds__(kBlock) void k_apply_trilinear(MeshArgs<TC> m, const TIN* __restrict__ x,
-                                                            TOUT* __restrict__ y, double* partials,
-                                                            const int* skip) {
+                                                            TOUT* __restrict__ y, const int* skip) {
   constexpr int NN = N * N, N3 = NN * N, EPB = elems_per_block(N), PE = Lay<N, TC>::PE;
   __shared__ TC sA[EPB * PE], sB[EPB * PE], sC[EPB * PE];
   __shared__ TC sX[EPB][8][3], sXn[EPB][8][3];
   __shared__ TC sF[EPB][10][NN];
-  __shared__ double red[kBlock / 64];
   if (skip != nullptr && *skip) return;
   const Tables<TC>& T = *m.tab;
   const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
@@ -438,22 +505,69 @@ __global__ __launch_bounds__(kBlock) void k_apply_trilinear(MeshArgs<TC> m, cons
       }
     Gc[18] = det3(J);
   }
-  // faces (each call synchronises before touching shared buffers)
-  face_term<N, 0, TC, TIN, false, AFF>(m, T, x, e, ex, ey, ez, X, sXn[le], K, t1, t2, C, sF[le], act, 0, Gc);
-  face_term<N, 0, TC, TIN, false, AFF>(m, T, x, e, ex, ey, ez, X, sXn[le], K, t1, t2, C, sF[le], act, 1, Gc);
+  // upper faces for both sides; lower faces only where there is no element below
+  // (each call synchronises before touching shared buffers)
+  const bool bx0 = act && neighbour<0>(m, ex, ey, ez, 0) < 0;
+  const bool by0 = act && neighbour<1>(m, ex, ey, ez, 0) < 0;
+  const bool bz0 = act && neighbour<2>(m, ex, ey, ez, 0) < 0;
+  face_term<N, 0, TC, TIN, false, AFF, true>(m, T, x, e, ex, ey, ez, X, sXn[le], K, t1, t2, C, sF[le], act, 1, Gc);
+  face_term<N, 0, TC, TIN, false, AFF>(m, T, x, e, ex, ey, ez, X, sXn[le], K, t1, t2, C, sF[le], bx0, 0, Gc);
   elem_sync<N>();
-  face_term<N, 1, TC, TIN, false, AFF>(m, T, x, e, ex, ey, ez, X, sXn[le], K, t1, t2, C, sF[le], act, 0, Gc);
-  face_term<N, 1, TC, TIN, false, AFF>(m, T, x, e, ex, ey, ez, X, sXn[le], K, t1, t2, C, sF[le], act, 1, Gc);
+  face_term<N, 1, TC, TIN, false, AFF, true>(m, T, x, e, ex, ey, ez, X, sXn[le], K, t1, t2, C, sF[le], act, 1, Gc);
+  face_term<N, 1, TC, TIN, false, AFF>(m, T, x, e, ex, ey, ez, X, sXn[le], K, t1, t2, C, sF[le], by0, 0, Gc);
   elem_sync<N>();
-  face_term<N, 2, TC, TIN, false, AFF>(m, T, x, e, ex, ey, ez, X, sXn[le], K, t1, t2, C, sF[le], act, 0, Gc);
-  face_term<N, 2, TC, TIN, false, AFF>(m, T, x, e, ex, ey, ez, X, sXn[le], K, t1, t2, C, sF[le], act, 1, Gc);
+  face_term<N, 2, TC, TIN, false, AFF, true>(m, T, x, e, ex, ey, ez, X, sXn[le], K, t1, t2, C, sF[le], act, 1, Gc);
+  face_term<N, 2, TC, TIN, false, AFF>(m, T, x, e, ex, ey, ez, X, sXn[le], K, t1, t2, C, sF[le], bz0, 0, Gc);
   elem_sync<N>();
-  double part = 0.0;
   if (act) {
     TC o[N];
     lds_get<N, 2>(C, t1, t2, o);
     TOUT* py = y + e * N3;
-    TC uz[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) py[lidx<N, 2>(t1, t2, i)] = (TOUT)o[i];
+  }
+}
+
+// Second pass: y_T += the T^+ side of each interior lower face of T, from the
+// line scalars the first pass left in m.fb (its line along d at (t1, t2):
+// l_i'(0) z added to every node, the trace term to node 0).  DOT: block
+// partials of <x, y> for the CG.
+template <int N, typename TIN, typename TOUT, typename TC, bool DOT>
+__global__ __launch_bounds__(kBlock) void k_tri_lower(MeshArgs<TC> m, const TIN* __restrict__ x,
+                                                      TOUT* __restrict__ y, double* partials, const int* skip) {
+  constexpr int NN = N * N, N3 = NN * N, EPB = elems_per_block(N), PE = Lay<N, TC>::PE;
+  __shared__ TC sC[EPB * PE];
+  __shared__ double red[kBlock / 64];
+  if (skip != nullptr && *skip) return;
+  const Tables<TC>& T = *m.tab;
+  const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
+  const int tid = threadIdx.x, el = tid / NN, t = tid % NN, t1 = t % N, t2 = t / N;
+  const int64_t e = blk * EPB + el;
+  const bool act = (el < EPB) && (e < m.E);
+  const int le = act ? el : 0;
+  TC* C = sC + le * PE;
+  int ex = 0, ey = 0, ez = 0;
+  TOUT* py = y + e * N3;
+  if (act) {
+    ex = (int)(e % m.nx);
+    ey = (int)((e / m.nx) % m.ny);
+    ez = (int)(e / ((int64_t)m.nx * m.ny));
+    TC o[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) o[i] = (TC)py[lidx<N, 2>(t1, t2, i)];
+    lds_put<N, 2>(C, t1, t2, o);
+  }
+  elem_sync<N>();
+  if (act && neighbour<0>(m, ex, ey, ez, 0) >= 0) lower_line<N, 0>(m, T, e, t1, t2, C);
+  elem_sync<N>();
+  if (act && neighbour<1>(m, ex, ey, ez, 0) >= 0) lower_line<N, 1>(m, T, e, t1, t2, C);
+  elem_sync<N>();
+  if (act && neighbour<2>(m, ex, ey, ez, 0) >= 0) lower_line<N, 2>(m, T, e, t1, t2, C);
+  elem_sync<N>();
+  double part = 0.0;
+  if (act) {
+    TC o[N], uz[N];
+    lds_get<N, 2>(C, t1, t2, o);
     if (DOT) glb_get<N, 2, TC, TIN>(x, e, t1, t2, uz);
 #pragma unroll
     for (int i = 0; i < N; ++i) {
@@ -689,12 +803,16 @@ static hipError_t run_tri(const MeshArgs<TC>& m, const void* x, void* y, double*
                           const int* skip, hipStream_t s) {
   const int64_t nb = element_blocks(N, m.E);
   if (m.affg)
-    hipLaunchKernelGGL((k_apply_trilinear<N, TIN, TOUT, TC, DOT, true>), dim3((unsigned)nb), dim3(kBlock), 0, s, m,
-                       (const TIN*)x, (TOUT*)y, partials, skip);
+    hipLaunchKernelGGL((k_apply_trilinear<N, TIN, TOUT, TC, true>), dim3((unsigned)nb), dim3(kBlock), 0, s, m,
+                       (const TIN*)x, (TOUT*)y, skip);
   else
-    hipLaunchKernelGGL((k_apply_trilinear<N, TIN, TOUT, TC, DOT, false>), dim3((unsigned)nb), dim3(kBlock), 0, s, m,
-                       (const TIN*)x, (TOUT*)y, partials, skip);
+    hipLaunchKernelGGL((k_apply_trilinear<N, TIN, TOUT, TC, false>), dim3((unsigned)nb), dim3(kBlock), 0, s, m,
+                       (const TIN*)x, (TOUT*)y, skip);
   hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_tri_lower<N, TIN, TOUT, TC, DOT>), dim3((unsigned)nb), dim3(kBlock), 0, s, m, (const TIN*)x,
+                     (TOUT*)y, partials, skip);
+  e = hipGetLastError();
   if (e != hipSuccess || !DOT || st == nullptr) return e;  // st == nullptr: partials only
   return launch_finish_dot(partials, nb, st, par, s);
 }
