@@ -238,7 +238,9 @@ struct AxisNeighbours {
       dH = dot_end<N, TC, 0>(T, gH);
     }
   }
-  // neighbour scalars: low side -> its upper-face (U, d1.u), high side -> its lower-face (U, d0.u)
+  // neighbour scalars: low side -> its upper-face (U, d1.u), high side -> its lower-face (U, d0.u);
+  // element slots of FS values in F
+  template <int FS>
   __device__ __forceinline__ void scalars(const TC* F, int t, TC& UL, TC& GLr, TC& UH, TC& GHr) const {
     constexpr int NN = N * N;
     UL = uL;
@@ -246,12 +248,12 @@ struct AxisNeighbours {
     UH = uH;
     GHr = dH;
     if (inL) {
-      UL = F[(elL * 4 + 2) * NN + t];
-      GLr = F[(elL * 4 + 3) * NN + t];
+      UL = F[elL * FS + 2 * NN + t];
+      GLr = F[elL * FS + 3 * NN + t];
     }
     if (inH) {
-      UH = F[(elH * 4 + 0) * NN + t];
-      GHr = F[(elH * 4 + 1) * NN + t];
+      UH = F[elH * FS + 0 * NN + t];
+      GHr = F[elH * FS + 1 * NN + t];
     }
   }
 };
@@ -278,7 +280,7 @@ __device__ __forceinline__ void lds_sync() {
 // of the block calls it.  act == false: a thread without an element of its
 // own (it computes on a clamped element, sees no neighbours, and its result
 // is discarded).
-template <int N, int D, int BX, int BY, int BZ, typename TC, typename TIN, bool TRANS>
+template <int N, int D, int BX, int BY, int BZ, int FS, typename TC, typename TIN, bool TRANS>
 __device__ __forceinline__ void face_phase(const MeshArgs<TC>& m, const Tables<TC>& T, const TIN* __restrict__ x,
                                            bool act, int64_t e, const int (&c)[3], const int (&o)[3],
                                            const int (&Nd)[3], int t, int t1, int t2, TC* F, TC* Fe, TC K, TC GL,
@@ -302,7 +304,7 @@ __device__ __forceinline__ void face_phase(const MeshArgs<TC>& m, const Tables<T
   lds_sync<D == 0 && 64 % (BX * NN) == 0>();
   {
     TC UL, GLr, UH, GHr;
-    nb.scalars(F, t, UL, GLr, UH, GHr);
+    nb.template scalars<FS>(F, t, UL, GLr, UH, GHr);
     line_op_s<N, TC, TRANS>(T, u, g0, g1, UL, GLr, UH, GHr, nb.hasL, nb.hasH, GL, GH, K * m.vs[D], m.ih[D],
                             m.sg[D], m.At[D], b);
     if (own != nullptr) {  // the caller keeps the line (x along D at (t1, t2))
@@ -341,6 +343,7 @@ __global__ __launch_bounds__(apply_block(N)) void k_apply_affine(MeshArgs<TC> m,
   constexpr int BX = tile_x(N), BY = tile_y(N), BZ = tile_z(N), TE = BX * BY * BZ;
   constexpr int PE = Lay<N, TC>::PE;
   constexpr bool F_IN_S2 = 4 * NN <= PE;
+  constexpr int FS = F_IN_S2 ? PE : 4 * NN;  // element stride of the face-scalar slots
   constexpr int BLOCK = apply_block(N);
   static_assert(TE * NN <= BLOCK && BLOCK <= kBlock, "brick too large");
   // an element's threads lie in one wavefront (ELEM), and so does each x-row
@@ -371,7 +374,10 @@ __global__ __launch_bounds__(apply_block(N)) void k_apply_affine(MeshArgs<TC> m,
   const int le = el < TE ? el : TE;
   TC* S1 = sS1 + le * PE;
   TC* S2 = sS2 + le * PE;
-  TC* Fe = F + le * 4 * NN;
+  // the face-scalar slot of an element lies inside its own S2 tile (slot
+  // stride PE): F traffic never touches another element's tile, so the
+  // element-local hand-offs below need no workgroup barrier
+  TC* Fe = F + le * FS;
   const int64_t e = c[0] + (int64_t)m.nx * (c[1] + (int64_t)m.ny * c[2]);
   TC K, G[6], cr = TC(0);
   K = m.K[e];
@@ -380,11 +386,11 @@ __global__ __launch_bounds__(apply_block(N)) void k_apply_affine(MeshArgs<TC> m,
   if (m.R) cr = m.R[e] * m.vol;
   TC b[N], v[N], w[N];
   // ---------------- X: b_x -> S1
-  face_phase<N, 0, BX, BY, BZ, TC, TIN, TRANS>(m, T, x, act, e, c, o, Nd, t, t1, t2, F, Fe, K, G[0], G[1], TC(0), b);
+  face_phase<N, 0, BX, BY, BZ, FS, TC, TIN, TRANS>(m, T, x, act, e, c, o, Nd, t, t1, t2, F, Fe, K, G[0], G[1], TC(0), b);
   lds_put<N, 0>(S1, t1, t2, b);
   lds_sync<XROW>();  // F (read by the x-neighbours) is rewritten by the next phase
   // ---------------- Y: b_y -> S2, M_y b_x -> S1
-  face_phase<N, 1, BX, BY, BZ, TC, TIN, TRANS>(m, T, x, act, e, c, o, Nd, t, t1, t2, F, Fe, K, G[2], G[3], TC(0), b);
+  face_phase<N, 1, BX, BY, BZ, FS, TC, TIN, TRANS>(m, T, x, act, e, c, o, Nd, t, t1, t2, F, Fe, K, G[2], G[3], TC(0), b);
   {
     lds_get<N, 1>(S1, t1, t2, v);
     mass_line<N, TC, TRANS>(T, v, w);
@@ -407,7 +413,7 @@ __global__ __launch_bounds__(apply_block(N)) void k_apply_affine(MeshArgs<TC> m,
   lds_sync<ELEM>();
   // ---------------- Z: b_z -> S2, r = M_z S1
   TC r[N], xz[N];  // xz: the thread's z-line of x, for the fused <x, y>
-  face_phase<N, 2, BX, BY, BZ, TC, TIN, TRANS>(m, T, x, act, e, c, o, Nd, t, t1, t2, F, Fe, K, G[4], G[5], cr, b,
+  face_phase<N, 2, BX, BY, BZ, FS, TC, TIN, TRANS>(m, T, x, act, e, c, o, Nd, t, t1, t2, F, Fe, K, G[4], G[5], cr, b,
                                                DOT ? xz : nullptr);
   {
     lds_get<N, 2>(S1, t1, t2, v);

@@ -171,3 +171,24 @@ def test_full_size_exact_solution():
         err = rel_l2(host(x), x_ex)
         print(f"cg {prec} {mode} {var} 32^3 Q3 K=1: solution rel err vs exact solve {err:.3e}")
         assert err <= 1e-7
+
+
+def test_mixed_precision_solves_repeat_exactly():
+    """Repeated FP32 and BF16 defect-correction solves of the 32^3 Q3 workload
+    (and FP64 PCG) return the same iteration counts and bit-identical
+    solutions: every reduction is deterministic and no kernel may depend on
+    stale data from an earlier launch."""
+    banner("cg repeatability")
+    N, k = 32, 3
+    op = DGOperator(N, N, N, k, "dirichlet", theta=dev(I.theta(N ** 3)))
+    b = _sine_rhs(op)
+    for prec, mode in (("f64", "restart"), ("f32", "restart"), ("bf16", "restart"), ("f32", "keep")):
+        first = None
+        for rep in range(4):
+            x, info = op.cg_solve(b, prec_inner=prec, rtol=1e-10, dc_mode=mode)
+            assert info["status"] == DG_OK
+            if first is None:
+                first = (info["iters"], x.clone())
+            else:
+                assert info["iters"] == first[0], (prec, mode, rep, info["iters"], first[0])
+                assert torch.equal(x, first[1]), (prec, mode, rep)
