@@ -48,6 +48,20 @@ def test_small_perturbed(k, bc):
         assert rel_l2(y, A @ x) <= 1e-12, (shape, k, bc)
 
 
+@pytest.mark.parametrize("shape", [(1, 2, 3), (2, 1, 1), (1, 1, 1)])
+@pytest.mark.parametrize("k", [2, 3])
+def test_periodic_self_neighbour(shape, k):
+    """Periodic meshes one element wide along some axes: the element is its own
+    neighbour there, so the face it evaluates for both sides in the first pass
+    of the apply feeds its own lower face in the second."""
+    banner(f"trilinear periodic self-neighbour {shape} k={k}")
+    V = box_vertices(*shape, seed=13)
+    m, op, x = _run(shape, k, "periodic", V, seed=3)
+    A = O.assemble(m)
+    y = host(op.apply(dev(x)))
+    assert rel_l2(y, A @ x) <= 1e-12, (shape, k)
+
+
 @pytest.mark.parametrize("shape,k", [((5, 4, 3), 3), ((4, 3, 5), 2), ((3, 3, 2), 5)])
 def test_ragged_perturbed(shape, k):
     banner(f"trilinear ragged {shape} k={k}")
