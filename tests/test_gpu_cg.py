@@ -182,10 +182,12 @@ def test_mixed_precision_solves_repeat_exactly():
     N, k = 32, 3
     op = DGOperator(N, N, N, k, "dirichlet", theta=dev(I.theta(N ** 3)))
     b = _sine_rhs(op)
-    for prec, mode in (("f64", "restart"), ("f32", "restart"), ("bf16", "restart"), ("f32", "keep")):
+    for prec, mode, var in (("f64", "restart", "standard"), ("f64", "restart", "single_reduction"),
+                            ("f32", "restart", "standard"), ("bf16", "restart", "standard"),
+                            ("f32", "keep", "standard")):
         first = None
         for rep in range(4):
-            x, info = op.cg_solve(b, prec_inner=prec, rtol=1e-10, dc_mode=mode)
+            x, info = op.cg_solve(b, prec_inner=prec, rtol=1e-10, dc_mode=mode, variant=var)
             assert info["status"] == DG_OK
             if first is None:
                 first = (info["iters"], x.clone())
