@@ -242,8 +242,9 @@ def test_repeatable_with_changing_inputs():
     trilinear meshes: a kernel reading LDS data of another element or of an
     earlier phase before it is rewritten would see the other input's values."""
     banner("repeatability with changing inputs")
-    for verts in (None, I.perturbed_vertices(8, 0.1, seed=3)):
-        N, k = (32, 3) if verts is None else (8, 3)
+    cases = [(32, 3, None), (12, 1, None), (6, 7, None), (8, 3, I.perturbed_vertices(8, 0.1, seed=3)),
+             (4, 7, I.perturbed_vertices(4, 0.1, seed=4))]
+    for N, k, verts in cases:
         op = DGOperator(N, N, N, k, "dirichlet", theta=dev(I.theta(N ** 3)),
                         vertices=None if verts is None else dev(verts))
         xs = [dev(I.uniform_vector(op.ndof, seed=s)) for s in (21, 22)]
@@ -253,4 +254,4 @@ def test_repeatable_with_changing_inputs():
             ref = [op.apply(X[0], prec=prec).clone(), op.apply(X[1], prec=prec).clone()]
             for r in range(40):
                 y = op.apply(X[r % 2], prec=prec)
-                assert torch.equal(y, ref[r % 2]), (verts is None, prec, r)
+                assert torch.equal(y, ref[r % 2]), (N, k, verts is None, prec, r)
