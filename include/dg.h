@@ -104,7 +104,10 @@ int dg_set_reaction(dg_ctx* ctx, const double* c, void* stream);
 
 /* y = A x (Sec. 3.3 operator application; form of Sec. 4.1).  x and y are
  * device vectors of N_dof = nx*ny*nz*(k+1)^3 entries of the types given by
- * `prec` (enum dg_precision); x == y is rejected (DG_ERR_ARG). */
+ * `prec` (enum dg_precision); x == y is rejected (DG_ERR_ARG).  On trilinear
+ * meshes the apply runs in two passes that exchange face data through the
+ * context's workspace, so applies (and solves) on one such context must not
+ * overlap in time: issue them on one stream or order them with events. */
 int dg_apply(dg_ctx* ctx, int prec, const void* x, void* y, void* stream);
 
 /* y = A^T x.  Affine meshes: evaluated from the transposed 1D operators and
