@@ -685,11 +685,23 @@ int pcg64(dg_ctx* c, const dg_cg_opts* o, const double* b, double* x, int maxit,
   CgState hs;
   int rc = read_state(c, 0, hs, s);
   if (rc != DG_OK) return rc;
+  // few block partials: the update kernels sum them themselves (no finish kernels)
+  const int64_t nbA = c->trilinear ? element_blocks(c->n, c->E) : affine_tiles(c->n, c->desc.nx, c->desc.ny,
+                                                                               c->desc.nz);
+  const bool fused = nbA <= 4096 && 2 * vec_blocks(n) <= 8192;
+  double* partA = c->partials;
+  double* partB = c->partials + nbA;
   int it = 0;
   while (!hs.done && it < maxit) {
     const int chunk = std::min(check, maxit - it);
     for (int j = 0; j < chunk; ++j, ++it) {
       const int par = it & 1;
+      if (fused) {
+        HIP_TRY(c, apply_any(c, DG_F64, o->transpose, 1, c->p64, c->q64, nullptr, 0, &st->done, s, partA));
+        HIP_TRY(c, launch_cg_update_fused(n, c->r64, c->q64, dinv, par, st, partA, nbA, partB, s));
+        HIP_TRY(c, launch_cg_pupdate_fused(n, x, c->r64, c->p64, dinv, par, st, partB, s));
+        continue;
+      }
       HIP_TRY(c, apply_any(c, DG_F64, o->transpose, 1, c->p64, c->q64, st, par, &st->done, s));
       HIP_TRY(c, (launch_cg_update<double, double>(n, c->r64, c->q64, dinv, par, st, c->partials, s)));
       HIP_TRY(c, (launch_cg_pupdate<double, double, double, double>(n, x, c->r64, c->p64, dinv, par, st, 0, s)));

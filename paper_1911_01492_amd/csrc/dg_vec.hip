@@ -188,6 +188,97 @@ __global__ __launch_bounds__(kBlock) void k_cg_pupdate(int64_t n, TX* __restrict
   }
 }
 
+// FP64 PCG without the single-workgroup finish kernels, for problems whose
+// block partials are few (the vectors then sit in the last-level cache and
+// a finish launch is a large part of an iteration).  Every block of the
+// consuming kernel sums the producer's partials itself, in the same fixed
+// order, so all blocks obtain bit-identical scalars; block 0 records them in
+// the state.  No block writes a state field that other blocks of the same
+// kernel read.
+//
+// update: pq = sum of the apply's partials (partA), lambda = rho / pq; on a
+// breakdown block 0 stops the solve; otherwise r -= lambda q with partials
+// {<z, r>, <r, r>} into partB, and block 0 records pq and a pending x update.
+template <typename TV, typename TD, bool SEQ>
+__global__ __launch_bounds__(kBlock) void k_cg_update_fused(int64_t n, TV* __restrict__ r, const TV* __restrict__ q,
+                                                            const TD* __restrict__ dinv, int par, CgState* st,
+                                                            const double* partA, int64_t nbA, double* partB) {
+  const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+  if (st->done) {
+    if (lead) st->xpend = 0;
+    return;
+  }
+  double t[1];
+  sum_partials<1, kBlock>(partA, nbA, t);
+  const double pq = t[0], lam = st->rho[par] / pq;
+  if (!(pq > 0.0) || !finite_d(lam)) {
+    if (lead) {
+      st->pq = pq;
+      st->xpend = 0;
+      st->breakdown = 1;
+      st->done = 1;
+    }
+    return;
+  }
+  if (lead) {
+    st->pq = pq;
+    st->xpend = 1;
+  }
+  __syncthreads();  // the partial-sum scratch of sum_partials is reused below
+  if constexpr (SEQ) {
+    cg_update_seq<TV, TD>(n, r, q, dinv, lam, partB);
+  } else {
+    if (dinv) cg_update_body<TV, TD, true>(n, r, q, dinv, lam, partB);
+    else cg_update_body<TV, TD, false>(n, r, q, dinv, lam, partB);
+  }
+}
+
+// x/p update: when the update ran (xpend), rho' = <z, r> and <r, r> from
+// partB decide convergence; x += lambda p and, unless the solve stops,
+// p = z + (rho' / rho) p.  Block 0 records rho', <r, r>, the iteration count
+// and the stop (xpend is cleared by the next update).
+template <typename TX, typename TV, typename TP, typename TD, bool SEQ>
+__global__ __launch_bounds__(kBlock) void k_cg_pupdate_fused(int64_t n, TX* __restrict__ x, const TV* __restrict__ r,
+                                                             TP* __restrict__ p, const TD* __restrict__ dinv,
+                                                             int par, CgState* st, const double* partB,
+                                                             int64_t nbB) {
+  if (!st->xpend) return;
+  double t[2];
+  sum_partials<2, kBlock>(partB, nbB, t);
+  const double rz = t[0], rr = t[1];
+  const bool bad = !finite_d(rz) || !finite_d(rr);
+  const bool conv = rr <= st->tol2;
+  const bool pu = !(conv || bad);
+  const double lam = st->rho[par] / st->pq;
+  const double beta = pu ? rz / st->rho[par] : 0.0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st->rho[par ^ 1] = rz;
+    st->rr = rr;
+    st->iters += 1;
+    if (conv) st->done = 1;
+    if (bad) {
+      st->breakdown = 1;
+      st->done = 1;
+    }
+  }
+  if constexpr (SEQ) {
+    DG_VEC_LOOP(i, k, n) {
+      const double pi = p_load<TP>(p, i);
+      x[i] = (TX)((double)x[i] + lam * pi);
+      if (pu) {
+        const double ri = (double)r[i];
+        const double z = dinv ? (double)dinv[i] * ri : ri;
+        p_store<TP>(p, i, z + beta * pi);
+      }
+    }
+  } else if (pu) {
+    if (dinv) cg_pupdate_body<TX, TV, TP, TD, true, true, true>(n, x, r, p, dinv, lam, beta);
+    else cg_pupdate_body<TX, TV, TP, TD, true, true, false>(n, x, r, p, dinv, lam, beta);
+  } else {
+    cg_pupdate_body<TX, TV, TP, TD, true, false, false>(n, x, r, p, dinv, lam, beta);
+  }
+}
+
 // FP64 outer residual of the defect correction: r64 = b - q64, r32 = fp32(r64);
 // partials {<r64, r64>, <b, b>}
 __global__ __launch_bounds__(kBlock) void k_dc_residual(int64_t n, const double* __restrict__ b,
@@ -479,6 +570,29 @@ hipError_t launch_cg_pupdate(int64_t n, TX* x, const TV* r, TP* p, const TD* din
   else
     hipLaunchKernelGGL((k_cg_pupdate<TX, TV, TP, TD, false>), dim3((unsigned)vec_blocks(n)), dim3(kBlock), 0, s, n,
                        x, r, p, dinv, par, st, force_p);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_update_fused(int64_t n, double* r, const double* q, const double* dinv, int par, CgState* st,
+                                  const double* partA, int64_t nbA, double* partB, hipStream_t s) {
+  const int64_t nb = vec_blocks(n);
+  if (seq_form<double>(n))
+    hipLaunchKernelGGL((k_cg_update_fused<double, double, true>), dim3((unsigned)nb), dim3(kBlock), 0, s, n, r, q,
+                       dinv, par, st, partA, nbA, partB);
+  else
+    hipLaunchKernelGGL((k_cg_update_fused<double, double, false>), dim3((unsigned)nb), dim3(kBlock), 0, s, n, r, q,
+                       dinv, par, st, partA, nbA, partB);
+  return hipGetLastError();
+}
+hipError_t launch_cg_pupdate_fused(int64_t n, double* x, const double* r, double* p, const double* dinv, int par,
+                                   CgState* st, const double* partB, hipStream_t s) {
+  const int64_t nb = vec_blocks(n);
+  if (seq_form<double>(n))
+    hipLaunchKernelGGL((k_cg_pupdate_fused<double, double, double, double, true>), dim3((unsigned)nb),
+                       dim3(kBlock), 0, s, n, x, r, p, dinv, par, st, partB, nb);
+  else
+    hipLaunchKernelGGL((k_cg_pupdate_fused<double, double, double, double, false>), dim3((unsigned)nb),
+                       dim3(kBlock), 0, s, n, x, r, p, dinv, par, st, partB, nb);
   return hipGetLastError();
 }
 
