@@ -698,8 +698,9 @@ int pcg64(dg_ctx* c, const dg_cg_opts* o, const double* b, double* x, int maxit,
       const int par = it & 1;
       if (fused) {
         HIP_TRY(c, apply_any(c, DG_F64, o->transpose, 1, c->p64, c->q64, nullptr, 0, &st->done, s, partA));
-        HIP_TRY(c, launch_cg_update_fused(n, c->r64, c->q64, dinv, par, st, partA, nbA, partB, s));
-        HIP_TRY(c, launch_cg_pupdate_fused(n, x, c->r64, c->p64, dinv, par, st, partB, s));
+        HIP_TRY(c, (launch_cg_update_fused<double, double>(n, c->r64, c->q64, dinv, par, st, partA, nbA, partB, s)));
+        HIP_TRY(c, (launch_cg_pupdate_fused<double, double, double, double>(n, x, c->r64, c->p64, dinv, par, st, partB,
+                                                                            s)));
         continue;
       }
       HIP_TRY(c, apply_any(c, DG_F64, o->transpose, 1, c->p64, c->q64, st, par, &st->done, s));
@@ -786,11 +787,23 @@ int pcg_inner(dg_ctx* c, const dg_cg_opts* o, int prec, bool fresh, double inner
   CgState hs;
   int rc = read_state(c, 1, hs, s);
   if (rc != DG_OK) return rc;
+  // few block partials: the update kernels sum them themselves (no finish kernels)
+  const int64_t nbA = c->trilinear ? element_blocks(c->n, c->E) : affine_tiles(c->n, c->desc.nx, c->desc.ny,
+                                                                               c->desc.nz);
+  const bool fused = nbA <= 4096 && 2 * vec_blocks(n) <= 8192;
+  double* partA = c->partials;
+  double* partB = c->partials + nbA;
   int it = 0;
   while (!hs.done && it < maxit) {
     const int chunk = std::min(check, maxit - it);
     for (int j = 0; j < chunk; ++j, ++it) {
       const int par = (par0 + it) & 1;
+      if (fused) {
+        HIP_TRY(c, apply_any(c, prec, o->transpose, 1, p, c->q32, nullptr, 0, &st->done, s, partA));
+        HIP_TRY(c, (launch_cg_update_fused<float, float>(n, c->r32, c->q32, dinv, par, st, partA, nbA, partB, s)));
+        HIP_TRY(c, (launch_cg_pupdate_fused<float, float, TP, float>(n, c->d32, c->r32, p, dinv, par, st, partB, s)));
+        continue;
+      }
       HIP_TRY(c, apply_any(c, prec, o->transpose, 1, p, c->q32, st, par, &st->done, s));
       HIP_TRY(c, (launch_cg_update<float, float>(n, c->r32, c->q32, dinv, par, st, c->partials, s)));
       HIP_TRY(c, (launch_cg_pupdate<float, float, TP, float>(n, c->d32, c->r32, p, dinv, par, st, 0, s)));

@@ -81,13 +81,15 @@ hipError_t launch_dc_update(int64_t n, double* x, float* d, hipStream_t s);
 // partials of the apply (mode 0: after the first apply, 1: every iteration)
 hipError_t launch_cg2_update(int64_t n, double* x, double* r, double* z, double* p, double* s, const double* w,
                              const double* dinv, const CgState* st, double* partials, hipStream_t st_);
-// FP64 PCG update kernels that sum the producer's block partials themselves
+// PCG update kernels that sum the producer's block partials themselves
 // (no finish kernels): partA = the apply's <p, q> partials (nbA of them),
 // partB = the update's {<z, r>, <r, r>} partials (disjoint from partA)
-hipError_t launch_cg_update_fused(int64_t n, double* r, const double* q, const double* dinv, int par, CgState* st,
+template <typename TV, typename TD>
+hipError_t launch_cg_update_fused(int64_t n, TV* r, const TV* q, const TD* dinv, int par, CgState* st,
                                   const double* partA, int64_t nbA, double* partB, hipStream_t s);
-hipError_t launch_cg_pupdate_fused(int64_t n, double* x, const double* r, double* p, const double* dinv, int par,
-                                   CgState* st, const double* partB, hipStream_t s);
+template <typename TX, typename TV, typename TP, typename TD>
+hipError_t launch_cg_pupdate_fused(int64_t n, TX* x, const TV* r, TP* p, const TD* dinv, int par, CgState* st,
+                                   const double* partB, hipStream_t s);
 hipError_t launch_cg2_finish(const double* partA, int64_t nbA, const double* partB, int64_t nbB, CgState* st,
                              int mode, hipStream_t s);
 hipError_t launch_dc_replace(int64_t n, const double* b, const double* q, const float* dinv, float* r32,

@@ -573,28 +573,43 @@ hipError_t launch_cg_pupdate(int64_t n, TX* x, const TV* r, TP* p, const TD* din
   return hipGetLastError();
 }
 
-hipError_t launch_cg_update_fused(int64_t n, double* r, const double* q, const double* dinv, int par, CgState* st,
+template <typename TV, typename TD>
+hipError_t launch_cg_update_fused(int64_t n, TV* r, const TV* q, const TD* dinv, int par, CgState* st,
                                   const double* partA, int64_t nbA, double* partB, hipStream_t s) {
   const int64_t nb = vec_blocks(n);
-  if (seq_form<double>(n))
-    hipLaunchKernelGGL((k_cg_update_fused<double, double, true>), dim3((unsigned)nb), dim3(kBlock), 0, s, n, r, q,
-                       dinv, par, st, partA, nbA, partB);
+  if (seq_form<TV>(n))
+    hipLaunchKernelGGL((k_cg_update_fused<TV, TD, true>), dim3((unsigned)nb), dim3(kBlock), 0, s, n, r, q, dinv,
+                       par, st, partA, nbA, partB);
   else
-    hipLaunchKernelGGL((k_cg_update_fused<double, double, false>), dim3((unsigned)nb), dim3(kBlock), 0, s, n, r, q,
-                       dinv, par, st, partA, nbA, partB);
+    hipLaunchKernelGGL((k_cg_update_fused<TV, TD, false>), dim3((unsigned)nb), dim3(kBlock), 0, s, n, r, q, dinv,
+                       par, st, partA, nbA, partB);
   return hipGetLastError();
 }
-hipError_t launch_cg_pupdate_fused(int64_t n, double* x, const double* r, double* p, const double* dinv, int par,
-                                   CgState* st, const double* partB, hipStream_t s) {
+template <typename TX, typename TV, typename TP, typename TD>
+hipError_t launch_cg_pupdate_fused(int64_t n, TX* x, const TV* r, TP* p, const TD* dinv, int par, CgState* st,
+                                   const double* partB, hipStream_t s) {
   const int64_t nb = vec_blocks(n);
-  if (seq_form<double>(n))
-    hipLaunchKernelGGL((k_cg_pupdate_fused<double, double, double, double, true>), dim3((unsigned)nb),
-                       dim3(kBlock), 0, s, n, x, r, p, dinv, par, st, partB, nb);
+  if (seq_form<TV>(n))
+    hipLaunchKernelGGL((k_cg_pupdate_fused<TX, TV, TP, TD, true>), dim3((unsigned)nb), dim3(kBlock), 0, s, n, x, r,
+                       p, dinv, par, st, partB, nb);
   else
-    hipLaunchKernelGGL((k_cg_pupdate_fused<double, double, double, double, false>), dim3((unsigned)nb),
-                       dim3(kBlock), 0, s, n, x, r, p, dinv, par, st, partB, nb);
+    hipLaunchKernelGGL((k_cg_pupdate_fused<TX, TV, TP, TD, false>), dim3((unsigned)nb), dim3(kBlock), 0, s, n, x,
+                       r, p, dinv, par, st, partB, nb);
   return hipGetLastError();
 }
+template hipError_t launch_cg_update_fused<double, double>(int64_t, double*, const double*, const double*, int,
+                                                           CgState*, const double*, int64_t, double*, hipStream_t);
+template hipError_t launch_cg_update_fused<float, float>(int64_t, float*, const float*, const float*, int, CgState*,
+                                                         const double*, int64_t, double*, hipStream_t);
+template hipError_t launch_cg_pupdate_fused<double, double, double, double>(int64_t, double*, const double*, double*,
+                                                                            const double*, int, CgState*,
+                                                                            const double*, hipStream_t);
+template hipError_t launch_cg_pupdate_fused<float, float, float, float>(int64_t, float*, const float*, float*,
+                                                                       const float*, int, CgState*, const double*,
+                                                                       hipStream_t);
+template hipError_t launch_cg_pupdate_fused<float, float, uint16_t, float>(int64_t, float*, const float*, uint16_t*,
+                                                                          const float*, int, CgState*,
+                                                                          const double*, hipStream_t);
 
 // explicit instantiations used by the host solvers
 template hipError_t launch_cg_init<double, double, double, double>(int64_t, const double*, const double*,
