@@ -166,7 +166,8 @@ typedef struct {
   int maxit;          /* total (inner) CG iterations allowed                          */
   int max_outer;      /* outer corrections allowed (mixed precision)                  */
   int check_every;    /* host looks at the device convergence flag every this many     *
-                       * iterations (>= 1; <= 0: default 8)                            */
+                       * iterations (>= 1; <= 0: default 32; up to this many - 1       *
+                       * iterations after convergence run as no-op launches)           */
   int dc_mode;        /* enum dg_dc_mode (mixed precision only; must be valid always)  */
   int cg_variant;     /* enum dg_cg_variant (prec_inner DG_F64 only for the second)   */
 } dg_cg_opts;

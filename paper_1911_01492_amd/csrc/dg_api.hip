@@ -678,7 +678,7 @@ int pcg64(dg_ctx* c, const dg_cg_opts* o, const double* b, double* x, int maxit,
   const int64_t n = c->ndof;
   const double* dinv = o->precond == DG_PC_JACOBI ? c->dinv64 : nullptr;
   CgState* st = &c->st[0];
-  const int check = o->check_every > 0 ? o->check_every : 8;
+  const int check = o->check_every > 0 ? o->check_every : 32;
   HIP_TRY(c, apply_any(c, DG_F64, o->transpose, 0, x, c->q64, nullptr, 0, nullptr, s));
   HIP_TRY(c, (launch_cg_init<double, double, double, double>(n, b, c->q64, c->r64, c->p64, dinv, o->rtol, st,
                                                             c->partials, s)));
@@ -723,7 +723,7 @@ int pcg64_single(dg_ctx* c, const dg_cg_opts* o, const double* b, double* x, int
   const int64_t n = c->ndof;
   const double* dinv = o->precond == DG_PC_JACOBI ? c->dinv64 : nullptr;
   CgState* st = &c->st[0];
-  const int check = o->check_every > 0 ? o->check_every : 8;
+  const int check = o->check_every > 0 ? o->check_every : 32;
   const int64_t nvb = vec_blocks(n);
   double* partA = c->partials;             // <r, z>, <r, r> of the update (2 per vector block)
   double* partB = c->partials + 2 * nvb;   // <z, w> of the apply
@@ -778,7 +778,7 @@ int pcg_inner(dg_ctx* c, const dg_cg_opts* o, int prec, bool fresh, double inner
   const float* dinv = o->precond == DG_PC_JACOBI ? c->dinv32 : nullptr;
   CgState* st = &c->st[1];
   TP* p = prec == DG_BF16 ? (TP*)c->p16 : (TP*)c->p32;
-  const int check = o->check_every > 0 ? o->check_every : 8;
+  const int check = o->check_every > 0 ? o->check_every : 32;
   if (fresh) {
     par0 = 0;
     HIP_TRY(c, (launch_cg_init_inner<float, TP, float>(n, c->r32, c->d32, p, dinv, inner_rtol, st, c->partials,

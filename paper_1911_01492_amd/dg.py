@@ -224,13 +224,14 @@ class DGOperator:
     def cg_solve(self, b: torch.Tensor, x: Optional[torch.Tensor] = None, prec_inner: str = "f64",
                  precond: str = "jacobi", rtol: float = 1e-10, maxit: int = 100000,
                  inner_rtol: float = 0.0, max_outer: int = 0, transpose: bool = False,
-                 check_every: int = 8, dc_mode: str = "restart", variant: str = "standard", stream=None):
+                 check_every: int = 0, dc_mode: str = "restart", variant: str = "standard", stream=None):
         """Solve A x = b (A^T x = b).  Returns (x, info dict).
 
         prec_inner "f32" / "bf16" selects the FP64 defect correction; dc_mode
         "restart" starts every inner solve afresh, "keep" replaces the inner
         residual by the FP64 one and keeps the search direction.  inner_rtol
-        and max_outer <= 0 take the library defaults."""
+        and max_outer <= 0 take the library defaults, check_every <= 0 its default
+        interval (32 iterations) between looks at the convergence flag."""
         self._vec(b, torch.float64)
         x = torch.zeros_like(b) if x is None else self._vec(x, torch.float64)
         o = CgOpts(PREC[prec_inner], PRECOND[precond], 1 if transpose else 0, rtol, inner_rtol, maxit,
