@@ -194,3 +194,39 @@ def test_mixed_precision_solves_repeat_exactly():
             else:
                 assert info["iters"] == first[0], (prec, mode, rep, info["iters"], first[0])
                 assert torch.equal(x, first[1]), (prec, mode, rep)
+
+
+@pytest.mark.parametrize("shape,k,bc,react", [((5, 4, 3), 3, "dirichlet", False),
+                                              ((1, 2, 3), 2, "periodic", False),
+                                              ((4, 3, 5), 4, "dirichlet", True),
+                                              ((2, 3, 2), 7, "periodic", True),
+                                              ((3, 3, 3), 1, "dirichlet", True)])
+def test_jacobi_iterates_match_oracle(shape, k, bc, react):
+    """The Jacobi preconditioner of the FP64 PCG.  The iterate after a fixed
+    number of steps depends on every entry of the inverse diagonal at first
+    order, so it is compared with the oracle's PCG (diagonal taken from its CSR
+    matrix) after the same number of steps, on meshes with self-neighbours
+    (periodic, one element wide), with a reaction term, and again after new
+    coefficients (set_theta must refresh the preconditioner)."""
+    banner(f"jacobi iterates {shape} k={k} {bc} reaction={react}")
+    E = int(np.prod(shape))
+    bcc = {"dirichlet": O.DIRICHLET, "periodic": O.PERIODIC}[bc]
+    theta = I.theta(E, seed=11)
+    c = I.reaction(E, seed=12) if react else None
+    op = DGOperator(*shape, k, bc, theta=dev(theta))
+    if react:
+        op.set_reaction(dev(c))
+    b = dev(I.uniform_vector(op.ndof, seed=13))
+    for th in (theta, I.theta(E, seed=14)):
+        op.set_theta(dev(th))
+        A = O.assemble(O.Mesh(*shape, k, bc=bcc, theta=th, reaction=c))
+        for steps in (1, 10):
+            x, info = op.cg_solve(b, rtol=1e-30, maxit=steps)
+            assert info["iters"] == steps
+            x_ref, it, _ = O.pcg(A, host(b), rtol=1e-30, maxit=steps)
+            assert it == steps
+            err = rel_l2(host(x), x_ref)
+            print(f"{steps} steps: rel diff vs oracle PCG {err:.2e}")
+            assert err <= 1e-12
+        # the diagonal itself, through the library's separate diagonal kernel
+        assert rel_l2(host(op.diagonal()), A.diagonal()) <= 1e-14
