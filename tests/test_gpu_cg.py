@@ -196,30 +196,34 @@ def test_mixed_precision_solves_repeat_exactly():
                 assert torch.equal(x, first[1]), (prec, mode, rep)
 
 
-@pytest.mark.parametrize("shape,k,bc,react", [((5, 4, 3), 3, "dirichlet", False),
-                                              ((1, 2, 3), 2, "periodic", False),
-                                              ((4, 3, 5), 4, "dirichlet", True),
-                                              ((2, 3, 2), 7, "periodic", True),
-                                              ((3, 3, 3), 1, "dirichlet", True)])
-def test_jacobi_iterates_match_oracle(shape, k, bc, react):
+@pytest.mark.parametrize("shape,k,bc,react,tri", [((5, 4, 3), 3, "dirichlet", False, False),
+                                                  ((1, 2, 3), 2, "periodic", False, False),
+                                                  ((4, 3, 5), 4, "dirichlet", True, False),
+                                                  ((2, 3, 2), 7, "periodic", True, False),
+                                                  ((3, 3, 3), 1, "dirichlet", True, False),
+                                                  ((3, 4, 3), 3, "dirichlet", True, True),
+                                                  ((2, 1, 3), 2, "periodic", False, True)])
+def test_jacobi_iterates_match_oracle(shape, k, bc, react, tri):
     """The Jacobi preconditioner of the FP64 PCG.  The iterate after a fixed
     number of steps depends on every entry of the inverse diagonal at first
     order, so it is compared with the oracle's PCG (diagonal taken from its CSR
     matrix) after the same number of steps, on meshes with self-neighbours
     (periodic, one element wide), with a reaction term, and again after new
     coefficients (set_theta must refresh the preconditioner)."""
-    banner(f"jacobi iterates {shape} k={k} {bc} reaction={react}")
+    banner(f"jacobi iterates {shape} k={k} {bc} reaction={react} trilinear={tri}")
+    from tests.test_gpu_trilinear import box_vertices
     E = int(np.prod(shape))
     bcc = {"dirichlet": O.DIRICHLET, "periodic": O.PERIODIC}[bc]
     theta = I.theta(E, seed=11)
     c = I.reaction(E, seed=12) if react else None
-    op = DGOperator(*shape, k, bc, theta=dev(theta))
+    V = box_vertices(*shape, amp=0.1, seed=15) if tri else None
+    op = DGOperator(*shape, k, bc, theta=dev(theta), vertices=None if V is None else dev(V))
     if react:
         op.set_reaction(dev(c))
     b = dev(I.uniform_vector(op.ndof, seed=13))
     for th in (theta, I.theta(E, seed=14)):
         op.set_theta(dev(th))
-        A = O.assemble(O.Mesh(*shape, k, bc=bcc, theta=th, reaction=c))
+        A = O.assemble(O.Mesh(*shape, k, bc=bcc, theta=th, vertices=V, reaction=c))
         for steps in (1, 10):
             x, info = op.cg_solve(b, rtol=1e-30, maxit=steps)
             assert info["iters"] == steps
