@@ -439,11 +439,13 @@ __global__ __launch_bounds__(apply_block(N)) void k_apply_affine(MeshArgs<TC> m,
   double part = 0.0;
   lds_get<N, 2>(S2, t1, t2, v);
   if (act) {
+    // y is written once and not read back here: nontemporal stores keep it
+    // from displacing in L2 the x lines that neighbouring bricks still read
     TOUT* py = y + e * N3;
 #pragma unroll
     for (int i = 0; i < N; ++i) {
       const TOUT yv = (TOUT)(r[i] + v[i]);
-      py[lidx<N, 2>(t1, t2, i)] = yv;
+      __builtin_nontemporal_store(yv, &py[lidx<N, 2>(t1, t2, i)]);
       if (DOT) part += (double)xz[i] * (double)yv;
     }
   }
