@@ -293,8 +293,9 @@ __device__ void face_term(const MeshArgs<TC>& m, const Tables<TC>& T, const TIN*
     lds_put<N, D>(Y, t1, t2, yl);
     if (PAIR && nb >= 0) {  // the neighbour's line (t1, t2) along D, added by its second pass
       TC* fbn = m.fb + ((int64_t)nb * 3 + D) * 2 * NN;
-      fbn[t] = outn;
-      fbn[NN + t] = zn;
+      // read once, by the second pass: stored nontemporal
+      __builtin_nontemporal_store(outn, &fbn[t]);
+      __builtin_nontemporal_store(zn, &fbn[NN + t]);
     }
   }
 }
@@ -524,7 +525,9 @@ __global__ __launch_bounds__(kBlock) void k_apply_trilinear(MeshArgs<TC> m, cons
     lds_get<N, 2>(C, t1, t2, o);
     TOUT* py = y + e * N3;
 #pragma unroll
-    for (int i = 0; i < N; ++i) py[lidx<N, 2>(t1, t2, i)] = (TOUT)o[i];
+    // y and the face buffer are not read again in this pass: nontemporal
+    // stores leave L2 to the x lines the face phases re-read
+    for (int i = 0; i < N; ++i) __builtin_nontemporal_store((TOUT)o[i], &py[lidx<N, 2>(t1, t2, i)]);
   }
 }
 
@@ -572,7 +575,7 @@ __global__ __launch_bounds__(kBlock) void k_tri_lower(MeshArgs<TC> m, const TIN*
 #pragma unroll
     for (int i = 0; i < N; ++i) {
       const TOUT v = (TOUT)o[i];
-      py[lidx<N, 2>(t1, t2, i)] = v;
+      __builtin_nontemporal_store(v, &py[lidx<N, 2>(t1, t2, i)]);
       if (DOT) part += (double)uz[i] * (double)v;
     }
   }
