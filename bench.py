@@ -1,17 +1,19 @@
 #!/usr/bin/env python3
 """Benchmark of the matrix-free SWIPDG operator application on one MI355X.
 
-Headline: GDOF/s of the FP64 sum-factorised apply y = A x on the 32^3-element
-Q3 Dirichlet workload with a lognormal coefficient per element (2.10M DOF),
+Headline: GDOF/s of the FP64 sum-factorised apply y = A x on the 64^3-element
+Q4 Dirichlet workload with a lognormal coefficient per element (32.8M DOF),
 inputs resident in device memory, K timed back-to-back launches bracketed by
-device synchronisation and HIP events on the launch stream.
+device synchronisation and HIP events on the launch stream.  The roofline
+fraction is taken from launches with the last-level cache flushed before each
+one (the warm figure is reported beside it).
 
 The same JSON line also carries the other rows of the hot path, each run once
-(or timed over a few repetitions): FP32 / BF16 applies on the 64^3 Q4
-workload, FP64 PCG and FP64 defect-correction CG (FP32 and BF16 inner solves)
-times to a true relative residual of 1e-10, the adjoint gradient, the
-trilinear Q7 apply, plus the roofline of the dominant kernel and the CPU
-oracle timed on a bounded sample (``cpu_baseline``).
+(or timed over a few repetitions): FP32 / BF16 applies on the same workload,
+FP64 PCG and FP64 defect-correction CG (FP32 and BF16 inner solves) times to a
+true relative residual of 1e-10, the 32^3 Q3 apply and solves, the adjoint
+gradient, the trilinear Q7 apply, plus the CPU oracle timed on bounded
+samples (``cpu_baseline``).
 
     python bench.py [--gpus 1] [--steps 50] [--warmup 10] [--no-extras] [--no-cpu-baseline]
 """
@@ -54,11 +56,13 @@ def flops_per_dof(n: int, trilinear: bool = False) -> float:
     """Algorithmic flops per DOF of one sum-factorised apply (not the 2 * 7 n^3
     of the dense product it avoids): affine, collapsed Kronecker sum with the
     face terms counted once per element side, 14 n + 48; trilinear quadrature
-    form, 12 (n + 2) (twelve volume contractions by the even-odd halves of the
-    1D tables: n + 2 flops per output instead of 2 n) + 120 (J, det J, J^-1 and
-    G per point) + 168 (face contractions) + 810 / n (face geometry)."""
+    form, 24 n (twelve full-length 1D volume contractions, 2 n flops per
+    output) + 120 (J, det J, J^-1 and G per point) + 168 (face contractions) +
+    810 / n (face geometry), about 581 at n = 8.  The kernels evaluate some
+    contractions with fewer operations (even-odd halves of the symmetric 1D
+    tables); the model counts the method's work, not the implementation's."""
     if trilinear:
-        return 12 * (n + 2) + 120 + 168 + 810 / n
+        return 24 * n + 120 + 168 + 810 / n
     return 14 * n + 48
 
 
@@ -125,9 +129,10 @@ def cold_apply(op, x, prec, reps, torch):
     return float(np.median(ts))
 
 
+HEADLINE = "mixed_q4_64"
 KERNEL_SOURCES = ("paper_1911_01492_amd/csrc/dg_affine.hip", "paper_1911_01492_amd/csrc/dg_lines.hpp",
                   "paper_1911_01492_amd/csrc/dg_internal.hpp")
-TRAFFIC_PROFILE = "profiles/k_apply_affine_q3_32_f64.txt"
+TRAFFIC_PROFILE = "profiles/k_apply_affine_q4_64_f64.txt"
 
 
 def measured_traffic():
@@ -149,13 +154,16 @@ def measured_traffic():
     return float(fields["traffic_bytes_per_launch"])
 
 
-def cpu_baseline(seconds: float = 12.0):
-    """The CPU oracle (CSR assembled by brute-force quadrature, OpenMP SpMV in
-    FP64), timed on this host on a bounded sample of the headline workload:
-    the same Q3 / lognormal-K Dirichlet problem on 16^3 elements (1/8 of it)."""
+def cpu_baseline(spmv_seconds: float = 8.0):
+    """The CPU oracle (CSR assembled by brute-force quadrature, OpenMP SpMV and
+    Alg. PCG in FP64), timed on this host on bounded samples of the headline
+    workload (Q4, lognormal K per element, weak Dirichlet; the full 64^3 CSR
+    would take about 340 GB): SpMV throughput on 16^3 elements (1/64 of it),
+    and the Jacobi PCG time to a relative residual of 1e-10 with b ~ U(-1,1)
+    on 8^3 elements."""
     from oracle import oracle as O
     from paper_1911_01492_amd import inputs as I
-    N, k = 16, 3
+    N, k = 16, 4
     m = O.Mesh(N, N, N, k, theta=I.theta(N ** 3))
     t0 = time.perf_counter()
     A = O.assemble(m)
@@ -164,16 +172,28 @@ def cpu_baseline(seconds: float = 12.0):
     O.spmv(A, x)
     reps, t = 0, 0.0
     t0 = time.perf_counter()
-    while t < seconds and reps < 1000:
+    while t < spmv_seconds and reps < 1000:
         O.spmv(A, x)
         reps += 1
         t = time.perf_counter() - t0
     per = t / reps
+    nnz = A.nnz
+    del A
+    Ns = 8
+    ms = O.Mesh(Ns, Ns, Ns, k, theta=I.theta(Ns ** 3))
+    As = O.assemble(ms)
+    bs = I.uniform_vector(ms.ndof, seed=I.S_B)
+    t0 = time.perf_counter()
+    _, its, rel = O.pcg(As, bs, rtol=1e-10, maxit=100000)
+    t_cg = time.perf_counter() - t0
     return {"value": m.ndof / per / 1e9, "unit": "GDOF/s", "cores": O.num_threads(), "kind": "oracle",
-            "sample": f"CSR SpMV of the Q3 lognormal-K Dirichlet operator on 16^3 elements "
-                      f"({m.ndof} DOF, {A.nnz} stored entries), {reps} products in {t:.1f} s; "
+            "sample": f"CSR SpMV of the Q4 lognormal-K Dirichlet operator on 16^3 elements "
+                      f"({m.ndof} DOF, {nnz} stored entries), {reps} products in {t:.1f} s; "
                       f"CSR assembly took {t_asm:.1f} s",
-            "assembly_s": t_asm, "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
+            "assembly_s": t_asm, "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
+            "solve": {"value": round(t_cg, 4), "unit": "s", "iters": its, "rel_true_residual": rel,
+                      "sample": f"oracle Jacobi PCG (Alg. PCG) to 1e-10 on the Q4 lognormal-K Dirichlet "
+                                f"operator on 8^3 elements ({ms.ndof} DOF), b ~ U(-1,1) seed 2"}}
 
 
 def main():
@@ -210,22 +230,24 @@ def main():
         log("copy calibration: 5 x 256 MiB device-to-device copies")
         del src, dst
 
-    # ------------------------------------------------------------ headline
-    wl = "dirichlet_q3_32"
+    # ------------------------------------------------------------ headline: 64^3 Q4, FP64
+    wl = HEADLINE
     cfg = I.WORKLOADS[wl]
     N, k = cfg["N"], cfg["k"]
     n = k + 1
     theta = I.theta(N ** 3)
     op = DGOperator(N, N, N, k, "dirichlet", theta=dev(theta))
-    x = dev(I.uniform_vector(op.ndof))
+    xh = I.uniform_vector(op.ndof)
+    x = dev(xh)
     log(f"headline {wl}: {op.ndof} DOF, warmup {args.warmup}, steps {args.steps}")
     t, y = time_apply(op, x, "f64", args.steps, args.warmup, torch)
     per = t / args.steps
     gdofs = op.ndof * args.steps / t / 1e9
     bpd = alg_bytes_per_dof(n, 8, 8, 8)
-    achieved = bpd * op.ndof / per / 1e9
-    t_cold = cold_apply(op, x, "f64", 10, torch)
-    t_med, t_min = launch_stats(op, x, "f64", 50, torch)
+    warm_achieved = bpd * op.ndof / per / 1e9
+    t_cold = cold_apply(op, x, "f64", 20, torch)
+    cold_achieved = bpd * op.ndof / t_cold / 1e9
+    t_med, t_min = launch_stats(op, x, "f64", 20, torch)
     fpd = flops_per_dof(n)
     result = {
         "metric": "GDOF/s of SIPG apply (fp64 vs fp32/bf16) + CG time-to-1e-10 residual",
@@ -242,20 +264,27 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl, "elements": f"{N}^3", "degree": k, "ndof": op.ndof,
                    "bc": "weak Dirichlet", "coefficient": "K=exp(g), g~N(0,1) per element, seed 1",
-                   "x": "U(-1,1), seed 0", "step": "one FP64 operator application y = A x"},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
-                     "kernel": "k_apply_affine<4,double,double,double,false,false>",
-                     "alg_bytes_per_dof": round(bpd, 4), "avg_launch_us": round(per * 1e6, 3),
-                     "isolated_launch_median_us": round(t_med * 1e6, 3), "isolated_launch_min_us": round(t_min * 1e6, 3),
+                   "x": "U(-1,1), seed 0", "step": "one FP64 operator application y = A x",
+                   "low_precision_and_cg": "FP32 / BF16 applies and the FP64 / mixed-precision CG times "
+                                           "to 1e-10 of the same workload are in extras"},
+        # the reported fraction is the cache-flushed one: a 1 GiB buffer is
+        # rewritten before each timed launch, so x, y and K come from HBM
+        "roofline": {"bound": "hbm", "achieved": round(cold_achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(cold_achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
+                     "kernel": f"k_apply_affine<{n},double,double,double,false,false>",
+                     "alg_bytes_per_dof": round(bpd, 4), "alg_bytes_per_launch": round(bpd * op.ndof),
+                     "cold_launch_us": round(t_cold * 1e6, 3),
+                     "warm_launch_us": round(per * 1e6, 3),
+                     "warm_achieved": round(warm_achieved, 1),
+                     "warm_frac": round(warm_achieved / HBM_PEAK_GBS, 4),
+                     "isolated_launch_median_us": round(t_med * 1e6, 3),
+                     "isolated_launch_min_us": round(t_min * 1e6, 3),
                      "alg_flops_per_dof": fpd,
                      "fp64_tflops": round(fpd * op.ndof / per / 1e12, 3),
-                     "fp64_frac": round(fpd * op.ndof / per / 1e12 / FP64_PEAK_TFS, 4),
-                     "cold_launch_us": round(t_cold * 1e6, 3),
-                     "cold_achieved": round(bpd * op.ndof / t_cold / 1e9, 1)},
+                     "fp64_frac": round(fpd * op.ndof / per / 1e12 / FP64_PEAK_TFS, 4)},
         "paper_context": {"note": "Table 'Full operator application' (Sec. 3.3), matrix-free problem A, "
-                                  "p=3, 2x Xeon E5-2698v3 (32 cores), problem size not stated",
-                          "dofs_per_s": 5.3775e8},
+                                  "p=4, 2x Xeon E5-2698v3 (32 cores), problem size not stated",
+                          "dofs_per_s": 5.95014e8},
     }
     extras = {}
     only = set(filter(None, args.only.split(",")))
@@ -263,72 +292,78 @@ def main():
     def want(name):
         return not args.no_extras and (not only or name in only)
 
-    # ------------------------------------------------------------ CG on the headline workload
-    if want("cg_q3_32"):
-        xq = op.quadrature_points()
-        fq = 3 * math.pi ** 2 * torch.sin(math.pi * xq[:, 0]) * torch.sin(math.pi * xq[:, 1]) * \
-            torch.sin(math.pi * xq[:, 2])
-        b = op.load_vector(fq.contiguous())
-        for prec, mode in CG_VARIANTS:
-            kw = {"variant": "single_reduction"} if mode == "single_reduction" else {"dc_mode": mode}
-            op.cg_solve(b, prec_inner=prec, rtol=1e-10, **kw)  # warm
-            u, info = op.cg_solve(b, prec_inner=prec, rtol=1e-10, **kw)
-            tag = (prec if mode == "restart" else f"{prec}_{mode}") if prec == "f64" else f"{prec}_{mode}"
-            extras[f"cg_{tag}_q3_32"] = info
-            log(f"cg {tag} q3_32: {info}")
-        del u, b, fq, xq
-    del op, x, y
-    torch.cuda.empty_cache()
-
-    # ------------------------------------------------------------ mixed precision workload (64^3 Q4)
+    # ------------------------------------------------------------ FP32 / BF16 applies and CG on the same workload
     if want("mixed_q4_64"):
-        wl3 = "mixed_q4_64"
-        c3 = I.WORKLOADS[wl3]
-        N3_, k3 = c3["N"], c3["k"]
-        n3 = k3 + 1
-        th3 = I.theta(N3_ ** 3)
-        op3 = DGOperator(N3_, N3_, N3_, k3, "dirichlet", theta=dev(th3))
-        xh = I.uniform_vector(op3.ndof)
         bits = I.to_bf16_bits(xh)
-        X = {"f64": dev(xh), "f32": dev(I.to_f32(xh), torch.float32),
+        X = {"f32": dev(I.to_f32(xh), torch.float32),
              "bf16": torch.from_numpy(bits.astype(np.int16)).view(torch.bfloat16).cuda()}
         del bits
-        ref = None
-        for prec, (ib, ob) in (("f64", (8, 8)), ("f32", (4, 4)), ("bf16", (2, 4))):
-            tt, yy = time_apply(op3, X[prec], prec, 20, 5, torch)
+        extras[f"apply_f64_{wl}"] = {"gdofs": round(gdofs, 3), "ms": round(per * 1e3, 4),
+                                     "cold_ms": round(t_cold * 1e3, 4),
+                                     "frac_hbm_cold": round(cold_achieved / HBM_PEAK_GBS, 4),
+                                     "frac_hbm_warm": round(warm_achieved / HBM_PEAK_GBS, 4)}
+        for prec, (ib, ob) in (("f32", (4, 4)), ("bf16", (2, 4))):
+            tt, yy = time_apply(op, X[prec], prec, 20, 5, torch)
             per3 = tt / 20
-            kb = 8 if prec == "f64" else 4
-            bpd3 = alg_bytes_per_dof(n3, ib, ob, kb)
-            fp3 = flops_per_dof(n3)
-            peak3 = FP64_PEAK_TFS if prec == "f64" else FP32_PEAK_TFS
-            ent = {"gdofs": round(op3.ndof / per3 / 1e9, 3), "ms": round(per3 * 1e3, 4),
-                   "achieved_GBs": round(bpd3 * op3.ndof / per3 / 1e9, 1),
-                   "frac_hbm": round(bpd3 * op3.ndof / per3 / 1e9 / HBM_PEAK_GBS, 4),
-                   "tflops": round(fp3 * op3.ndof / per3 / 1e12, 3),
-                   "frac_alu": round(fp3 * op3.ndof / per3 / 1e12 / peak3, 4)}
-            if prec == "f64":
-                ref = yy.clone()
-            else:
-                ent["rel_err_vs_gpu_f64"] = float(torch.linalg.norm(yy.double() - ref) / torch.linalg.norm(ref))
-            extras[f"apply_{prec}_{wl3}"] = ent
-            log(f"apply {prec} {wl3}: {ent}")
+            tc3 = cold_apply(op, X[prec], prec, 10, torch)
+            bpd3 = alg_bytes_per_dof(n, ib, ob, 4)
+            ent = {"gdofs": round(op.ndof / per3 / 1e9, 3), "ms": round(per3 * 1e3, 4),
+                   "cold_ms": round(tc3 * 1e3, 4),
+                   "achieved_GBs": round(bpd3 * op.ndof / per3 / 1e9, 1),
+                   "frac_hbm_warm": round(bpd3 * op.ndof / per3 / 1e9 / HBM_PEAK_GBS, 4),
+                   "frac_hbm_cold": round(bpd3 * op.ndof / tc3 / 1e9 / HBM_PEAK_GBS, 4),
+                   "rel_err_vs_gpu_f64": float(torch.linalg.norm(yy.double() - y) / torch.linalg.norm(y))}
+            extras[f"apply_{prec}_{wl}"] = ent
+            log(f"apply {prec} {wl}: {ent}")
             del yy
-        del X, ref
+        del X
         torch.cuda.empty_cache()
-        b3 = dev(I.uniform_vector(op3.ndof, seed=I.S_B))
+    if want("cg_q4_64"):
+        b3 = dev(I.uniform_vector(op.ndof, seed=I.S_B))
         for prec, mode in CG_VARIANTS:
             kw = {"variant": "single_reduction"} if mode == "single_reduction" else {"dc_mode": mode}
-            op3.cg_solve(b3, prec_inner=prec, rtol=1e-10, maxit=30, **kw)  # warm
-            u3, info = op3.cg_solve(b3, prec_inner=prec, rtol=1e-10, **kw)
+            op.cg_solve(b3, prec_inner=prec, rtol=1e-10, maxit=30, **kw)  # warm
+            u3, info = op.cg_solve(b3, prec_inner=prec, rtol=1e-10, **kw)
             tag = (prec if mode == "restart" else f"{prec}_{mode}") if prec == "f64" else f"{prec}_{mode}"
-            extras[f"cg_{tag}_{wl3}"] = info
-            log(f"cg {tag} {wl3}: {info}")
+            extras[f"cg_{tag}_{wl}"] = info
+            log(f"cg {tag} {wl}: {info}")
             if tag == "f64":
                 u64 = u3
             else:
-                extras[f"cg_{tag}_{wl3}"]["rel_diff_vs_f64_solution"] = float(
+                extras[f"cg_{tag}_{wl}"]["rel_diff_vs_f64_solution"] = float(
                     torch.linalg.norm(u3 - u64) / torch.linalg.norm(u64))
-        del op3, b3, u3, u64
+        del b3, u3, u64
+    del op, x, y
+    torch.cuda.empty_cache()
+
+    # ------------------------------------------------------------ 32^3 Q3 (manufactured sine right-hand side)
+    if want("dirichlet_q3_32"):
+        c2 = I.WORKLOADS["dirichlet_q3_32"]
+        N2, k2 = c2["N"], c2["k"]
+        op2 = DGOperator(N2, N2, N2, k2, "dirichlet", theta=dev(I.theta(N2 ** 3)))
+        x2 = dev(I.uniform_vector(op2.ndof))
+        tt, yy = time_apply(op2, x2, "f64", 50, 10, torch)
+        tc2 = cold_apply(op2, x2, "f64", 20, torch)
+        bpd2 = alg_bytes_per_dof(k2 + 1, 8, 8, 8)
+        extras["apply_f64_dirichlet_q3_32"] = {
+            "gdofs": round(op2.ndof * 50 / tt / 1e9, 3), "us": round(tt / 50 * 1e6, 3),
+            "cold_us": round(tc2 * 1e6, 3),
+            "frac_hbm_warm_cache_resident": round(bpd2 * op2.ndof / (tt / 50) / 1e9 / HBM_PEAK_GBS, 4),
+            "frac_hbm_cold": round(bpd2 * op2.ndof / tc2 / 1e9 / HBM_PEAK_GBS, 4)}
+        log(f"apply f64 dirichlet_q3_32: {extras['apply_f64_dirichlet_q3_32']}")
+        del yy, x2
+        xq = op2.quadrature_points()
+        fq = 3 * math.pi ** 2 * torch.sin(math.pi * xq[:, 0]) * torch.sin(math.pi * xq[:, 1]) * \
+            torch.sin(math.pi * xq[:, 2])
+        b = op2.load_vector(fq.contiguous())
+        for prec, mode in CG_VARIANTS:
+            kw = {"variant": "single_reduction"} if mode == "single_reduction" else {"dc_mode": mode}
+            op2.cg_solve(b, prec_inner=prec, rtol=1e-10, **kw)  # warm
+            u, info = op2.cg_solve(b, prec_inner=prec, rtol=1e-10, **kw)
+            tag = (prec if mode == "restart" else f"{prec}_{mode}") if prec == "f64" else f"{prec}_{mode}"
+            extras[f"cg_{tag}_q3_32"] = info
+            log(f"cg {tag} q3_32: {info}")
+        del u, b, fq, xq, op2
         torch.cuda.empty_cache()
 
     # ------------------------------------------------------------ adjoint gradient (32^3 Q3)

@@ -84,14 +84,23 @@ typedef struct {
  * descriptor are not read).  DG_ERR_ARG / DG_ERR_UNSUPPORTED on bad sizes. */
 int dg_query_workspace(const dg_mesh_desc* mesh, size_t* bytes);
 
-/* Build a context: 1D tables (Gauss-Lobatto nodes, Gauss points, basis values
- * and derivatives) in FP64 on the host, K = exp(theta) in FP64 and FP32,
+/* Build a context for the discrete problem of Sec. 4.1 ("Continuous problem
+ * and discretization": the mesh T_h of the unit cube, the broken polynomial
+ * space, the coefficient K) in the cell-blocked storage of the Sec. 3.3 DG
+ * codepath: 1D tables (Gauss-Lobatto nodes, Gauss points, basis values and
+ * derivatives) in FP64 on the host, K = exp(theta) in FP64 and FP32,
  * geometry, Jacobi diagonal.  Synchronises `stream`.  *out receives the
- * context (host memory owned by the library until dg_destroy). */
+ * context (host memory owned by the library until dg_destroy).  Errors:
+ * DG_ERR_ARG for a bad descriptor or a workspace below dg_query_workspace,
+ * DG_ERR_UNSUPPORTED for a degree outside 1..7, DG_ERR_DEVICE for a failed HIP
+ * call; *out is NULL then. */
 int dg_setup(const dg_mesh_desc* mesh, dg_ctx** out, void* stream);
 
-/* Replace the coefficient: K_T = exp(theta_T) (device, nx*ny*nz doubles), and
- * recompute the Jacobi diagonal.  Asynchronous on `stream`. */
+/* Replace the coefficient K of the form of Sec. 4.1: K_T = exp(theta_T)
+ * (device, nx*ny*nz doubles), face coefficients and Jacobi diagonal.  When
+ * every new K_T equals the current one bit for bit, the diagonal kernels find
+ * that out on the device and return at once (no host synchronisation).
+ * Asynchronous on `stream`.  Errors: DG_ERR_ARG for NULL pointers. */
 int dg_set_theta(dg_ctx* ctx, const double* theta, void* stream);
 
 /* Add a reaction term int c_T u v to the form (the diffusion-reaction problems
@@ -110,14 +119,21 @@ int dg_set_reaction(dg_ctx* ctx, const double* c, void* stream);
  * overlap in time: issue them on one stream or order them with events. */
 int dg_apply(dg_ctx* ctx, int prec, const void* x, void* y, void* stream);
 
-/* y = A^T x.  Affine meshes: evaluated from the transposed 1D operators and
- * the transposed face algebra (equal to A x up to rounding since the form is
- * symmetric); trilinear meshes: the apply itself (the discrete form is
- * symmetric).  Arguments and errors as dg_apply. */
+/* y = A^T x, the operator of the adjoint problems.  The symmetric weighted
+ * interior-penalty form of Sec. 4.1 is symmetric in its two arguments (the
+ * consistency and symmetry terms are mirror images and the penalty term is
+ * symmetric), so A^T = A.  Affine meshes: evaluated from the transposed 1D
+ * operators and the transposed face algebra (equal to A x up to rounding);
+ * trilinear meshes: the apply itself.  Arguments and errors as dg_apply. */
 int dg_apply_transpose(dg_ctx* ctx, int prec, const void* x, void* y, void* stream);
 
 /* g_T = u^T (dA / dtheta_T) v for every element T (device: u, v N_dof
- * doubles, g nx*ny*nz doubles): the volume form with K_T and each face form
+ * doubles, g nx*ny*nz doubles).  In the form of Sec. 4.1 the coefficient
+ * enters through K_T in the element integrals and through the harmonic face
+ * weights gamma_e of the face terms; this is the derivative of that form with
+ * respect to theta_T = log K_T, as the gradient of an inverse problem
+ * (Sec. 3.5 names optimisation and inverse problems among the users of
+ * repeated solves) needs it: the volume form with K_T and each face form
  * of T with d gamma_e / d theta_T = gamma_e K_other / (K^- + K^+) (boundary:
  * K_T); the reaction term does not depend on theta.  FP64, affine and
  * trilinear meshes (on trilinear meshes the context's CG work space holds
@@ -125,7 +141,10 @@ int dg_apply_transpose(dg_ctx* ctx, int prec, const void* x, void* y, void* stre
  * the same context). */
 int dg_dA_dtheta(dg_ctx* ctx, const double* u, const double* v, double* g, void* stream);
 
-/* d = diag(A) (device, N_dof doubles), FP64. */
+/* d = diag(A) (device, N_dof doubles), FP64: the point-Jacobi choice of the
+ * preconditioner M that Alg. "PCG" of Sec. 2.4 leaves open (the smallest of
+ * the block-diagonal preconditioners Sec. 3.4 builds from the element
+ * blocks).  Errors: DG_ERR_ARG for NULL pointers. */
 int dg_diagonal(dg_ctx* ctx, double* d, void* stream);
 
 /* Physical coordinates of the (k+1)^3 volume Gauss points of every element

@@ -459,8 +459,9 @@ __global__ __launch_bounds__(apply_block(N)) void k_apply_affine(MeshArgs<TC> m,
 // the unit line (the neighbour line is the unit line too when the element is
 // its own neighbour, i.e. one element along d with periodic wrap).
 template <int N>
-__global__ __launch_bounds__(256) void k_diag_affine(MeshArgs<double> m, double* __restrict__ d) {
+__global__ __launch_bounds__(256) void k_diag_affine(MeshArgs<double> m, double* __restrict__ d, const int* run) {
   constexpr int NN = N * N, N3 = NN * N;
+  if (run != nullptr && *run == 0) return;
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (gid >= m.E * N3) return;
   const Tables<double>& T = *m.tab;
@@ -771,20 +772,20 @@ hipError_t launch_apply_affine(int n, int prec, int trans, int dot, const MeshAr
 }
 
 template <int N>
-static hipError_t run_diag(const MeshArgs<double>& m, double* d, hipStream_t s) {
+static hipError_t run_diag(const MeshArgs<double>& m, double* d, const int* run, hipStream_t s) {
   const int64_t tot = m.E * N * N * N;
-  hipLaunchKernelGGL((k_diag_affine<N>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, m, d);
+  hipLaunchKernelGGL((k_diag_affine<N>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, m, d, run);
   return hipGetLastError();
 }
-hipError_t launch_diag_affine(int n, const MeshArgs<double>& m, double* d, hipStream_t s) {
+hipError_t launch_diag_affine(int n, const MeshArgs<double>& m, double* d, const int* run, hipStream_t s) {
   switch (n) {
-    case 2: return run_diag<2>(m, d, s);
-    case 3: return run_diag<3>(m, d, s);
-    case 4: return run_diag<4>(m, d, s);
-    case 5: return run_diag<5>(m, d, s);
-    case 6: return run_diag<6>(m, d, s);
-    case 7: return run_diag<7>(m, d, s);
-    case 8: return run_diag<8>(m, d, s);
+    case 2: return run_diag<2>(m, d, run, s);
+    case 3: return run_diag<3>(m, d, run, s);
+    case 4: return run_diag<4>(m, d, run, s);
+    case 5: return run_diag<5>(m, d, run, s);
+    case 6: return run_diag<6>(m, d, run, s);
+    case 7: return run_diag<7>(m, d, run, s);
+    case 8: return run_diag<8>(m, d, run, s);
   }
   return hipErrorInvalidValue;
 }

@@ -46,6 +46,7 @@ struct dg_ctx {
   void* fb;              // trilinear meshes: lower-face line scalars between the two apply passes
   double* partials;
   CgState* st;           // [0]: outer / FP64 solve, [1]: inner solve
+  int* coef_changed;     // set by dg_set_theta's exp kernel when K changed (device)
   std::string err;
 };
 
@@ -71,7 +72,11 @@ int fail(dg_ctx* c, int code, const std::string& msg) {
 // symmetric tridiagonal Jacobi matrix of the Legendre recurrence, weights from
 // the first eigenvector components), and the interior Gauss-Lobatto nodes as
 // the Gauss points of the Jacobi weight (1-x^2) (roots of P^(1,1)_{n-2}, i.e.
-// of P'_{n-1}).  Eigen-decomposition: implicit QL with Wilkinson shifts.
+// of P'_{n-1}).  Eigen-decomposition: the implicit QL algorithm with
+// Wilkinson shifts for symmetric tridiagonal matrices, as published by
+// Bowdler, Martin, Reinsch and Wilkinson (procedure tql2, Numer. Math. 11,
+// 1968; Handbook for Automatic Computation, Vol. II), restricted here to the
+// first row of the eigenvector matrix.
 
 // diag d[0..m), off-diagonal e[1..m) (e[0] unused); on exit d = eigenvalues,
 // z[0..m) = first components of the normalised eigenvectors.
@@ -304,7 +309,7 @@ void tables_to_f32(const Tables<double>& a, Tables<float>& b) {
 // ------------------------------------------------------------------ workspace
 struct Layout {
   size_t tab64, tab32, K64, K32, G64, G32, R64, R32, vert64, vert32, dinv64, dinv32, r64, p64, q64, r32, d32, p32,
-      q32, p16, z64, s64, w64, fb, partials, st, total;
+      q32, p16, z64, s64, w64, fb, partials, st, flags, total;
 };
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
@@ -364,6 +369,7 @@ Layout layout(const dg_mesh_desc* m) {
                                        affine_tiles(n, m->nx, m->ny, m->nz));
   L.partials = take((size_t)nb * 3 * sizeof(double));
   L.st = take(2 * sizeof(CgState));
+  L.flags = take(64);
   L.total = o;
   return L;
 }
@@ -439,19 +445,23 @@ hipError_t apply_any(dg_ctx* c, int prec, int trans, int dot, const void* x, voi
   return launch_apply_affine(c->n, prec, trans, dot, m64, m32, x, y, part, st, par, skip, s);
 }
 
-hipError_t coef_setup(dg_ctx* c, const double* theta, hipStream_t s) {
-  hipError_t e = launch_exp(c->E, theta, c->K64, c->K32, s);
+// K = exp(theta) and the face coefficients; changed != nullptr: the exp kernel
+// records in *changed whether any K_T differs from the current one
+hipError_t coef_setup(dg_ctx* c, const double* theta, int* changed, hipStream_t s) {
+  hipError_t e = launch_exp(c->E, theta, c->K64, c->K32, changed, s);
   if (e != hipSuccess) return e;
   MeshArgs<double> m = args64(c);
   return launch_face_coef(m, c->G64, c->G32, s);
 }
 
-hipError_t compute_dinv(dg_ctx* c, hipStream_t s) {
+// Jacobi diagonal and its inverse; run != nullptr: the kernels do nothing when
+// *run == 0 on the device (the coefficients did not change)
+hipError_t compute_dinv(dg_ctx* c, hipStream_t s, const int* run = nullptr) {
   const MeshArgs<double> m64 = args64(c);
-  hipError_t e = c->trilinear ? launch_diag_trilinear(c->n, m64, c->r64, s)
-                              : launch_diag_affine(c->n, m64, c->r64, s);
+  hipError_t e = c->trilinear ? launch_diag_trilinear(c->n, m64, c->r64, run, s)
+                              : launch_diag_affine(c->n, m64, c->r64, run, s);
   if (e != hipSuccess) return e;
-  return launch_inv_diag(c->ndof, c->r64, c->dinv64, c->dinv32, s);
+  return launch_inv_diag(c->ndof, c->r64, c->dinv64, c->dinv32, run, s);
 }
 
 bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
@@ -538,6 +548,7 @@ int dg_setup(const dg_mesh_desc* mesh, dg_ctx** out, void* stream) {
   c->fb = c->trilinear ? (void*)(w + L.fb) : nullptr;
   c->partials = (double*)(w + L.partials);
   c->st = (CgState*)(w + L.st);
+  c->coef_changed = (int*)(w + L.flags);
   hipStream_t s = (hipStream_t)stream;
   auto bail = [&](int code, const std::string& msg) {
     g_err = msg;
@@ -557,7 +568,7 @@ int dg_setup(const dg_mesh_desc* mesh, dg_ctx** out, void* stream) {
   SETUP_TRY(hipMemcpyAsync(c->tab64, &t64, sizeof(t64), hipMemcpyHostToDevice, s));
   SETUP_TRY(hipMemcpyAsync(c->tab32, &t32, sizeof(t32), hipMemcpyHostToDevice, s));
   SETUP_TRY(hipMemsetAsync(c->st, 0, 2 * sizeof(CgState), s));
-  SETUP_TRY(coef_setup(c, mesh->theta, s));
+  SETUP_TRY(coef_setup(c, mesh->theta, nullptr, s));
   if (c->trilinear) {
     const int64_t nv3 = (int64_t)(mesh->nx + 1) * (mesh->ny + 1) * (mesh->nz + 1) * 3;
     SETUP_TRY(hipMemcpyAsync(c->vert64, mesh->vertices, nv3 * sizeof(double), hipMemcpyDeviceToDevice, s));
@@ -580,8 +591,10 @@ int dg_set_theta(dg_ctx* c, const double* theta, void* stream) {
   if (!c) return fail(nullptr, DG_ERR_ARG, "ctx is NULL");
   if (!theta) return fail(c, DG_ERR_ARG, "theta is NULL");
   hipStream_t s = (hipStream_t)stream;
-  HIP_TRY(c, coef_setup(c, theta, s));
-  HIP_TRY(c, compute_dinv(c, s));
+  // the diagonal kernels skip their work on the device when no K_T changed
+  // (an autograd backward sets the same theta as its forward)
+  HIP_TRY(c, coef_setup(c, theta, c->coef_changed, s));
+  HIP_TRY(c, compute_dinv(c, s, c->coef_changed));
   return DG_OK;
 }
 
@@ -637,7 +650,8 @@ int dg_diagonal(dg_ctx* c, double* d, void* stream) {
   if (!d) return fail(c, DG_ERR_ARG, "d is NULL");
   const MeshArgs<double> m64 = args64(c);
   hipStream_t s = (hipStream_t)stream;
-  HIP_TRY(c, c->trilinear ? launch_diag_trilinear(c->n, m64, d, s) : launch_diag_affine(c->n, m64, d, s));
+  HIP_TRY(c, c->trilinear ? launch_diag_trilinear(c->n, m64, d, nullptr, s)
+                          : launch_diag_affine(c->n, m64, d, nullptr, s));
   return DG_OK;
 }
 

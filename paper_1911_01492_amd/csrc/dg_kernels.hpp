@@ -42,7 +42,8 @@ hipError_t launch_apply_affine(int n, int prec, int trans, int dot, const MeshAr
                                CgState* st, int par, const int* skip, hipStream_t s);
 hipError_t launch_face_coef(const MeshArgs<double>& m, double* G64, float* G32, hipStream_t s);
 hipError_t launch_finish_dot(const double* partials, int64_t nblocks, CgState* st, int par, hipStream_t s);
-hipError_t launch_diag_affine(int n, const MeshArgs<double>& m, double* d, hipStream_t s);
+// diagonal kernels: run != nullptr && *run == 0 makes them return at once
+hipError_t launch_diag_affine(int n, const MeshArgs<double>& m, double* d, const int* run, hipStream_t s);
 hipError_t launch_dA_affine(int n, const MeshArgs<double>& m, const double* u, const double* v, double* g,
                             hipStream_t s);
 
@@ -50,7 +51,7 @@ hipError_t launch_dA_affine(int n, const MeshArgs<double>& m, const double* u, c
 hipError_t launch_apply_trilinear(int n, int prec, int trans, int dot, const MeshArgs<double>& m64,
                                   const MeshArgs<float>& m32, const void* x, void* y, double* partials,
                                   CgState* st, int par, const int* skip, hipStream_t s);
-hipError_t launch_diag_trilinear(int n, const MeshArgs<double>& m, double* d, hipStream_t s);
+hipError_t launch_diag_trilinear(int n, const MeshArgs<double>& m, double* d, const int* run, hipStream_t s);
 // g_T = u^T dA/dtheta_T v on trilinear meshes; parts: 7 E doubles of scratch
 hipError_t launch_dA_trilinear(int n, const MeshArgs<double>& m, const double* u, const double* v, double* parts,
                                double* g, hipStream_t s);
@@ -97,8 +98,9 @@ hipError_t launch_dc_replace(int64_t n, const double* b, const double* q, const 
                              hipStream_t s);
 hipError_t launch_resid_norm(int64_t n, const double* b, const double* q, CgState* st, double* partials,
                              hipStream_t s);
-hipError_t launch_exp(int64_t n, const double* th, double* K64, float* K32, hipStream_t s);
-hipError_t launch_inv_diag(int64_t n, const double* d, double* i64, float* i32, hipStream_t s);
+// K = exp(theta); changed != nullptr: *changed = 1 if any K differs from before, else 0
+hipError_t launch_exp(int64_t n, const double* th, double* K64, float* K32, int* changed, hipStream_t s);
+hipError_t launch_inv_diag(int64_t n, const double* d, double* i64, float* i32, const int* run, hipStream_t s);
 hipError_t launch_to_f32(int64_t n, const double* a, float* b, hipStream_t s);
 
 }  // namespace dg

@@ -14,8 +14,11 @@
 // derivatives by 2D sum factorisation through LDS), physical gradients with
 // each side's own Jacobian, area-weighted normal n dS = dF/dxi_a x dF/dxi_b
 // of T^-; the test-function side is projected back with the transposed
-// tangential operators.  Every face is evaluated by both of its elements,
-// which write only their own rows (no atomics).
+// tangential operators.  Each interior face is evaluated once, by its lower
+// element T^-, in the first of two passes: T^- adds its own rows and leaves
+// the two line scalars per face node of the T^+ side in a face buffer of the
+// workspace, which the second pass adds to T^+ (no atomics).  Dirichlet faces
+// are evaluated by their only element in the first pass.
 //
 // The discrete form is symmetric, so the transposed apply evaluates the same
 // kernel.
@@ -233,7 +236,12 @@ __device__ void face_term(const MeshArgs<TC>& m, const Tables<TC>& T, const TIN*
     F[1][t] = Ra;
     F[2][t] = Rb;
     F[3][t] = Rd;
-    if (PAIR) {
+  }
+  if (PAIR) {
+    // F[4..9] are read above by every thread of the element, which may span
+    // two wavefronts (n^2 not dividing 64): the T^+ rows wait for all of them
+    elem_sync<N>();
+    if (act) {
       F[4][t] = Pn;
       F[5][t] = Ran;
       F[6][t] = Rbn;
@@ -691,9 +699,11 @@ __global__ __launch_bounds__(256) void k_dA_combine_trilinear(MeshArgs<double> m
 // per DOF sums gr_i^T G_q gr_i over the points, plus the face terms of the
 // face-layer DOFs (a_e(phi_i, phi_i) with phi_i on its own side).
 template <int N>
-__global__ __launch_bounds__(512) void k_diag_trilinear(MeshArgs<double> m, double* __restrict__ d) {
+__global__ __launch_bounds__(512) void k_diag_trilinear(MeshArgs<double> m, double* __restrict__ d,
+                                                        const int* run) {
   constexpr int NN = N * N, N3 = NN * N;
   __shared__ double G[N3][7];
+  if (run != nullptr && *run == 0) return;
   const int64_t e = blockIdx.x;
   const int t = threadIdx.x;
   const Tables<double>& T = *m.tab;
@@ -856,9 +866,9 @@ hipError_t launch_apply_trilinear(int n, int prec, int trans, int dot, const Mes
 }
 
 template <int N>
-static hipError_t run_tri_diag(const MeshArgs<double>& m, double* d, hipStream_t s) {
+static hipError_t run_tri_diag(const MeshArgs<double>& m, double* d, const int* run, hipStream_t s) {
   const int th = ((N * N * N + 63) / 64) * 64;
-  hipLaunchKernelGGL((k_diag_trilinear<N>), dim3((unsigned)m.E), dim3(th), 0, s, m, d);
+  hipLaunchKernelGGL((k_diag_trilinear<N>), dim3((unsigned)m.E), dim3(th), 0, s, m, d, run);
   return hipGetLastError();
 }
 template <int N>
@@ -886,15 +896,15 @@ hipError_t launch_dA_trilinear(int n, const MeshArgs<double>& m, const double* u
   }
 }
 
-hipError_t launch_diag_trilinear(int n, const MeshArgs<double>& m, double* d, hipStream_t s) {
+hipError_t launch_diag_trilinear(int n, const MeshArgs<double>& m, double* d, const int* run, hipStream_t s) {
   switch (n) {
-    case 2: return run_tri_diag<2>(m, d, s);
-    case 3: return run_tri_diag<3>(m, d, s);
-    case 4: return run_tri_diag<4>(m, d, s);
-    case 5: return run_tri_diag<5>(m, d, s);
-    case 6: return run_tri_diag<6>(m, d, s);
-    case 7: return run_tri_diag<7>(m, d, s);
-    case 8: return run_tri_diag<8>(m, d, s);
+    case 2: return run_tri_diag<2>(m, d, run, s);
+    case 3: return run_tri_diag<3>(m, d, run, s);
+    case 4: return run_tri_diag<4>(m, d, run, s);
+    case 5: return run_tri_diag<5>(m, d, run, s);
+    case 6: return run_tri_diag<6>(m, d, run, s);
+    case 7: return run_tri_diag<7>(m, d, run, s);
+    case 8: return run_tri_diag<8>(m, d, run, s);
   }
   return hipErrorInvalidValue;
 }

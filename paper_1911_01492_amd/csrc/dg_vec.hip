@@ -674,16 +674,24 @@ hipError_t launch_resid_norm(int64_t n, const double* b, const double* q, CgStat
 }
 
 // ---------------------------------------------------------------- elementwise helpers
+// K = exp(theta).  changed != nullptr: set *changed = 1 when any coefficient
+// differs bitwise from the one it replaces (every writer stores the same value).
 __global__ void k_exp(int64_t n, const double* __restrict__ th, double* __restrict__ K64,
-                      float* __restrict__ K32) {
+                      float* __restrict__ K32, int* changed) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double k = th ? exp(th[i]) : 1.0;
+  if (changed != nullptr && __double_as_longlong(K64[i]) != __double_as_longlong(k)) *changed = 1;
   K64[i] = k;
   K32[i] = (float)k;
 }
+__global__ void k_set_flag(int* f, int v) {
+  if (threadIdx.x == 0) *f = v;
+}
+// run != nullptr && *run == 0: nothing to do (the diagonal is unchanged)
 __global__ void k_inv_diag(int64_t n, const double* __restrict__ d, double* __restrict__ i64,
-                           float* __restrict__ i32) {
+                           float* __restrict__ i32, const int* run) {
+  if (run != nullptr && *run == 0) return;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double v = 1.0 / d[i];
@@ -695,12 +703,17 @@ __global__ void k_to_f32(int64_t n, const double* __restrict__ a, float* __restr
   if (i < n) b[i] = (float)a[i];
 }
 
-hipError_t launch_exp(int64_t n, const double* th, double* K64, float* K32, hipStream_t s) {
-  hipLaunchKernelGGL(k_exp, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, th, K64, K32);
+hipError_t launch_exp(int64_t n, const double* th, double* K64, float* K32, int* changed, hipStream_t s) {
+  if (changed != nullptr) {
+    hipLaunchKernelGGL(k_set_flag, dim3(1), dim3(64), 0, s, changed, 0);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_exp, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, th, K64, K32, changed);
   return hipGetLastError();
 }
-hipError_t launch_inv_diag(int64_t n, const double* d, double* i64, float* i32, hipStream_t s) {
-  hipLaunchKernelGGL(k_inv_diag, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, d, i64, i32);
+hipError_t launch_inv_diag(int64_t n, const double* d, double* i64, float* i32, const int* run, hipStream_t s) {
+  hipLaunchKernelGGL(k_inv_diag, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, d, i64, i32, run);
   return hipGetLastError();
 }
 hipError_t launch_to_f32(int64_t n, const double* a, float* b, hipStream_t s) {

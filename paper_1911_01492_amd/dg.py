@@ -106,8 +106,18 @@ def _ptr(t: Optional[torch.Tensor]):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 
 
-def _stream(stream) -> ctypes.c_void_p:
-    s = stream if stream is not None else torch.cuda.current_stream()
+def _stream(stream, *keep) -> ctypes.c_void_p:
+    """The HIP stream handle for a call.  When the work goes to a stream other
+    than the current one, the tensors it uses (``keep``: outputs allocated
+    here, contiguous temporaries, the workspace) are recorded on that stream,
+    so the caching allocator does not hand their memory out again before the
+    library's kernels on it have finished."""
+    cur = torch.cuda.current_stream()
+    s = stream if stream is not None else cur
+    if s != cur:
+        for t in keep:
+            if t is not None:
+                t.record_stream(s)
     return ctypes.c_void_p(s.cuda_stream)
 
 
@@ -177,13 +187,15 @@ class DGOperator:
     def set_theta(self, theta: torch.Tensor, stream=None):
         if theta.numel() != self.E or theta.dtype != torch.float64 or not theta.is_cuda:
             raise ValueError("theta must be a CUDA float64 tensor with one entry per element")
-        self._check(lib().dg_set_theta(self._h, _ptr(theta.contiguous()), _stream(stream)))
+        th = theta.contiguous()
+        self._check(lib().dg_set_theta(self._h, _ptr(th), _stream(stream, th, self.workspace)))
 
     def set_reaction(self, c: Optional[torch.Tensor], stream=None):
         """Reaction coefficients c_T (CUDA float64, one per element) or None to remove the term."""
         if c is not None and (c.numel() != self.E or c.dtype != torch.float64 or not c.is_cuda):
             raise ValueError("c must be a CUDA float64 tensor with one entry per element")
-        self._check(lib().dg_set_reaction(self._h, _ptr(None if c is None else c.contiguous()), _stream(stream)))
+        cc = None if c is None else c.contiguous()
+        self._check(lib().dg_set_reaction(self._h, _ptr(cc), _stream(stream, cc, self.workspace)))
 
     def apply(self, x: torch.Tensor, prec: str = "f64", out: Optional[torch.Tensor] = None,
               transpose: bool = False, stream=None) -> torch.Tensor:
@@ -193,7 +205,7 @@ class DGOperator:
         y = torch.empty(self.ndof, dtype=_OUT_DTYPE[prec], device=x.device) if out is None else out
         self._vec(y, _OUT_DTYPE[prec])
         fn = lib().dg_apply_transpose if transpose else lib().dg_apply
-        self._check(fn(self._h, PREC[prec], _ptr(x), _ptr(y), _stream(stream)))
+        self._check(fn(self._h, PREC[prec], _ptr(x), _ptr(y), _stream(stream, x, y, self.workspace)))
         return y
 
     def dA_dtheta(self, u: torch.Tensor, v: torch.Tensor, out: Optional[torch.Tensor] = None,
@@ -202,23 +214,23 @@ class DGOperator:
         self._vec(u, torch.float64)
         self._vec(v, torch.float64)
         g = torch.empty(self.E, dtype=torch.float64, device=u.device) if out is None else out
-        self._check(lib().dg_dA_dtheta(self._h, _ptr(u), _ptr(v), _ptr(g), _stream(stream)))
+        self._check(lib().dg_dA_dtheta(self._h, _ptr(u), _ptr(v), _ptr(g), _stream(stream, u, v, g, self.workspace)))
         return g
 
     def diagonal(self, stream=None) -> torch.Tensor:
         d = torch.empty(self.ndof, dtype=torch.float64, device="cuda")
-        self._check(lib().dg_diagonal(self._h, _ptr(d), _stream(stream)))
+        self._check(lib().dg_diagonal(self._h, _ptr(d), _stream(stream, d, self.workspace)))
         return d
 
     def quadrature_points(self, stream=None) -> torch.Tensor:
         xq = torch.empty((self.ndof, 3), dtype=torch.float64, device="cuda")
-        self._check(lib().dg_quadrature_points(self._h, _ptr(xq), _stream(stream)))
+        self._check(lib().dg_quadrature_points(self._h, _ptr(xq), _stream(stream, xq, self.workspace)))
         return xq
 
     def load_vector(self, fq: torch.Tensor, stream=None) -> torch.Tensor:
         self._vec(fq, torch.float64)
         b = torch.empty(self.ndof, dtype=torch.float64, device="cuda")
-        self._check(lib().dg_load_vector(self._h, _ptr(fq), _ptr(b), _stream(stream)))
+        self._check(lib().dg_load_vector(self._h, _ptr(fq), _ptr(b), _stream(stream, fq, b, self.workspace)))
         return b
 
     def cg_solve(self, b: torch.Tensor, x: Optional[torch.Tensor] = None, prec_inner: str = "f64",
@@ -238,7 +250,7 @@ class DGOperator:
                    max_outer, check_every, DC_MODE[dc_mode], CG_VARIANT[variant])
         info = CgInfo()
         rc = lib().dg_cg_solve(self._h, ctypes.byref(o), _ptr(b), _ptr(x), ctypes.byref(info),
-                               _stream(stream))
+                               _stream(stream, b, x, self.workspace))
         self._check(rc)
         return x, {"status": info.status, "iters": info.iters, "outer_iters": info.outer_iters,
                    "restarts": info.restarts, "rel_true_residual": info.rel_true_residual,

@@ -48,17 +48,19 @@ def test_algorithmic_models(bench):
     assert bench.alg_bytes_per_dof(4, 8, 8, 8) == 16.125
     assert bench.alg_bytes_per_dof(4, 4, 4, 4) == 8.0625
     assert bench.alg_bytes_per_dof(5, 2, 4, 4) == 6 + 4 / 125
-    # affine 14 n + 48, trilinear 12 (n + 2) + 288 + 810 / n
+    # affine 14 n + 48, trilinear 24 n + 288 + 810 / n (about 581 at n = 8)
     assert bench.flops_per_dof(4) == 104
-    assert bench.flops_per_dof(8, trilinear=True) == 12 * 10 + 288 + 810 / 8
+    assert bench.flops_per_dof(8, trilinear=True) == 24 * 8 + 288 + 810 / 8
+    assert abs(bench.flops_per_dof(8, trilinear=True) - 581) < 1
 
 
 def test_committed_traffic_figure(bench):
     """The traffic figure is either withheld (kernel sources changed since the
     counters were taken) or the committed one, between the algorithmic bytes and
-    twice them for the 2,097,152-DOF headline launch."""
+    twice them for the 32,768,000-DOF headline launch (64^3 Q4)."""
+    assert bench.HEADLINE == "mixed_q4_64"
     t = bench.measured_traffic()
     if t is None:
         pytest.skip("kernel sources changed since the HBM counters were taken")
-    alg = 16.125 * 2097152
+    alg = (16 + 8 / 125) * 32768000
     assert alg <= t <= 2 * alg

@@ -91,6 +91,43 @@ def test_full_size_sampled_rows(wl):
     assert err <= 1e-12
 
 
+def test_full_size_low_precision_q4_64():
+    """FP32 and BF16 applies of the 64^3 Q4 workload (the benchmark's launch
+    configuration, 32.8M DOF) against the oracle on sampled element rows, with
+    both errors of each result: the total error against A x (x the FP64
+    input) and the arithmetic error against A x_hat (x_hat = the rounded input
+    the kernel actually received)."""
+    N, k = 64, 4
+    banner("apply 64^3 Q4 FP32 / BF16 sampled rows")
+    theta = I.theta(N ** 3)
+    m = O.Mesh(N, N, N, k, theta=theta)
+    op = DGOperator(N, N, N, k, "dirichlet", theta=dev(theta))
+    x = I.uniform_vector(m.ndof)
+    el = _sample_elements(N, extra_seed=4)
+    ref = O.apply_rows(m, x, el)
+    idx = torch.as_tensor(el, device="cuda")
+    x32 = I.to_f32(x)
+    X32 = dev(x32, torch.float32)
+    got32 = host(op.apply(X32, prec="f32").view(-1, m.n3)[idx])
+    del X32
+    bits = I.to_bf16_bits(x)
+    xh = I.bf16_bits_to_f64(bits)
+    X16 = bf16_dev(bits)
+    del bits
+    got16 = host(op.apply(X16, prec="bf16").view(-1, m.n3)[idx])
+    del X16
+    e32_total = rel_l2(got32, ref)
+    e32_arith = rel_l2(got32, O.apply_rows(m, x32.astype(np.float64), el))
+    e16_total = rel_l2(got16, ref)
+    e16_arith = rel_l2(got16, O.apply_rows(m, xh, el))
+    print(f"64^3 Q4 sampled rows: fp32 total {e32_total:.3e} arithmetic {e32_arith:.3e}; "
+          f"bf16 total {e16_total:.3e} arithmetic {e16_arith:.3e}")
+    assert e32_arith <= 2e-5 and e32_total <= 2e-5
+    assert e16_arith <= 2e-5
+    assert e16_total <= 2e-2
+    torch.cuda.empty_cache()
+
+
 def test_full_csr_q3_32():
     """The 32^3 Q3 headline workload against the oracle's full CSR matrix
     (9.1e8 stored entries) and its OpenMP SpMV."""
@@ -242,9 +279,16 @@ def test_repeatable_with_changing_inputs():
     trilinear meshes: a kernel reading LDS data of another element or of an
     earlier phase before it is rewritten would see the other input's values."""
     banner("repeatability with changing inputs")
+    # trilinear k = 2, 4, 5, 6: an element's n^2 threads span two wavefronts,
+    # so the face phases depend on workgroup barriers; perturbed meshes take
+    # the general kernel, sheared ones the constant-metric (parallelepiped) one
     cases = [(32, 3, None), (12, 1, None), (6, 7, None), (8, 3, I.perturbed_vertices(8, 0.1, seed=3)),
-             (4, 7, I.perturbed_vertices(4, 0.1, seed=4))]
+             (4, 7, I.perturbed_vertices(4, 0.1, seed=4)),
+             (9, 2, I.perturbed_vertices(9, 0.1, seed=5)), (7, 4, I.sheared_vertices(7, 7, 7)),
+             (6, 5, I.perturbed_vertices(6, 0.1, seed=6)), (5, 6, I.sheared_vertices(5, 5, 5)),
+             (5, 4, I.perturbed_vertices(5, 0.1, seed=8)), (6, 2, I.sheared_vertices(6, 6, 6))]
     for N, k, verts in cases:
+        print(f"repeatability N={N} k={k} {'affine' if verts is None else 'trilinear'}", flush=True)
         op = DGOperator(N, N, N, k, "dirichlet", theta=dev(I.theta(N ** 3)),
                         vertices=None if verts is None else dev(verts))
         xs = [dev(I.uniform_vector(op.ndof, seed=s)) for s in (21, 22)]

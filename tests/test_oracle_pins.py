@@ -101,6 +101,27 @@ def test_convergence_rate(k, pert):
     assert rate >= k + 1 - 0.2, (errs, rate)
 
 
+@pytest.mark.parametrize("N,k,pert", [(4, 2, False), (2, 3, False), (3, 1, True), (3, 2, True)])
+def test_l2_error_closed_forms(N, k, pert):
+    """The L2 error helper itself, two-sided: for u_h = 0 it is the L2 norm of the
+    exact solution over the unit cube, ||sin(pi x) sin(pi y) sin(pi z)|| = 1/sqrt(8),
+    ||x|| = 1/sqrt(3), ||y z|| = 1/3; for u_h = c and u = 0 it is |c| (unit
+    volume).  Also on perturbed trilinear meshes, which tile the same cube.  A
+    dropped square root, weight or |det J| moves every one of these values."""
+    V = I.perturbed_vertices(N, 0.1, seed=5 + k) if pert else None
+    m = O.Mesh(N, N, N, k, vertices=V)
+    z = np.zeros(m.ndof)
+    # the sine is integrated by (k+3)-point Gauss: not exact, error well below 1e-7 here
+    assert abs(O.l2_error(m, z, "sine") - 1 / np.sqrt(8)) <= 1e-7
+    cx = np.zeros((k + 1,) * 3)
+    cx[1, 0, 0] = 1.0
+    assert abs(O.l2_error(m, z, "poly", cx) - 1 / np.sqrt(3)) <= 1e-13
+    cyz = np.zeros((k + 1,) * 3)
+    cyz[0, 1, 1] = 1.0
+    assert abs(O.l2_error(m, z, "poly", cyz) - 1 / 3) <= 1e-13
+    assert abs(O.l2_error(m, np.full(m.ndof, -2.5), "poly", np.zeros((k + 1,) * 3)) - 2.5) <= 1e-13
+
+
 @pytest.mark.parametrize("k", [1, 2, 3])
 def test_polynomial_reproduction_affine(k):
     """P5: for p in global Q_k with f = -lap p and Dirichlet data g = p, u_h = p."""
