@@ -8,7 +8,9 @@ computations that need no assembly:
 * ``fast_diag_solve`` -- the exact solution for K == 1 on a uniform box mesh
   from the Kronecker-sum structure of the operator (1D SWIPDG operators along
   each axis, tangential 1D mass matrices), solved by fast diagonalisation;
-* ``pcg`` -- Alg. "PCG" of Sec. 2.4 on the assembled matrix (in C++).
+* ``pcg`` -- Alg. "PCG" of Sec. 2.4 on the assembled matrix (in C++);
+* ``block_jacobi_pcg`` -- the same algorithm with exact element-block inverses
+  as the preconditioner (numpy).
 
 The operator, its readings and its notation are those of Sec. 4.1 (SWIPDG
 forms b_h and b_h^e); see the header of ``dg_oracle.cpp``.
@@ -215,6 +217,46 @@ def pcg(A: sp.csr_matrix, b: np.ndarray, rtol: float = 1e-10, maxit: int = 10000
     _load().oracle_pcg(A.shape[0], _ptr(ip), _ptr(ix), _ptr(dv), _ptr(b), _ptr(x), rtol, maxit,
                        1 if jacobi else 0, ctypes.byref(it), ctypes.byref(rr))
     return x, it.value, rr.value
+
+
+def block_jacobi_pcg(A: sp.csr_matrix, b: np.ndarray, block: int, rtol: float = 1e-10, maxit: int = 10000,
+                     x0: Optional[np.ndarray] = None):
+    """Alg. PCG (Sec. 2.4) with the preconditioner M = blockdiag(A)^{-1} over the
+    consecutive diagonal blocks of size `block` (the element blocks of Sec. 3.4's
+    block preconditioners), in numpy: every block inverted densely.  Steps in
+    the order of the algorithm: r0 = b - A x0, p1 = M r0, rho1 = <p1, r0>; per
+    iteration q = A p, alpha = <p, q>, x += rho/alpha p, r -= rho/alpha q,
+    z = M r, stop when ||r|| <= rtol ||b||, rho' = <z, r>, p = z + rho'/rho p.
+    Returns (x, iterations, true relative residual)."""
+    nblk = A.shape[0] // block
+    Ad = A.tocsr()
+    inv = [np.linalg.inv(Ad[e * block:(e + 1) * block, e * block:(e + 1) * block].toarray()) for e in range(nblk)]
+
+    def M(v):
+        return np.concatenate([inv[e] @ v[e * block:(e + 1) * block] for e in range(nblk)])
+
+    b = np.asarray(b, dtype=np.float64)
+    x = np.zeros_like(b) if x0 is None else np.array(x0, dtype=np.float64)
+    bnorm = np.linalg.norm(b)
+    r = b - Ad @ x
+    p = M(r)
+    rho = p @ r
+    it = 0
+    done = np.linalg.norm(r) <= rtol * bnorm
+    while not done and it < maxit:
+        it += 1
+        q = Ad @ p
+        lam = rho / (p @ q)
+        x = x + lam * p
+        r = r - lam * q
+        z = M(r)
+        if np.linalg.norm(r) <= rtol * bnorm:
+            break
+        rho_new = z @ r
+        p = z + (rho_new / rho) * p
+        rho = rho_new
+    res = np.linalg.norm(b - Ad @ x) / (bnorm if bnorm > 0 else 1.0)
+    return x, it, float(res)
 
 
 def rhs(mesh: Mesh, kind: str = "sine", coef: Optional[np.ndarray] = None) -> np.ndarray:
