@@ -134,6 +134,28 @@ __host__ __device__ constexpr int apply_block(int n) {
   return ((tile_x(n) * tile_y(n) * tile_z(n) * n * n + 63) / 64) * 64;
 }
 
+// Origin of logical brick tb.  The brick grid (ntx x nty x ntz) is cut into
+// slabs of CY brick rows along y; a slab is walked x fastest, then y, then z.
+// Consecutive logical bricks run on the same XCD (xcd_remap), so the bricks
+// that read an element's lines as neighbours run close in time to the brick
+// that owns it: x-neighbours 1 brick apart, y-neighbours ntx, z-neighbours
+// ntx CY (about 96 bricks), and the lines are still in that XCD's L2.  (With
+// plain x-y-z order the z-neighbours were ntx nty bricks apart and each x
+// line was fetched from HBM three times.)  Only the y-faces between slabs
+// (one in CY brick rows) read lines of bricks that run much later.
+template <int BX, int BY, int BZ>
+__device__ __forceinline__ void brick_origin(int tb, int nx, int ny, int nz, int (&o)[3]) {
+  const int ntx = (nx + BX - 1) / BX, nty = (ny + BY - 1) / BY, ntz = (nz + BZ - 1) / BZ;
+  const int CY = max(1, min(nty, 96 / ntx));
+  const int slab = ntx * CY * ntz;
+  const int g = tb / slab, r = tb - g * slab;
+  const int cy = min(CY, nty - g * CY);  // brick rows of this slab (the last one may be thinner)
+  const int bx = r % ntx, q = r / ntx;
+  o[0] = bx * BX;
+  o[1] = (g * CY + q % cy) * BY;
+  o[2] = (q / cy) * BZ;
+}
+
 // neighbour coordinate along one axis (periodic wrap), -1 on a Dirichlet boundary
 __device__ __forceinline__ int nb_coord(int c, int s, int Nd, int periodic) {
   int v = c + (s ? 1 : -1);
@@ -359,9 +381,9 @@ __global__ __launch_bounds__(apply_block(N)) void k_apply_affine(MeshArgs<TC> m,
   TC* F = F_IN_S2 ? sS2 : sFx;
   const Tables<TC>& T = *m.tab;
   // brick coordinates: uniform per workgroup (scalar arithmetic)
-  const int ntx = (m.nx + BX - 1) / BX, nty = (m.ny + BY - 1) / BY;
   const int tb = (int)xcd_remap(blockIdx.x, gridDim.x);
-  const int o[3] = {(tb % ntx) * BX, ((tb / ntx) % nty) * BY, (tb / (ntx * nty)) * BZ};
+  int o[3];
+  brick_origin<BX, BY, BZ>(tb, m.nx, m.ny, m.nz, o);
   const int Nd[3] = {m.nx, m.ny, m.nz};
   const int tid = threadIdx.x, el = tid / NN, t = tid - el * NN, t1 = t % N, t2 = t / N;
   const int lx = el % BX, ly = (el / BX) % BY, lz = el / (BX * BY);
