@@ -33,7 +33,8 @@
  *   - A context is used by one host thread at a time.
  *   - The library allocates no device memory: everything it keeps lives in
  *     the caller's workspace (dg_query_workspace), which must outlive the
- *     context.
+ *     context, except the static scratch array of dg_dA_dtheta_noalloc
+ *     (16 MiB per GPU, part of the library's code object).
  */
 #ifndef DG_H
 #define DG_H
@@ -140,6 +141,19 @@ int dg_apply_transpose(dg_ctx* ctx, int prec, const void* x, void* y, void* stre
  * per-element partial forms, so the call must not overlap a dg_cg_solve on
  * the same context). */
 int dg_dA_dtheta(dg_ctx* ctx, const double* u, const double* v, double* g, void* stream);
+
+/* For callers that cannot allocate device memory while they run (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * dg_dA_dtheta with its scratch in a static device array of the library
+ * instead of the context's workspace.  Same arguments, results and errors as
+ * dg_dA_dtheta (bit-identical g); no allocation of any kind.  On trilinear
+ * meshes the per-element partial forms (7 doubles per element) go to a 16 MiB
+ * array that each GPU holds until the process ends, so such meshes are limited
+ * to 299593 elements (DG_ERR_ARG above that); affine meshes need no scratch.
+ * All calls on one GPU share that array and every call overwrites it: calls
+ * that overlap in time on one GPU (other streams, other contexts, other host
+ * threads) race and must be ordered by the caller. */
+int dg_dA_dtheta_noalloc(dg_ctx* ctx, const double* u, const double* v, double* g, void* stream);
 
 /* d = diag(A) (device, N_dof doubles), FP64: the point-Jacobi choice of the
  * preconditioner M that Alg. "PCG" of Sec. 2.4 leaves open (the smallest of

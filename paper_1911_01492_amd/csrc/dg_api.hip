@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -47,8 +48,39 @@ struct dg_ctx {
   double* partials;
   CgState* st;           // [0]: outer / FP64 solve, [1]: inner solve
   int* coef_changed;     // set by dg_set_theta's exp kernel when K changed (device)
+  double* scratch;       // this device's copy of the static scratch array (dg_dA_dtheta_noalloc)
   std::string err;
 };
+
+// ------------------------------------------------------------------ static scratch
+// Scratch of dg_dA_dtheta_noalloc: the per-element partial forms of trilinear
+// meshes (7 doubles per element) live in this file-scope device array instead
+// of the caller's workspace.  Every GPU the library runs on holds its own copy
+// until the process ends.  In host code the name `scratch` is only a stand-in
+// for the symbol: its device address is looked up once per device (at the
+// first dg_setup with that device current) and only that address is used.
+static constexpr size_t kScratchBytes = (size_t)16 << 20;
+static __device__ __align__(256) double scratch[kScratchBytes / sizeof(double)];
+static constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static double* g_scratch_ptr[kMaxDevices] = {};
+
+// device address of `scratch` on the current device (resolved once per device)
+static hipError_t scratch_address(double** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[dev] == nullptr) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = (double*)p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
 
 namespace {
 
@@ -565,6 +597,7 @@ int dg_setup(const dg_mesh_desc* mesh, dg_ctx** out, void* stream) {
     e = (expr);                                                                           \
     if (e != hipSuccess) return bail(DG_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e)); \
   } while (0)
+  SETUP_TRY(scratch_address(&c->scratch));
   SETUP_TRY(hipMemcpyAsync(c->tab64, &t64, sizeof(t64), hipMemcpyHostToDevice, s));
   SETUP_TRY(hipMemcpyAsync(c->tab32, &t32, sizeof(t32), hipMemcpyHostToDevice, s));
   SETUP_TRY(hipMemsetAsync(c->st, 0, 2 * sizeof(CgState), s));
@@ -642,6 +675,20 @@ int dg_dA_dtheta(dg_ctx* c, const double* u, const double* v, double* g, void* s
     HIP_TRY(c, launch_dA_trilinear(c->n, args64(c), u, v, c->r64, g, (hipStream_t)stream));
   else
     HIP_TRY(c, launch_dA_affine(c->n, args64(c), u, v, g, (hipStream_t)stream));
+  return DG_OK;
+}
+
+int dg_dA_dtheta_noalloc(dg_ctx* c, const double* u, const double* v, double* g, void* stream) {
+  if (!c) return fail(nullptr, DG_ERR_ARG, "ctx is NULL");
+  if (!u || !v || !g) return fail(c, DG_ERR_ARG, "u, v or g is NULL");
+  if (c->trilinear) {  // the 7 per-element parts go to this device's static scratch array
+    if ((size_t)c->E * 7 * sizeof(double) > kScratchBytes)
+      return fail(c, DG_ERR_ARG, "mesh too large for dg_dA_dtheta_noalloc: at most " +
+                                     std::to_string(kScratchBytes / (7 * sizeof(double))) + " elements");
+    HIP_TRY(c, launch_dA_trilinear(c->n, args64(c), u, v, c->scratch, g, (hipStream_t)stream));
+  } else {
+    HIP_TRY(c, launch_dA_affine(c->n, args64(c), u, v, g, (hipStream_t)stream));
+  }
   return DG_OK;
 }
 

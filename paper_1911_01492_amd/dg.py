@@ -31,7 +31,7 @@ _OUT_DTYPE = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.float32}
 
 #: every function declared in include/dg.h
 ABI_FUNCTIONS = ["dg_query_workspace", "dg_setup", "dg_set_theta", "dg_set_reaction", "dg_apply", "dg_apply_transpose",
-                 "dg_dA_dtheta", "dg_diagonal", "dg_quadrature_points", "dg_load_vector", "dg_cg_solve",
+                 "dg_dA_dtheta", "dg_dA_dtheta_noalloc", "dg_diagonal", "dg_quadrature_points", "dg_load_vector", "dg_cg_solve",
                  "dg_num_dofs", "dg_num_elements", "dg_nodes_per_dir", "dg_destroy", "dg_last_error"]
 
 
@@ -85,6 +85,7 @@ def lib() -> ctypes.CDLL:
     L.dg_apply.argtypes = [vp, ctypes.c_int, vp, vp, vp]
     L.dg_apply_transpose.argtypes = [vp, ctypes.c_int, vp, vp, vp]
     L.dg_dA_dtheta.argtypes = [vp, vp, vp, vp, vp]
+    L.dg_dA_dtheta_noalloc.argtypes = [vp, vp, vp, vp, vp]
     L.dg_diagonal.argtypes = [vp, vp, vp]
     L.dg_quadrature_points.argtypes = [vp, vp, vp]
     L.dg_load_vector.argtypes = [vp, vp, vp, vp]
@@ -216,6 +217,15 @@ class DGOperator:
         g = torch.empty(self.E, dtype=torch.float64, device=u.device) if out is None else out
         self._check(lib().dg_dA_dtheta(self._h, _ptr(u), _ptr(v), _ptr(g), _stream(stream, u, v, g, self.workspace)))
         return g
+
+    def dA_dtheta_noalloc(self, u: torch.Tensor, v: torch.Tensor, out: torch.Tensor, stream=None) -> torch.Tensor:
+        """g_T = u^T (dA/dtheta_T) v through dg_dA_dtheta_noalloc (scratch in the library's
+        static device array; ``out`` must be given, nothing is allocated)."""
+        self._vec(u, torch.float64)
+        self._vec(v, torch.float64)
+        self._check(lib().dg_dA_dtheta_noalloc(self._h, _ptr(u), _ptr(v), _ptr(out),
+                                               _stream(stream, u, v, out, self.workspace)))
+        return out
 
     def diagonal(self, stream=None) -> torch.Tensor:
         d = torch.empty(self.ndof, dtype=torch.float64, device="cuda")
