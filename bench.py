@@ -39,7 +39,15 @@ FP32_PEAK_TFS = 157.3
 # pure FP64 PCG, then the FP64 defect correction with FP32 / BF16 inner solves,
 # restarted per correction or keeping the search direction
 CG_VARIANTS = (("f64", "restart"), ("f32", "restart"), ("bf16", "restart"), ("f32", "keep"), ("bf16", "keep"),
-               ("f64", "single_reduction"))
+               ("f64", "single_reduction"), ("f64", "block_jacobi"))
+
+
+def cg_kwargs(mode):
+    if mode == "single_reduction":
+        return {"variant": "single_reduction"}
+    if mode == "block_jacobi":
+        return {"precond": "block_jacobi"}
+    return {"dc_mode": mode}
 
 
 def log(msg: str):
@@ -302,7 +310,8 @@ def main():
                                      "cold_ms": round(t_cold * 1e3, 4),
                                      "frac_hbm_cold": round(cold_achieved / HBM_PEAK_GBS, 4),
                                      "frac_hbm_warm": round(warm_achieved / HBM_PEAK_GBS, 4)}
-        for prec, (ib, ob) in (("f32", (4, 4)), ("bf16", (2, 4))):
+        X["bf16_mfma"] = X["bf16"]
+        for prec, (ib, ob) in (("f32", (4, 4)), ("bf16", (2, 4)), ("bf16_mfma", (2, 4))):
             tt, yy = time_apply(op, X[prec], prec, 20, 5, torch)
             per3 = tt / 20
             tc3 = cold_apply(op, X[prec], prec, 10, torch)
@@ -321,7 +330,7 @@ def main():
     if want("cg_q4_64"):
         b3 = dev(I.uniform_vector(op.ndof, seed=I.S_B))
         for prec, mode in CG_VARIANTS:
-            kw = {"variant": "single_reduction"} if mode == "single_reduction" else {"dc_mode": mode}
+            kw = cg_kwargs(mode)
             op.cg_solve(b3, prec_inner=prec, rtol=1e-10, maxit=30, **kw)  # warm
             u3, info = op.cg_solve(b3, prec_inner=prec, rtol=1e-10, **kw)
             tag = (prec if mode == "restart" else f"{prec}_{mode}") if prec == "f64" else f"{prec}_{mode}"
@@ -357,7 +366,7 @@ def main():
             torch.sin(math.pi * xq[:, 2])
         b = op2.load_vector(fq.contiguous())
         for prec, mode in CG_VARIANTS:
-            kw = {"variant": "single_reduction"} if mode == "single_reduction" else {"dc_mode": mode}
+            kw = cg_kwargs(mode)
             op2.cg_solve(b, prec_inner=prec, rtol=1e-10, **kw)  # warm
             u, info = op2.cg_solve(b, prec_inner=prec, rtol=1e-10, **kw)
             tag = (prec if mode == "restart" else f"{prec}_{mode}") if prec == "f64" else f"{prec}_{mode}"

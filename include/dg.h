@@ -60,11 +60,22 @@ enum dg_status {
 enum dg_precision {
   DG_F64 = 0,  /* x: double, y: double; FP64 arithmetic                              */
   DG_F32 = 1,  /* x: float,  y: float;  FP32 arithmetic, FP32 tables and K          */
-  DG_BF16 = 2  /* x: bfloat16 (uint16_t bit patterns), y: float; FP32 accumulation   */
+  DG_BF16 = 2, /* x: bfloat16 (uint16_t bit patterns), y: float; FP32 accumulation   */
+  DG_BF16_MFMA = 3 /* as DG_BF16, with the tangential mass contractions (M (x) M on  *
+                    * the n^2 points of every element plane) on the matrix cores:     *
+                    * exact BF16 x operands, the matrix as a three-term BF16 sum,     *
+                    * FP32 accumulation; the 1D operators along each axis in FP32.    *
+                    * Affine meshes, k <= 4 (DG_ERR_UNSUPPORTED otherwise).           */
 };
 
 enum dg_bc { DG_BC_DIRICHLET0 = 0, DG_BC_PERIODIC = 1 };
-enum dg_preconditioner { DG_PC_NONE = 0, DG_PC_JACOBI = 1 };
+/* DG_PC_JACOBI: M = diag(A)^-1.  DG_PC_BLOCK_JACOBI: M = blockdiag(A)^-1 over the
+ * element blocks (Sec. 3.4's block preconditioners from the element blocks of
+ * the DG matrix), inverted exactly by fast diagonalisation: on axis-parallel
+ * box elements the block is a Kronecker sum of per-element 1D operators.
+ * Affine meshes, FP64 PCG (prec_inner DG_F64, DG_CG_STANDARD) only;
+ * DG_ERR_UNSUPPORTED otherwise. */
+enum dg_preconditioner { DG_PC_NONE = 0, DG_PC_JACOBI = 1, DG_PC_BLOCK_JACOBI = 2 };
 
 typedef struct {
   int32_t nx, ny, nz;        /* elements per direction, >= 1                              */

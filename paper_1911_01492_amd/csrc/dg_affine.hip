@@ -98,119 +98,6 @@ __device__ __forceinline__ void line_op(const Tables<TC>& T, const TC (&u)[N], c
   }
 }
 
-// out = A a along the line for the symmetric, centro-symmetric 1D matrix A
-// (M or S, so A^T a = A a) given in full (Af) and by its even-odd halves
-// (Ae): the halves from n = 5 on, where they save operations (n^2/2 + 2n
-// against n^2 at even n), the full matrix below.
-template <int N, typename TC>
-__device__ __forceinline__ void sym_line(const TC* Af, const EvenOdd<TC>& Ae, const TC (&a)[N], TC (&out)[N]) {
-  if constexpr (N >= 5) {
-    contract_eo<N, TC, 1>(Ae, a, out);
-  } else {
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-      TC s = TC(0);
-#pragma unroll
-      for (int j = 0; j < N; ++j) s += Af[i * kMaxN + j] * a[j];
-      out[i] = s;
-    }
-  }
-}
-
-// out = M a along the line (M is symmetric: also M^T a)
-template <int N, typename TC, bool TRANS>
-__device__ __forceinline__ void mass_line(const Tables<TC>& T, const TC (&a)[N], TC (&out)[N]) {
-  sym_line<N, TC>(T.M, T.eM, a, out);
-}
-
-// Brick of elements per workgroup for n nodes per direction (BX x BY x BZ,
-// at most kBlock / n^2 elements); x is the fastest element index inside the
-// brick so that a wave's elements share their y and z position.
-__host__ __device__ constexpr int tile_x(int n) { return n == 2 ? 4 : n == 3 ? 4 : n == 4 ? 4 : n == 5 ? 5 : n == 6 ? 7 : n == 7 ? 5 : 4; }
-__host__ __device__ constexpr int tile_y(int n) { return n == 2 ? 4 : n == 3 ? 3 : n == 4 ? 2 : n == 5 ? 2 : 1; }
-__host__ __device__ constexpr int tile_z(int n) { return n == 2 ? 4 : n == 3 ? 2 : n == 4 ? 2 : 1; }
-// threads per workgroup of the affine apply: the brick's lines, rounded up to whole waves
-__host__ __device__ constexpr int apply_block(int n) {
-  return ((tile_x(n) * tile_y(n) * tile_z(n) * n * n + 63) / 64) * 64;
-}
-
-// Origin of logical brick tb.  The brick grid (ntx x nty x ntz) is cut into
-// slabs of CY brick rows along y; a slab is walked x fastest, then y, then z.
-// Consecutive logical bricks run on the same XCD (xcd_remap), so the bricks
-// that read an element's lines as neighbours run close in time to the brick
-// that owns it: x-neighbours 1 brick apart, y-neighbours ntx, z-neighbours
-// ntx CY (about 96 bricks), and the lines are still in that XCD's L2.  (With
-// plain x-y-z order the z-neighbours were ntx nty bricks apart and each x
-// line was fetched from HBM three times.)  Only the y-faces between slabs
-// (one in CY brick rows) read lines of bricks that run much later.
-template <int BX, int BY, int BZ>
-__device__ __forceinline__ void brick_origin(int tb, int nx, int ny, int nz, int (&o)[3]) {
-  const int ntx = (nx + BX - 1) / BX, nty = (ny + BY - 1) / BY, ntz = (nz + BZ - 1) / BZ;
-  const int CY = max(1, min(nty, 96 / ntx));
-  const int slab = ntx * CY * ntz;
-  const int g = tb / slab, r = tb - g * slab;
-  const int cy = min(CY, nty - g * CY);  // brick rows of this slab (the last one may be thinner)
-  const int bx = r % ntx, q = r / ntx;
-  o[0] = bx * BX;
-  o[1] = (g * CY + q % cy) * BY;
-  o[2] = (q / cy) * BZ;
-}
-
-// neighbour coordinate along one axis (periodic wrap), -1 on a Dirichlet boundary
-__device__ __forceinline__ int nb_coord(int c, int s, int Nd, int periodic) {
-  int v = c + (s ? 1 : -1);
-  if (v < 0 || v >= Nd) {
-    if (!periodic) return -1;
-    v = v < 0 ? Nd - 1 : 0;
-  }
-  return v;
-}
-
-// Line operator with the neighbour data reduced to the two scalars the face
-// terms need: the neighbour's trace at the shared end (U) and its raw normal
-// derivative at that end (Gr = l'(end) . line, without 1/h), both zero on a
-// side without neighbour (Dirichlet face).  Own face scalars: u[0],
-// g0 = d0.u, u[n-1], g1 = d1.u.  Same algebra as line_op.
-template <int N, typename TC, bool TRANS>
-__device__ __forceinline__ void line_op_s(const Tables<TC>& T, const TC (&u)[N], TC g0, TC g1, TC UL, TC GLr,
-                                          TC UH, TC GHr, bool hasL, bool hasH, TC GL, TC GH, TC vs, TC ih,
-                                          TC sig, TC At, TC (&b)[N]) {
-  {  // volume: vs S u (S is symmetric: also the transpose)
-    TC su[N];
-    sym_line<N, TC>(T.S, T.eS, u, su);
-#pragma unroll
-    for (int i = 0; i < N; ++i) b[i] = vs * su[i];
-  }
-  {  // upper face: this element is T^-
-    const TC g = g1 + GHr;
-    const TC J = u[N - 1] - UH;
-    const TC aP = sig * GH * (hasH ? TC(2) : TC(1));
-    const TC GAi = At * GH * ih;
-    b[N - 1] += At * aP * J - GAi * g;
-    const TC cj = GAi * J;
-#pragma unroll
-    for (int i = 0; i < N; ++i) b[i] -= cj * T.d1[i];
-  }
-  {  // lower face: this element is T^+
-    const TC g = g0 + GLr;
-    const TC J = UL - u[0];
-    const TC aP = sig * GL * (hasL ? TC(2) : TC(1));
-    const TC GAi = At * GL * ih;
-    b[0] += GAi * g - At * aP * J;
-    const TC cj = GAi * J;
-#pragma unroll
-    for (int i = 0; i < N; ++i) b[i] -= cj * T.d0[i];
-  }
-}
-
-// d0 . u (END = 0) or d1 . u (END = 1)
-template <int N, typename TC, int END>
-__device__ __forceinline__ TC dot_end(const Tables<TC>& T, const TC (&u)[N]) {
-  TC s = TC(0);
-#pragma unroll
-  for (int j = 0; j < N; ++j) s += (END ? T.d1[j] : T.d0[j]) * u[j];
-  return s;
-}
 
 // Neighbour face scalars along axis D for both sides.  In-brick neighbours
 // publish their own face scalars in F (written by their threads in this
@@ -520,6 +407,197 @@ __global__ __launch_bounds__(256) void k_diag_affine(MeshArgs<double> m, double*
   d[gid] = acc;
 }
 
+// ------------------------------------------------------------ element block-Jacobi
+// Sec. 3.4 builds preconditioners from the element blocks of the DG matrix.
+// On an axis-parallel box element with constant coefficients the diagonal
+// block is a Kronecker sum of per-element 1D operators,
+//     A_TT = M (x) M (x) L_x + M (x) L_y (x) M + L_z (x) M (x) M
+// (L_d: the 1D DG operator along d restricted to the element's own values --
+// stiffness, penalty and consistency terms of its two faces, the neighbour
+// coupling only when the element is its own neighbour -- plus the reaction
+// c |T| M on one axis), so its inverse follows from the generalized
+// eigenproblems L_d q = lambda M q (fast diagonalisation):
+//     A_TT^-1 = (Q_z (x) Q_y (x) Q_x) diag(1 / (l_z + l_y + l_x)) (Q_z (x) Q_y (x) Q_x)^T,
+// with Q_d^T M Q_d = I and Q_d^T L_d Q_d = diag(l_d).  Setup: one thread per
+// (element, axis) forms L_d column by column with the line operator, takes
+// the symmetric C L_d C (C = M^-1/2), diagonalises it by cyclic Jacobi
+// rotations and stores Q_d = C V (N x N, row = node, column = mode) and l_d.
+template <int N>
+__global__ __launch_bounds__(256) void k_bj_setup(MeshArgs<double> m, double* __restrict__ Q, double* __restrict__ lam,
+                                                  float* __restrict__ Q32, float* __restrict__ lam32) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= 3 * m.E) return;
+  const Tables<double>& T = *m.tab;
+  const int64_t e = gid / 3;
+  const int D = (int)(gid % 3);
+  const int ex = (int)(e % m.nx), ey = (int)((e / m.nx) % m.ny), ez = (int)(e / ((int64_t)m.nx * m.ny));
+  int64_t nL, nH;
+  if (D == 0) { nL = neighbour<0>(m, ex, ey, ez, 0); nH = neighbour<0>(m, ex, ey, ez, 1); }
+  else if (D == 1) { nL = neighbour<1>(m, ex, ey, ez, 0); nH = neighbour<1>(m, ex, ey, ez, 1); }
+  else { nL = neighbour<2>(m, ex, ey, ez, 0); nH = neighbour<2>(m, ex, ey, ez, 1); }
+  const double K = m.K[e], GL = m.G[6 * e + 2 * D], GH = m.G[6 * e + 2 * D + 1];
+  double L[kMaxN * kMaxN];
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    double u[N], uL[N], uH[N], b[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      u[i] = i == j ? 1.0 : 0.0;
+      uL[i] = (nL == e && i == j) ? 1.0 : 0.0;
+      uH[i] = (nH == e && i == j) ? 1.0 : 0.0;
+    }
+    line_op<N, double, false>(T, u, uL, uH, nL >= 0, nH >= 0, GL, GH, K * m.vs[D], m.ih[D], m.sg[D], m.At[D], true,
+                              b);
+#pragma unroll
+    for (int i = 0; i < N; ++i) L[i * kMaxN + j] = b[i];
+  }
+  if (D == 2 && m.R) {
+    const double cr = m.R[e] * m.vol;
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+      for (int j = 0; j < N; ++j) L[i * kMaxN + j] += cr * T.M[i * kMaxN + j];
+  }
+  // A' = C L C (symmetrised: L is symmetric up to rounding)
+  double A[kMaxN * kMaxN], V[kMaxN * kMaxN], CL[kMaxN * kMaxN];
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      double s = 0.0;
+#pragma unroll
+      for (int k = 0; k < N; ++k) s += T.Mis[i * kMaxN + k] * 0.5 * (L[k * kMaxN + j] + L[j * kMaxN + k]);
+      CL[i * kMaxN + j] = s;
+    }
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      double s = 0.0;
+#pragma unroll
+      for (int k = 0; k < N; ++k) s += CL[i * kMaxN + k] * T.Mis[k * kMaxN + j];
+      A[i * kMaxN + j] = s;
+    }
+  sym_eig_jacobi<double>(N, A, V);
+  double* q = Q + (e * 3 + D) * N * N;
+  double* l = lam + (e * 3 + D) * N;
+  float* q32 = Q32 + (e * 3 + D) * N * N;
+  float* l32 = lam32 + (e * 3 + D) * N;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      double s = 0.0;
+#pragma unroll
+      for (int k = 0; k < N; ++k) s += T.Mis[i * kMaxN + k] * V[k * kMaxN + j];
+      q[i * N + j] = s;
+      q32[i * N + j] = (float)s;
+    }
+    l[i] = A[i * kMaxN + i];
+    l32[i] = (float)A[i * kMaxN + i];
+  }
+}
+
+// z = P r with P = blockdiag(A_TT^-1) by fast diagonalisation, and the block
+// partials {<z, r>, <r, r>}.  n^2 threads per element, one line each per
+// phase: Q_x^T, Q_y^T, Q_z^T, the scaling by 1 / (l_x + l_y + l_z), Q_z,
+// Q_y, Q_x.  TV: vector type (double / float), TQ: type of the stored Q, l.
+template <int N, typename TV, typename TQ>
+__global__ __launch_bounds__(kBlock) void k_bj_apply(int64_t E, const TQ* __restrict__ Q, const TQ* __restrict__ lam,
+                                                     const TV* __restrict__ r, TV* __restrict__ z, double* partials,
+                                                     const int* skip) {
+  constexpr int NN = N * N, EPB = elems_per_block(N), PE = Lay<N, TV>::PE;
+  __shared__ TV sT[EPB * PE];
+  __shared__ TQ sQ[EPB][3 * NN], sL[EPB][3 * N];
+  __shared__ double red[kBlock / 64];
+  if (skip != nullptr && *skip) return;
+  const int tid = threadIdx.x, el = tid / NN, t = tid % NN, t1 = t % N, t2 = t / N;
+  const int64_t e = (int64_t)blockIdx.x * EPB + el;
+  const bool act = el < EPB && e < E;
+  const int le = act ? el : 0;
+  if (act) {
+    for (int i = t; i < 3 * NN; i += NN) sQ[el][i] = Q[e * 3 * NN + i];
+    for (int i = t; i < 3 * N; i += NN) sL[el][i] = lam[e * 3 * N + i];
+  }
+  __syncthreads();
+  TV* tile = sT + le * PE;
+  const TQ* qx = sQ[le];
+  const TQ* qy = sQ[le] + NN;
+  const TQ* qz = sQ[le] + 2 * NN;
+  TV rl[N], a[N], b[N];
+  // x-lines: w = Q_x^T r
+  if (act) glb_get<N, 0, TV, TV>(r, e, t1, t2, rl);
+  else {
+#pragma unroll
+    for (int i = 0; i < N; ++i) rl[i] = TV(0);
+  }
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    TV s = TV(0);
+#pragma unroll
+    for (int i = 0; i < N; ++i) s += (TV)qx[i * N + j] * rl[i];
+    b[j] = s;
+  }
+  if (act) lds_put<N, 0>(tile, t1, t2, b);  // threads without an element write nothing
+  __syncthreads();
+  lds_get<N, 1>(tile, t1, t2, a);  // y-lines: Q_y^T
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    TV s = TV(0);
+#pragma unroll
+    for (int i = 0; i < N; ++i) s += (TV)qy[i * N + j] * a[i];
+    b[j] = s;
+  }
+  if (act) lds_put<N, 1>(tile, t1, t2, b);
+  __syncthreads();
+  lds_get<N, 2>(tile, t1, t2, a);  // z-lines: Q_z^T, scale (modes j1 = t1, j2 = t2), Q_z
+  {
+    const TV lxy = (TV)sL[le][t1] + (TV)sL[le][N + t2];
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      TV s = TV(0);
+#pragma unroll
+      for (int i = 0; i < N; ++i) s += (TV)qz[i * N + j] * a[i];
+      b[j] = s / (lxy + (TV)sL[le][2 * N + j]);
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      TV s = TV(0);
+#pragma unroll
+      for (int j = 0; j < N; ++j) s += (TV)qz[i * N + j] * b[j];
+      a[i] = s;
+    }
+  }
+  if (act) lds_put<N, 2>(tile, t1, t2, a);
+  __syncthreads();
+  lds_get<N, 1>(tile, t1, t2, a);  // y-lines: Q_y
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    TV s = TV(0);
+#pragma unroll
+    for (int j = 0; j < N; ++j) s += (TV)qy[i * N + j] * a[j];
+    b[i] = s;
+  }
+  if (act) lds_put<N, 1>(tile, t1, t2, b);
+  __syncthreads();
+  lds_get<N, 0>(tile, t1, t2, a);  // x-lines: Q_x, out
+  double zr = 0.0, rr = 0.0;
+  if (act) {
+    TV* pz = z + e * NN * N;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      TV s = TV(0);
+#pragma unroll
+      for (int j = 0; j < N; ++j) s += (TV)qx[i * N + j] * a[j];
+      pz[lidx<N, 0>(t1, t2, i)] = s;
+      zr += (double)s * (double)rl[i];
+      rr += (double)rl[i] * (double)rl[i];
+    }
+  }
+  const double mine[2] = {block_sum<kBlock>(zr, red), block_sum<kBlock>(rr, red)};
+  store_partials<2>(mine, partials, blockIdx.x);
+}
+
 // g_T = u^T (dA/dtheta_T) v on affine meshes (FP64).  Per element:
 //  volume  K_T u_T^T A_vol v_T with A_vol = sum_d M (x) M (x) (At/h) S_d
 //          (dK/dtheta = K), composed like the apply:
@@ -747,9 +825,10 @@ template <int N, typename TIN, typename TOUT, typename TC, bool TRANS, bool DOT>
 static hipError_t run_apply(const MeshArgs<TC>& m, const void* x, void* y, double* partials, CgState* st,
                             int par, const int* skip, hipStream_t s) {
   const int64_t nb = affine_tiles(N, m.nx, m.ny, m.nz);
+  hipError_t e;
   hipLaunchKernelGGL((k_apply_affine<N, TIN, TOUT, TC, TRANS, DOT>), dim3((unsigned)nb), dim3(apply_block(N)), 0, s, m,
                      (const TIN*)x, (TOUT*)y, partials, skip);
-  hipError_t e = hipGetLastError();
+  e = hipGetLastError();
   if (e != hipSuccess || !DOT || st == nullptr) return e;  // st == nullptr: partials only
   return launch_finish_dot(partials, nb, st, par, s);
 }
@@ -762,6 +841,12 @@ static hipError_t run_apply_prec(int prec, const MeshArgs<double>& m64, const Me
     case 0: return run_apply<N, double, double, double, TRANS, DOT>(m64, x, y, partials, st, par, skip, s);
     case 1: return run_apply<N, float, float, float, TRANS, DOT>(m32, x, y, partials, st, par, skip, s);
     case 2: return run_apply<N, uint16_t, float, float, TRANS, DOT>(m32, x, y, partials, st, par, skip, s);
+    case 3: {  // BF16 input, tangential masses on MFMA (the operator is symmetric: A^T x is the same product)
+      const int64_t nb = affine_tiles(N, m32.nx, m32.ny, m32.nz);
+      hipError_t e = launch_apply_affine_mfma(N, DOT ? 1 : 0, m32, (const uint16_t*)x, (float*)y, partials, skip, s);
+      if (e != hipSuccess || !DOT || st == nullptr) return e;
+      return launch_finish_dot(partials, nb, st, par, s);
+    }
   }
   return hipErrorInvalidValue;
 }
@@ -832,5 +917,51 @@ hipError_t launch_dA_affine(int n, const MeshArgs<double>& m, const double* u, c
   }
   return hipErrorInvalidValue;
 }
+
+// ------------------------------------------------------------ block-Jacobi launchers
+template <int N>
+static hipError_t run_bj_setup(const MeshArgs<double>& m, double* Q, double* lam, float* Q32, float* lam32,
+                               hipStream_t s) {
+  hipLaunchKernelGGL((k_bj_setup<N>), dim3((unsigned)((3 * m.E + 255) / 256)), dim3(256), 0, s, m, Q, lam, Q32, lam32);
+  return hipGetLastError();
+}
+hipError_t launch_bj_setup(int n, const MeshArgs<double>& m, double* Q, double* lam, float* Q32, float* lam32,
+                           hipStream_t s) {
+  switch (n) {
+    case 2: return run_bj_setup<2>(m, Q, lam, Q32, lam32, s);
+    case 3: return run_bj_setup<3>(m, Q, lam, Q32, lam32, s);
+    case 4: return run_bj_setup<4>(m, Q, lam, Q32, lam32, s);
+    case 5: return run_bj_setup<5>(m, Q, lam, Q32, lam32, s);
+    case 6: return run_bj_setup<6>(m, Q, lam, Q32, lam32, s);
+    case 7: return run_bj_setup<7>(m, Q, lam, Q32, lam32, s);
+    case 8: return run_bj_setup<8>(m, Q, lam, Q32, lam32, s);
+  }
+  return hipErrorInvalidValue;
+}
+template <int N, typename TV, typename TQ>
+static hipError_t run_bj_apply(int64_t E, const TQ* Q, const TQ* lam, const TV* r, TV* z, double* partials,
+                               const int* skip, hipStream_t s) {
+  hipLaunchKernelGGL((k_bj_apply<N, TV, TQ>), dim3((unsigned)element_blocks(N, E)), dim3(kBlock), 0, s, E, Q, lam, r, z,
+                     partials, skip);
+  return hipGetLastError();
+}
+template <typename TV, typename TQ>
+hipError_t launch_bj_apply(int n, int64_t E, const TQ* Q, const TQ* lam, const TV* r, TV* z, double* partials,
+                           const int* skip, hipStream_t s) {
+  switch (n) {
+    case 2: return run_bj_apply<2, TV, TQ>(E, Q, lam, r, z, partials, skip, s);
+    case 3: return run_bj_apply<3, TV, TQ>(E, Q, lam, r, z, partials, skip, s);
+    case 4: return run_bj_apply<4, TV, TQ>(E, Q, lam, r, z, partials, skip, s);
+    case 5: return run_bj_apply<5, TV, TQ>(E, Q, lam, r, z, partials, skip, s);
+    case 6: return run_bj_apply<6, TV, TQ>(E, Q, lam, r, z, partials, skip, s);
+    case 7: return run_bj_apply<7, TV, TQ>(E, Q, lam, r, z, partials, skip, s);
+    case 8: return run_bj_apply<8, TV, TQ>(E, Q, lam, r, z, partials, skip, s);
+  }
+  return hipErrorInvalidValue;
+}
+template hipError_t launch_bj_apply<double, double>(int, int64_t, const double*, const double*, const double*, double*,
+                                                    double*, const int*, hipStream_t);
+template hipError_t launch_bj_apply<float, float>(int, int64_t, const float*, const float*, const float*, float*,
+                                                  double*, const int*, hipStream_t);
 
 }  // namespace dg

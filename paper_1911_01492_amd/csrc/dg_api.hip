@@ -40,6 +40,8 @@ struct dg_ctx {
   float* vert32;
   double* dinv64;
   float* dinv32;
+  double *bjQ64, *bjL64;  // block-Jacobi factors (affine meshes): Q_d and l_d per element and axis
+  float *bjQ32, *bjL32;
   double *r64, *p64, *q64;
   double *z64, *s64, *w64;   // single-reduction CG
   float *r32, *d32, *p32, *q32;
@@ -313,6 +315,20 @@ bool build_tables(int n, Tables<double>& T) {
       Bt[i * n + j] = B[j * n + i];
       Dgt[i * n + j] = Dg[j * n + i];
     }
+  {  // M^{-1/2} = V diag(mu^{-1/2}) V^T from the eigen-decomposition of M
+    double a[kMaxN * kMaxN], v[kMaxN * kMaxN];
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) a[i * kMaxN + j] = Mv[i * n + j];
+    sym_eig_jacobi<double>(n, a, v);
+    for (int i = 0; i < n; ++i) {
+      if (!(a[i * kMaxN + i] > 0.0)) return false;
+      for (int j = 0; j < n; ++j) {
+        double s = 0.0;
+        for (int k = 0; k < n; ++k) s += v[i * kMaxN + k] * v[j * kMaxN + k] / std::sqrt(a[k * kMaxN + k]);
+        T.Mis[i * kMaxN + j] = s;
+      }
+    }
+  }
   return even_odd(n, Mv, 1, T.eM) && even_odd(n, Sv, 1, T.eS) && even_odd(n, B, 1, T.eB) &&
          even_odd(n, Bt, 1, T.eBt) && even_odd(n, Dg, -1, T.eDg) && even_odd(n, Dgt, -1, T.eDgt);
 }
@@ -320,6 +336,7 @@ bool build_tables(int n, Tables<double>& T) {
 void tables_to_f32(const Tables<double>& a, Tables<float>& b) {
   for (int i = 0; i < kMaxN * kMaxN; ++i) {
     b.M[i] = (float)a.M[i];
+    b.Mis[i] = (float)a.Mis[i];
     b.S[i] = (float)a.S[i];
     b.B[i] = (float)a.B[i];
     b.D[i] = (float)a.D[i];
@@ -340,8 +357,8 @@ void tables_to_f32(const Tables<double>& a, Tables<float>& b) {
 
 // ------------------------------------------------------------------ workspace
 struct Layout {
-  size_t tab64, tab32, K64, K32, G64, G32, R64, R32, vert64, vert32, dinv64, dinv32, r64, p64, q64, r32, d32, p32,
-      q32, p16, z64, s64, w64, fb, partials, st, flags, total;
+  size_t tab64, tab32, K64, K32, G64, G32, R64, R32, vert64, vert32, dinv64, dinv32, bjQ64, bjL64, bjQ32, bjL32, r64,
+      p64, q64, r32, d32, p32, q32, p16, z64, s64, w64, fb, partials, st, flags, total;
 };
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
@@ -385,6 +402,10 @@ Layout layout(const dg_mesh_desc* m) {
   L.vert32 = take(tri ? nv * 3 * sizeof(float) : 0);
   L.dinv64 = take(nd * sizeof(double));
   L.dinv32 = take(nd * sizeof(float));
+  L.bjQ64 = take(tri ? 0 : (size_t)E * 3 * n * n * sizeof(double));
+  L.bjL64 = take(tri ? 0 : (size_t)E * 3 * n * sizeof(double));
+  L.bjQ32 = take(tri ? 0 : (size_t)E * 3 * n * n * sizeof(float));
+  L.bjL32 = take(tri ? 0 : (size_t)E * 3 * n * sizeof(float));
   L.r64 = take(nd * sizeof(double));
   L.p64 = take(nd * sizeof(double));
   L.q64 = take(nd * sizeof(double));
@@ -493,7 +514,10 @@ hipError_t compute_dinv(dg_ctx* c, hipStream_t s, const int* run = nullptr) {
   hipError_t e = c->trilinear ? launch_diag_trilinear(c->n, m64, c->r64, run, s)
                               : launch_diag_affine(c->n, m64, c->r64, run, s);
   if (e != hipSuccess) return e;
-  return launch_inv_diag(c->ndof, c->r64, c->dinv64, c->dinv32, run, s);
+  e = launch_inv_diag(c->ndof, c->r64, c->dinv64, c->dinv32, run, s);
+  if (e != hipSuccess || c->trilinear) return e;
+  // element block-Jacobi factors (cheap: one small eigenproblem per element and axis)
+  return launch_bj_setup(c->n, m64, c->bjQ64, c->bjL64, c->bjQ32, c->bjL32, s);
 }
 
 bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
@@ -566,6 +590,10 @@ int dg_setup(const dg_mesh_desc* mesh, dg_ctx** out, void* stream) {
   c->vert32 = c->trilinear ? (float*)(w + L.vert32) : nullptr;
   c->dinv64 = (double*)(w + L.dinv64);
   c->dinv32 = (float*)(w + L.dinv32);
+  c->bjQ64 = c->trilinear ? nullptr : (double*)(w + L.bjQ64);
+  c->bjL64 = c->trilinear ? nullptr : (double*)(w + L.bjL64);
+  c->bjQ32 = c->trilinear ? nullptr : (float*)(w + L.bjQ32);
+  c->bjL32 = c->trilinear ? nullptr : (float*)(w + L.bjL32);
   c->r64 = (double*)(w + L.r64);
   c->p64 = (double*)(w + L.p64);
   c->q64 = (double*)(w + L.q64);
@@ -648,8 +676,10 @@ static int apply_common(dg_ctx* c, int prec, int trans, const void* x, void* y, 
   if (!c) return fail(nullptr, DG_ERR_ARG, "ctx is NULL");
   if (!x || !y) return fail(c, DG_ERR_ARG, "x or y is NULL");
   if (x == y) return fail(c, DG_ERR_ARG, "x and y must not alias");
-  if (prec != DG_F64 && prec != DG_F32 && prec != DG_BF16)
+  if (prec != DG_F64 && prec != DG_F32 && prec != DG_BF16 && prec != DG_BF16_MFMA)
     return fail(c, DG_ERR_UNSUPPORTED, "unknown precision");
+  if (prec == DG_BF16_MFMA && (c->trilinear || !mfma_apply_supported(c->n)))
+    return fail(c, DG_ERR_UNSUPPORTED, "DG_BF16_MFMA needs an affine mesh and degree <= 4");
   const size_t ein = prec == DG_F64 ? 8 : (prec == DG_F32 ? 4 : 2);
   const size_t eout = prec == DG_F64 ? 8 : 4;
   if (!aligned(x, ein) || !aligned(y, eout)) return fail(c, DG_ERR_ARG, "misaligned x or y");
@@ -776,6 +806,48 @@ int pcg64(dg_ctx* c, const dg_cg_opts* o, const double* b, double* x, int maxit,
   return DG_OK;
 }
 
+// FP64 PCG (Alg. PCG) with the element block-Jacobi preconditioner: z = P r
+// is an element-local kernel of its own (fast diagonalisation), so each
+// iteration runs the apply (with <p, q>), r -= lambda q (with <r, r>), z = P r
+// (with <z, r>) and x += lambda p, p = z + beta p, where the last kernel reads
+// z in place of the Jacobi-scaled residual.
+int pcg64_block(dg_ctx* c, const dg_cg_opts* o, const double* b, double* x, int maxit, int& iters, bool& broke,
+                hipStream_t s) {
+  const int64_t n = c->ndof;
+  CgState* st = &c->st[0];
+  const int check = o->check_every > 0 ? o->check_every : 32;
+  const int64_t nbj = element_blocks(c->n, c->E);
+  HIP_TRY(c, apply_any(c, DG_F64, o->transpose, 0, x, c->q64, nullptr, 0, nullptr, s));
+  // r = b - A x, <r, r>, <b, b> (z64 receives r and is overwritten below)
+  HIP_TRY(c, (launch_cg_init<double, double, double, double>(n, b, c->q64, c->r64, c->z64, nullptr, o->rtol, st,
+                                                            c->partials, s)));
+  HIP_TRY(c, (launch_bj_apply<double, double>(c->n, c->E, c->bjQ64, c->bjL64, c->r64, c->z64, c->partials,
+                                              &st->done, s)));
+  HIP_TRY(c, launch_bj_finish(c->partials, nbj, st, 0, s));
+  HIP_TRY(c, hipMemcpyAsync(c->p64, c->z64, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  CgState hs;
+  int rc = read_state(c, 0, hs, s);
+  if (rc != DG_OK) return rc;
+  int it = 0;
+  while (!hs.done && it < maxit) {
+    const int chunk = std::min(check, maxit - it);
+    for (int j = 0; j < chunk; ++j, ++it) {
+      const int par = it & 1;
+      HIP_TRY(c, apply_any(c, DG_F64, o->transpose, 1, c->p64, c->q64, st, par, &st->done, s));
+      HIP_TRY(c, (launch_cg_update<double, double>(n, c->r64, c->q64, nullptr, par, st, c->partials, s)));
+      HIP_TRY(c, (launch_bj_apply<double, double>(c->n, c->E, c->bjQ64, c->bjL64, c->r64, c->z64, c->partials,
+                                                  &st->done, s)));
+      HIP_TRY(c, launch_bj_finish(c->partials, nbj, st, par ^ 1, s));
+      HIP_TRY(c, (launch_cg_pupdate<double, double, double, double>(n, x, c->z64, c->p64, nullptr, par, st, 0, s)));
+    }
+    rc = read_state(c, 0, hs, s);
+    if (rc != DG_OK) return rc;
+  }
+  iters = hs.iters;
+  broke = hs.breakdown != 0;
+  return DG_OK;
+}
+
 // Single-reduction PCG in FP64 (Chronopoulos-Gear recurrences): per iteration
 // one fused vector kernel, the apply w = A z with <z, w>, and one finish over
 // both partial sets (the other sums of Alg. PCG are carried by recurrences).
@@ -838,7 +910,7 @@ int pcg_inner(dg_ctx* c, const dg_cg_opts* o, int prec, bool fresh, double inner
   const int64_t n = c->ndof;
   const float* dinv = o->precond == DG_PC_JACOBI ? c->dinv32 : nullptr;
   CgState* st = &c->st[1];
-  TP* p = prec == DG_BF16 ? (TP*)c->p16 : (TP*)c->p32;
+  TP* p = prec != DG_F32 ? (TP*)c->p16 : (TP*)c->p32;
   const int check = o->check_every > 0 ? o->check_every : 32;
   if (fresh) {
     par0 = 0;
@@ -891,7 +963,7 @@ int dc_solve(dg_ctx* c, const dg_cg_opts* o, int prec, const double* b, double* 
                                        : (keep ? 0.1 : (prec == DG_F32 ? 1e-5 : 1e-2));
   const int max_outer = o->max_outer > 0 ? o->max_outer : (keep ? 200 : 30);
   const float* dinv = o->precond == DG_PC_JACOBI ? c->dinv32 : nullptr;
-  TP* p = prec == DG_BF16 ? (TP*)c->p16 : (TP*)c->p32;
+  TP* p = prec != DG_F32 ? (TP*)c->p16 : (TP*)c->p32;
   bool fresh = true;
   int last_par = 0;
   int rc;
@@ -954,9 +1026,16 @@ int dg_cg_solve(dg_ctx* c, const dg_cg_opts* o, const double* b, double* x, dg_c
   if (!c) return fail(nullptr, DG_ERR_ARG, "ctx is NULL");
   if (!o || !b || !x || !info) return fail(c, DG_ERR_ARG, "opts, b, x or info is NULL");
   if (b == x) return fail(c, DG_ERR_ARG, "b and x must not alias");
-  if (o->prec_inner != DG_F64 && o->prec_inner != DG_F32 && o->prec_inner != DG_BF16)
+  if (o->prec_inner != DG_F64 && o->prec_inner != DG_F32 && o->prec_inner != DG_BF16 &&
+      o->prec_inner != DG_BF16_MFMA)
     return fail(c, DG_ERR_UNSUPPORTED, "unknown inner precision");
-  if (o->precond != DG_PC_NONE && o->precond != DG_PC_JACOBI) return fail(c, DG_ERR_ARG, "unknown preconditioner");
+  if (o->prec_inner == DG_BF16_MFMA && (c->trilinear || !mfma_apply_supported(c->n)))
+    return fail(c, DG_ERR_UNSUPPORTED, "DG_BF16_MFMA needs an affine mesh and degree <= 4");
+  if (o->precond != DG_PC_NONE && o->precond != DG_PC_JACOBI && o->precond != DG_PC_BLOCK_JACOBI)
+    return fail(c, DG_ERR_ARG, "unknown preconditioner");
+  if (o->precond == DG_PC_BLOCK_JACOBI &&
+      (c->trilinear || o->prec_inner != DG_F64 || o->cg_variant != DG_CG_STANDARD))
+    return fail(c, DG_ERR_UNSUPPORTED, "block-Jacobi is built for FP64 PCG (standard variant) on affine meshes");
   if (o->dc_mode != DG_DC_RESTART && o->dc_mode != DG_DC_KEEP) return fail(c, DG_ERR_ARG, "unknown dc_mode");
   if (o->cg_variant != DG_CG_STANDARD && o->cg_variant != DG_CG_SINGLE_REDUCTION)
     return fail(c, DG_ERR_ARG, "unknown cg_variant");
@@ -977,7 +1056,8 @@ int dg_cg_solve(dg_ctx* c, const dg_cg_opts* o, const double* b, double* x, dg_c
     for (int attempt = 0;; ++attempt) {
       int its = 0;
       rc = o->cg_variant == DG_CG_SINGLE_REDUCTION ? pcg64_single(c, o, b, x, o->maxit - total, its, broke, s)
-                                                   : pcg64(c, o, b, x, o->maxit - total, its, broke, s);
+           : o->precond == DG_PC_BLOCK_JACOBI    ? pcg64_block(c, o, b, x, o->maxit - total, its, broke, s)
+                                                 : pcg64(c, o, b, x, o->maxit - total, its, broke, s);
       if (rc != DG_OK) return rc;
       total += its;
       rc = true_residual(c, o->transpose, b, x, rel, s);
@@ -988,7 +1068,7 @@ int dg_cg_solve(dg_ctx* c, const dg_cg_opts* o, const double* b, double* x, dg_c
   } else {
     int outer = 0;
     rc = o->prec_inner == DG_F32 ? dc_solve<float>(c, o, DG_F32, b, x, total, outer, broke, rel, s)
-                                 : dc_solve<uint16_t>(c, o, DG_BF16, b, x, total, outer, broke, rel, s);
+                                 : dc_solve<uint16_t>(c, o, o->prec_inner, b, x, total, outer, broke, rel, s);
     if (rc != DG_OK) return rc;
     info->outer_iters = outer;
   }

@@ -45,7 +45,50 @@ struct Tables {
   EvenOdd<T> eB, eBt;   // B and B^T (centro-symmetric)
   EvenOdd<T> eDg, eDgt; // Dg and Dg^T, Dg the collocation derivative on the Gauss
                         // points (Dg B = D; centro-antisymmetric)
+  T Mis[kMaxN * kMaxN]; // M^{-1/2} (symmetric), for the generalized eigenproblems of
+                        // the element block-Jacobi preconditioner
 };
+
+// Eigen-decomposition of a symmetric n x n matrix (row stride kMaxN) by the
+// cyclic Jacobi method (Jacobi 1846; the row-cyclic ordering with the
+// symmetric 2 x 2 Schur rotation as in Golub and Van Loan, Matrix
+// Computations, Sec. 8.5): a is overwritten (its diagonal holds the
+// eigenvalues), v receives the eigenvectors as columns.  Sweeps stop when
+// every off-diagonal entry is negligible against its two diagonal entries.
+template <typename T>
+__host__ __device__ inline void sym_eig_jacobi(int n, T* a, T* v) {
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) v[i * kMaxN + j] = i == j ? T(1) : T(0);
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    bool rotated = false;
+    for (int p = 0; p < n - 1; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        const T apq = a[p * kMaxN + q];
+        const T app = a[p * kMaxN + p], aqq = a[q * kMaxN + q];
+        if (apq == T(0) || (T)1e-17 * (T)1e-17 * app * aqq >= apq * apq) continue;
+        rotated = true;
+        const T tau = (aqq - app) / (T(2) * apq);
+        const T t = (tau >= T(0) ? T(1) : T(-1)) / ((tau >= T(0) ? tau : -tau) + sqrt(T(1) + tau * tau));
+        const T c = T(1) / sqrt(T(1) + t * t), s = t * c;
+        for (int k = 0; k < n; ++k) {  // columns p, q of a J
+          const T akp = a[k * kMaxN + p], akq = a[k * kMaxN + q];
+          a[k * kMaxN + p] = c * akp - s * akq;
+          a[k * kMaxN + q] = s * akp + c * akq;
+        }
+        for (int k = 0; k < n; ++k) {  // rows p, q of J^T (a J)
+          const T apk = a[p * kMaxN + k], aqk = a[q * kMaxN + k];
+          a[p * kMaxN + k] = c * apk - s * aqk;
+          a[q * kMaxN + k] = s * apk + c * aqk;
+        }
+        for (int k = 0; k < n; ++k) {  // v J
+          const T vkp = v[k * kMaxN + p], vkq = v[k * kMaxN + q];
+          v[k * kMaxN + p] = c * vkp - s * vkq;
+          v[k * kMaxN + q] = s * vkp + c * vkq;
+        }
+      }
+    if (!rotated) break;
+  }
+}
 
 // Mesh data passed by value to the kernels.
 template <typename T>

@@ -40,6 +40,21 @@ int64_t vec_blocks(int64_t n);
 hipError_t launch_apply_affine(int n, int prec, int trans, int dot, const MeshArgs<double>& m64,
                                const MeshArgs<float>& m32, const void* x, void* y, double* partials,
                                CgState* st, int par, const int* skip, hipStream_t s);
+// BF16-input affine apply with the tangential masses on MFMA (n = 2..5):
+// partials only (one per brick, as launch_apply_affine); the caller finishes.
+bool mfma_apply_supported(int n);
+hipError_t launch_apply_affine_mfma(int n, int dot, const MeshArgs<float>& m, const uint16_t* x, float* y,
+                                    double* partials, const int* skip, hipStream_t s);
+// element block-Jacobi (axis-parallel affine meshes): per element and axis the
+// fast-diagonalisation factors Q_d (n x n) and l_d (n), FP64 and FP32 copies;
+// z = P r with the block partials {<z, r>, <r, r>} (element_blocks(n, E) of them)
+hipError_t launch_bj_setup(int n, const MeshArgs<double>& m, double* Q, double* lam, float* Q32, float* lam32,
+                           hipStream_t s);
+template <typename TV, typename TQ>
+hipError_t launch_bj_apply(int n, int64_t E, const TQ* Q, const TQ* lam, const TV* r, TV* z, double* partials,
+                           const int* skip, hipStream_t s);
+// st->rho[idx] = <z, r> from the block-Jacobi partials (nothing once the solve stopped)
+hipError_t launch_bj_finish(const double* partials, int64_t nblocks, CgState* st, int idx, hipStream_t s);
 hipError_t launch_face_coef(const MeshArgs<double>& m, double* G64, float* G32, hipStream_t s);
 hipError_t launch_finish_dot(const double* partials, int64_t nblocks, CgState* st, int par, hipStream_t s);
 // diagonal kernels: run != nullptr && *run == 0 makes them return at once

@@ -112,4 +112,118 @@ __device__ __forceinline__ void contract_eo(const EvenOdd<TC>& A, const TC (&a)[
   }
 }
 
+// out = A a along the line for the symmetric, centro-symmetric 1D matrix A
+// (M or S, so A^T a = A a) given in full (Af) and by its even-odd halves
+// (Ae): the halves from n = 5 on, where they save operations (n^2/2 + 2n
+// against n^2 at even n), the full matrix below.
+template <int N, typename TC>
+__device__ __forceinline__ void sym_line(const TC* Af, const EvenOdd<TC>& Ae, const TC (&a)[N], TC (&out)[N]) {
+  if constexpr (N >= 5) {
+    contract_eo<N, TC, 1>(Ae, a, out);
+  } else {
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      TC s = TC(0);
+#pragma unroll
+      for (int j = 0; j < N; ++j) s += Af[i * kMaxN + j] * a[j];
+      out[i] = s;
+    }
+  }
+}
+
+// out = M a along the line (M is symmetric: also M^T a)
+template <int N, typename TC, bool TRANS>
+__device__ __forceinline__ void mass_line(const Tables<TC>& T, const TC (&a)[N], TC (&out)[N]) {
+  sym_line<N, TC>(T.M, T.eM, a, out);
+}
+
+// Line operator with the neighbour data reduced to the two scalars the face
+// terms need: the neighbour's trace at the shared end (U) and its raw normal
+// derivative at that end (Gr = l'(end) . line, without 1/h), both zero on a
+// side without neighbour (Dirichlet face).  Own face scalars: u[0],
+// g0 = d0.u, u[n-1], g1 = d1.u.  Same algebra as line_op.
+template <int N, typename TC, bool TRANS>
+__device__ __forceinline__ void line_op_s(const Tables<TC>& T, const TC (&u)[N], TC g0, TC g1, TC UL, TC GLr,
+                                          TC UH, TC GHr, bool hasL, bool hasH, TC GL, TC GH, TC vs, TC ih,
+                                          TC sig, TC At, TC (&b)[N]) {
+  {  // volume: vs S u (S is symmetric: also the transpose)
+    TC su[N];
+    sym_line<N, TC>(T.S, T.eS, u, su);
+#pragma unroll
+    for (int i = 0; i < N; ++i) b[i] = vs * su[i];
+  }
+  {  // upper face: this element is T^-
+    const TC g = g1 + GHr;
+    const TC J = u[N - 1] - UH;
+    const TC aP = sig * GH * (hasH ? TC(2) : TC(1));
+    const TC GAi = At * GH * ih;
+    b[N - 1] += At * aP * J - GAi * g;
+    const TC cj = GAi * J;
+#pragma unroll
+    for (int i = 0; i < N; ++i) b[i] -= cj * T.d1[i];
+  }
+  {  // lower face: this element is T^+
+    const TC g = g0 + GLr;
+    const TC J = UL - u[0];
+    const TC aP = sig * GL * (hasL ? TC(2) : TC(1));
+    const TC GAi = At * GL * ih;
+    b[0] += GAi * g - At * aP * J;
+    const TC cj = GAi * J;
+#pragma unroll
+    for (int i = 0; i < N; ++i) b[i] -= cj * T.d0[i];
+  }
+}
+
+// d0 . u (END = 0) or d1 . u (END = 1)
+template <int N, typename TC, int END>
+__device__ __forceinline__ TC dot_end(const Tables<TC>& T, const TC (&u)[N]) {
+  TC s = TC(0);
+#pragma unroll
+  for (int j = 0; j < N; ++j) s += (END ? T.d1[j] : T.d0[j]) * u[j];
+  return s;
+}
+
+// Brick of elements per workgroup for n nodes per direction (BX x BY x BZ,
+// at most kBlock / n^2 elements); x is the fastest element index inside the
+// brick so that a wave's elements share their y and z position.
+__host__ __device__ constexpr int tile_x(int n) { return n == 2 ? 4 : n == 3 ? 4 : n == 4 ? 4 : n == 5 ? 5 : n == 6 ? 7 : n == 7 ? 5 : 4; }
+__host__ __device__ constexpr int tile_y(int n) { return n == 2 ? 4 : n == 3 ? 3 : n == 4 ? 2 : n == 5 ? 2 : 1; }
+__host__ __device__ constexpr int tile_z(int n) { return n == 2 ? 4 : n == 3 ? 2 : n == 4 ? 2 : 1; }
+// threads per workgroup of the affine apply: the brick's lines, rounded up to whole waves
+__host__ __device__ constexpr int apply_block(int n) {
+  return ((tile_x(n) * tile_y(n) * tile_z(n) * n * n + 63) / 64) * 64;
+}
+
+// Origin of logical brick tb.  The brick grid (ntx x nty x ntz) is cut into
+// slabs of CY brick rows along y; a slab is walked x fastest, then y, then z.
+// Consecutive logical bricks run on the same XCD (xcd_remap), so the bricks
+// that read an element's lines as neighbours run close in time to the brick
+// that owns it: x-neighbours 1 brick apart, y-neighbours ntx, z-neighbours
+// ntx CY (about 96 bricks), and the lines are still in that XCD's L2.  (With
+// plain x-y-z order the z-neighbours were ntx nty bricks apart and each x
+// line was fetched from HBM three times.)  Only the y-faces between slabs
+// (one in CY brick rows) read lines of bricks that run much later.
+template <int BX, int BY, int BZ>
+__device__ __forceinline__ void brick_origin(int tb, int nx, int ny, int nz, int (&o)[3]) {
+  const int ntx = (nx + BX - 1) / BX, nty = (ny + BY - 1) / BY, ntz = (nz + BZ - 1) / BZ;
+  const int CY = max(1, min(nty, 96 / ntx));
+  const int slab = ntx * CY * ntz;
+  const int g = tb / slab, r = tb - g * slab;
+  const int cy = min(CY, nty - g * CY);  // brick rows of this slab (the last one may be thinner)
+  const int bx = r % ntx, q = r / ntx;
+  o[0] = bx * BX;
+  o[1] = (g * CY + q % cy) * BY;
+  o[2] = (q / cy) * BZ;
+}
+
+// neighbour coordinate along one axis (periodic wrap), -1 on a Dirichlet boundary
+__device__ __forceinline__ int nb_coord(int c, int s, int Nd, int periodic) {
+  int v = c + (s ? 1 : -1);
+  if (v < 0 || v >= Nd) {
+    if (!periodic) return -1;
+    v = v < 0 ? Nd - 1 : 0;
+  }
+  return v;
+}
+
 }  // namespace dg

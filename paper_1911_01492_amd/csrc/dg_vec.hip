@@ -428,7 +428,8 @@ enum FinishMode {
   FIN_UPDATE = 3,    // 2 values: rho[par^1], rr; iters++; done when rr <= tol2
   FIN_DC = 4,        // 2 values: rr, bb
   FIN_TRUE = 5,      // 2 values: true_rr, true_bb
-  FIN_REPLACE = 6    // 3 values: true_rr (= rr), true_bb, rho[par^1]; restarts the inner stop test
+  FIN_REPLACE = 6,   // 3 values: true_rr (= rr), true_bb, rho[par^1]; restarts the inner stop test
+  FIN_BJ = 7         // 2 values: rho[par] = <z, r> of the block-Jacobi z (skipped once stopped)
 };
 
 constexpr int kFinishBlock = 1024;
@@ -440,7 +441,7 @@ __global__ __launch_bounds__(kFinishBlock) void k_finish(const double* partials,
     // a new iteration starts: the deferred x update of the last one has been applied
     if (threadIdx.x == 0) st->xpend = 0;
   }
-  if (MODE == FIN_DOT || MODE == FIN_UPDATE) {
+  if (MODE == FIN_DOT || MODE == FIN_UPDATE || MODE == FIN_BJ) {
     if (st->done) return;
   }
   double t[NV];
@@ -474,6 +475,12 @@ __global__ __launch_bounds__(kFinishBlock) void k_finish(const double* partials,
     st->xpend = 1;
     if (t[1] <= st->tol2) st->done = 1;
     if (!finite_d(t[0]) || !finite_d(t[1])) {
+      st->breakdown = 1;
+      st->done = 1;
+    }
+  } else if (MODE == FIN_BJ) {
+    st->rho[par] = t[0];
+    if (!finite_d(t[0]) || !(t[0] > 0.0)) {
       st->breakdown = 1;
       st->done = 1;
     }
@@ -513,6 +520,9 @@ static hipError_t finish(const double* partials, int64_t nb, CgState* st, int pa
 
 hipError_t launch_finish_dot(const double* partials, int64_t nblocks, CgState* st, int par, hipStream_t s) {
   return finish<1, FIN_DOT>(partials, nblocks, st, par, 0.0, s);
+}
+hipError_t launch_bj_finish(const double* partials, int64_t nblocks, CgState* st, int idx, hipStream_t s) {
+  return finish<2, FIN_BJ>(partials, nblocks, st, idx, 0.0, s);
 }
 
 // ---------------------------------------------------------------- launchers

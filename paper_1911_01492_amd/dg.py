@@ -23,11 +23,11 @@ LIB_PATH = os.path.join(_HERE, "libdg.so")
 
 DG_OK, DG_NOT_CONVERGED, DG_BREAKDOWN = 0, 1, 2
 DG_ERR_ARG, DG_ERR_UNSUPPORTED, DG_ERR_DEVICE = -1, -2, -3
-PREC = {"f64": 0, "f32": 1, "bf16": 2}
+PREC = {"f64": 0, "f32": 1, "bf16": 2, "bf16_mfma": 3}
 BC = {"dirichlet": 0, "periodic": 1}
-PRECOND = {"none": 0, "jacobi": 1}
-_IN_DTYPE = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16}
-_OUT_DTYPE = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.float32}
+PRECOND = {"none": 0, "jacobi": 1, "block_jacobi": 2}
+_IN_DTYPE = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16, "bf16_mfma": torch.bfloat16}
+_OUT_DTYPE = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.float32, "bf16_mfma": torch.float32}
 
 #: every function declared in include/dg.h
 ABI_FUNCTIONS = ["dg_query_workspace", "dg_setup", "dg_set_theta", "dg_set_reaction", "dg_apply", "dg_apply_transpose",
@@ -201,7 +201,8 @@ class DGOperator:
     def apply(self, x: torch.Tensor, prec: str = "f64", out: Optional[torch.Tensor] = None,
               transpose: bool = False, stream=None) -> torch.Tensor:
         """y = A x (transpose: A^T x).  prec f64 (double in/out), f32 (float in/out),
-        bf16 (bfloat16 in, float out)."""
+        bf16 (bfloat16 in, float out), bf16_mfma (as bf16, tangential masses on the
+        matrix cores; affine meshes, degree <= 4)."""
         self._vec(x, _IN_DTYPE[prec])
         y = torch.empty(self.ndof, dtype=_OUT_DTYPE[prec], device=x.device) if out is None else out
         self._vec(y, _OUT_DTYPE[prec])
