@@ -327,6 +327,28 @@ def main():
             del yy
         del X
         torch.cuda.empty_cache()
+    if want("multi_q4_64"):
+        # multiple right-hand sides Y = A X (one launch, the vectors as the second grid dimension)
+        for R in (2, 4):
+            Xm = x.unsqueeze(0).repeat(R, 1).contiguous()
+            Ym = op.apply_multi(Xm)
+            for _ in range(3):
+                op.apply_multi(Xm, out=Ym)
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(10):
+                op.apply_multi(Xm, out=Ym)
+            e1.record()
+            torch.cuda.synchronize()
+            tm = e0.elapsed_time(e1) / 1e3 / 10
+            extras[f"apply_multi_f64_r{R}_{wl}"] = {"ms": round(tm * 1e3, 4),
+                                                   "gdofs_per_vector": round(R * op.ndof / tm / 1e9, 3),
+                                                   "single_gdofs": round(gdofs, 3)}
+            log(f"apply_multi f64 R={R}: {extras[f'apply_multi_f64_r{R}_{wl}']}")
+            del Xm, Ym
+        torch.cuda.empty_cache()
     if want("cg_q4_64"):
         b3 = dev(I.uniform_vector(op.ndof, seed=I.S_B))
         for prec, mode in CG_VARIANTS:

@@ -265,6 +265,9 @@ __global__ __launch_bounds__(apply_block(N)) void k_apply_affine(MeshArgs<TC> m,
   __shared__ TC sFx[F_IN_S2 ? 1 : SLOTS * 4 * NN];
   __shared__ double red[BLOCK / 64];
   if (skip != nullptr && *skip) return;
+  // vector blockIdx.y of a multi-vector apply (the vectors follow each other)
+  x += (size_t)blockIdx.y * (size_t)m.E * N3;
+  y += (size_t)blockIdx.y * (size_t)m.E * N3;
   TC* F = F_IN_S2 ? sS2 : sFx;
   const Tables<TC>& T = *m.tab;
   // brick coordinates: uniform per workgroup (scalar arithmetic)
@@ -823,11 +826,11 @@ int64_t affine_tiles(int n, int nx, int ny, int nz) {
 
 template <int N, typename TIN, typename TOUT, typename TC, bool TRANS, bool DOT>
 static hipError_t run_apply(const MeshArgs<TC>& m, const void* x, void* y, double* partials, CgState* st,
-                            int par, const int* skip, hipStream_t s) {
+                            int par, const int* skip, hipStream_t s, int nrhs = 1) {
   const int64_t nb = affine_tiles(N, m.nx, m.ny, m.nz);
   hipError_t e;
-  hipLaunchKernelGGL((k_apply_affine<N, TIN, TOUT, TC, TRANS, DOT>), dim3((unsigned)nb), dim3(apply_block(N)), 0, s, m,
-                     (const TIN*)x, (TOUT*)y, partials, skip);
+  hipLaunchKernelGGL((k_apply_affine<N, TIN, TOUT, TC, TRANS, DOT>), dim3((unsigned)nb, (unsigned)nrhs),
+                     dim3(apply_block(N)), 0, s, m, (const TIN*)x, (TOUT*)y, partials, skip);
   e = hipGetLastError();
   if (e != hipSuccess || !DOT || st == nullptr) return e;  // st == nullptr: partials only
   return launch_finish_dot(partials, nb, st, par, s);
@@ -914,6 +917,37 @@ hipError_t launch_dA_affine(int n, const MeshArgs<double>& m, const double* u, c
     case 6: return run_dA<6>(m, u, v, g, s);
     case 7: return run_dA<7>(m, u, v, g, s);
     case 8: return run_dA<8>(m, u, v, g, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+// ------------------------------------------------------------ multi-vector apply
+template <int N, bool TRANS>
+static hipError_t run_multi(int prec, int nrhs, const MeshArgs<double>& m64, const MeshArgs<float>& m32, const void* x,
+                            void* y, hipStream_t s) {
+  switch (prec) {
+    case 0: return run_apply<N, double, double, double, TRANS, false>(m64, x, y, nullptr, nullptr, 0, nullptr, s, nrhs);
+    case 1: return run_apply<N, float, float, float, TRANS, false>(m32, x, y, nullptr, nullptr, 0, nullptr, s, nrhs);
+    case 2: return run_apply<N, uint16_t, float, float, TRANS, false>(m32, x, y, nullptr, nullptr, 0, nullptr, s, nrhs);
+    case 3: return launch_apply_affine_mfma(N, 0, m32, (const uint16_t*)x, (float*)y, nullptr, nullptr, s, nrhs);
+  }
+  return hipErrorInvalidValue;
+}
+template <int N>
+static hipError_t run_multi_n(int prec, int trans, int nrhs, const MeshArgs<double>& m64, const MeshArgs<float>& m32,
+                              const void* x, void* y, hipStream_t s) {
+  return trans ? run_multi<N, true>(prec, nrhs, m64, m32, x, y, s) : run_multi<N, false>(prec, nrhs, m64, m32, x, y, s);
+}
+hipError_t launch_apply_affine_multi(int n, int prec, int trans, int nrhs, const MeshArgs<double>& m64,
+                                     const MeshArgs<float>& m32, const void* x, void* y, hipStream_t s) {
+  switch (n) {
+    case 2: return run_multi_n<2>(prec, trans, nrhs, m64, m32, x, y, s);
+    case 3: return run_multi_n<3>(prec, trans, nrhs, m64, m32, x, y, s);
+    case 4: return run_multi_n<4>(prec, trans, nrhs, m64, m32, x, y, s);
+    case 5: return run_multi_n<5>(prec, trans, nrhs, m64, m32, x, y, s);
+    case 6: return run_multi_n<6>(prec, trans, nrhs, m64, m32, x, y, s);
+    case 7: return run_multi_n<7>(prec, trans, nrhs, m64, m32, x, y, s);
+    case 8: return run_multi_n<8>(prec, trans, nrhs, m64, m32, x, y, s);
   }
   return hipErrorInvalidValue;
 }

@@ -698,6 +698,33 @@ int dg_apply_transpose(dg_ctx* c, int prec, const void* x, void* y, void* stream
   return apply_common(c, prec, 1, x, y, stream);
 }
 
+int dg_apply_multi(dg_ctx* c, int prec, int transpose, int nrhs, const void* X, void* Y, void* stream) {
+  if (!c) return fail(nullptr, DG_ERR_ARG, "ctx is NULL");
+  if (!X || !Y) return fail(c, DG_ERR_ARG, "X or Y is NULL");
+  if (nrhs < 1 || nrhs > 65535) return fail(c, DG_ERR_ARG, "nrhs must be in 1..65535");
+  if (transpose != 0 && transpose != 1) return fail(c, DG_ERR_ARG, "transpose must be 0 or 1");
+  if (prec != DG_F64 && prec != DG_F32 && prec != DG_BF16 && prec != DG_BF16_MFMA)
+    return fail(c, DG_ERR_UNSUPPORTED, "unknown precision");
+  if (prec == DG_BF16_MFMA && (c->trilinear || !mfma_apply_supported(c->n)))
+    return fail(c, DG_ERR_UNSUPPORTED, "DG_BF16_MFMA needs an affine mesh and degree <= 4");
+  const size_t ein = prec == DG_F64 ? 8 : (prec == DG_F32 ? 4 : 2);
+  const size_t eout = prec == DG_F64 ? 8 : 4;
+  if (!aligned(X, ein) || !aligned(Y, eout)) return fail(c, DG_ERR_ARG, "misaligned X or Y");
+  const char* xb = (const char*)X;
+  const char* yb = (const char*)Y;
+  const size_t tot = (size_t)nrhs * (size_t)c->ndof;
+  if (xb < yb + tot * eout && yb < xb + tot * ein) return fail(c, DG_ERR_ARG, "X and Y overlap");
+  hipStream_t s = (hipStream_t)stream;
+  if (c->trilinear) {  // the two-pass apply shares its face buffer: one vector after the other
+    for (int j = 0; j < nrhs; ++j)
+      HIP_TRY(c, apply_any(c, prec, transpose, 0, xb + (size_t)j * c->ndof * ein, (char*)Y + (size_t)j * c->ndof * eout,
+                           nullptr, 0, nullptr, s));
+    return DG_OK;
+  }
+  HIP_TRY(c, launch_apply_affine_multi(c->n, prec, transpose, nrhs, args64(c), args32(c), X, Y, s));
+  return DG_OK;
+}
+
 int dg_dA_dtheta(dg_ctx* c, const double* u, const double* v, double* g, void* stream) {
   if (!c) return fail(nullptr, DG_ERR_ARG, "ctx is NULL");
   if (!u || !v || !g) return fail(c, DG_ERR_ARG, "u, v or g is NULL");

@@ -44,7 +44,11 @@ hipError_t launch_apply_affine(int n, int prec, int trans, int dot, const MeshAr
 // partials only (one per brick, as launch_apply_affine); the caller finishes.
 bool mfma_apply_supported(int n);
 hipError_t launch_apply_affine_mfma(int n, int dot, const MeshArgs<float>& m, const uint16_t* x, float* y,
-                                    double* partials, const int* skip, hipStream_t s);
+                                    double* partials, const int* skip, hipStream_t s, int nrhs = 1);
+// Y = A X for nrhs vectors stored one after another (affine meshes, no fused
+// dot): the vectors are the second grid dimension of the apply kernels
+hipError_t launch_apply_affine_multi(int n, int prec, int trans, int nrhs, const MeshArgs<double>& m64,
+                                     const MeshArgs<float>& m32, const void* x, void* y, hipStream_t s);
 // element block-Jacobi (axis-parallel affine meshes): per element and axis the
 // fast-diagonalisation factors Q_d (n x n) and l_d (n), FP64 and FP32 copies;
 // z = P r with the block partials {<z, r>, <r, r>} (element_blocks(n, E) of them)

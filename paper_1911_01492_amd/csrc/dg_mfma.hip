@@ -218,6 +218,9 @@ __global__ __launch_bounds__(kBlock) void k_apply_affine_mfma(MeshArgs<float> m,
   __shared__ int sEl[XS], sOff[XS];
   __shared__ double red[kBlock / 64];
   if (skip != nullptr && *skip) return;
+  // vector blockIdx.y of a multi-vector apply (the vectors follow each other)
+  x += (size_t)blockIdx.y * (size_t)m.E * N3;
+  y += (size_t)blockIdx.y * (size_t)m.E * N3;
   const Tables<float>& T = *m.tab;
   const int tid = threadIdx.x, lane = tid & 63;
   const int tb = (int)xcd_remap(blockIdx.x, gridDim.x);
@@ -342,22 +345,22 @@ __global__ __launch_bounds__(kBlock) void k_apply_affine_mfma(MeshArgs<float> m,
 
 template <int N, bool DOT>
 static hipError_t run_mfma(const MeshArgs<float>& m, const uint16_t* x, float* y, double* partials, const int* skip,
-                           hipStream_t s) {
+                           hipStream_t s, int nrhs) {
   const int64_t nb = affine_tiles(N, m.nx, m.ny, m.nz);
-  hipLaunchKernelGGL((k_apply_affine_mfma<N, tile_x(N), tile_y(N), tile_z(N), DOT>), dim3((unsigned)nb), dim3(kBlock),
-                     0, s, m, x, y, partials, skip);
+  hipLaunchKernelGGL((k_apply_affine_mfma<N, tile_x(N), tile_y(N), tile_z(N), DOT>), dim3((unsigned)nb, (unsigned)nrhs),
+                     dim3(kBlock), 0, s, m, x, y, partials, skip);
   return hipGetLastError();
 }
 
 bool mfma_apply_supported(int n) { return n >= 2 && n <= 5; }
 
 hipError_t launch_apply_affine_mfma(int n, int dot, const MeshArgs<float>& m, const uint16_t* x, float* y,
-                                    double* partials, const int* skip, hipStream_t s) {
+                                    double* partials, const int* skip, hipStream_t s, int nrhs) {
   switch (n) {
-    case 2: return dot ? run_mfma<2, true>(m, x, y, partials, skip, s) : run_mfma<2, false>(m, x, y, partials, skip, s);
-    case 3: return dot ? run_mfma<3, true>(m, x, y, partials, skip, s) : run_mfma<3, false>(m, x, y, partials, skip, s);
-    case 4: return dot ? run_mfma<4, true>(m, x, y, partials, skip, s) : run_mfma<4, false>(m, x, y, partials, skip, s);
-    case 5: return dot ? run_mfma<5, true>(m, x, y, partials, skip, s) : run_mfma<5, false>(m, x, y, partials, skip, s);
+    case 2: return dot ? run_mfma<2, true>(m, x, y, partials, skip, s, 1) : run_mfma<2, false>(m, x, y, partials, skip, s, nrhs);
+    case 3: return dot ? run_mfma<3, true>(m, x, y, partials, skip, s, 1) : run_mfma<3, false>(m, x, y, partials, skip, s, nrhs);
+    case 4: return dot ? run_mfma<4, true>(m, x, y, partials, skip, s, 1) : run_mfma<4, false>(m, x, y, partials, skip, s, nrhs);
+    case 5: return dot ? run_mfma<5, true>(m, x, y, partials, skip, s, 1) : run_mfma<5, false>(m, x, y, partials, skip, s, nrhs);
   }
   return hipErrorInvalidValue;
 }

@@ -30,7 +30,7 @@ _IN_DTYPE = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16,
 _OUT_DTYPE = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.float32, "bf16_mfma": torch.float32}
 
 #: every function declared in include/dg.h
-ABI_FUNCTIONS = ["dg_query_workspace", "dg_setup", "dg_set_theta", "dg_set_reaction", "dg_apply", "dg_apply_transpose",
+ABI_FUNCTIONS = ["dg_query_workspace", "dg_setup", "dg_set_theta", "dg_set_reaction", "dg_apply", "dg_apply_transpose", "dg_apply_multi",
                  "dg_dA_dtheta", "dg_dA_dtheta_noalloc", "dg_diagonal", "dg_quadrature_points", "dg_load_vector", "dg_cg_solve",
                  "dg_num_dofs", "dg_num_elements", "dg_nodes_per_dir", "dg_destroy", "dg_last_error"]
 
@@ -84,6 +84,7 @@ def lib() -> ctypes.CDLL:
     L.dg_set_reaction.argtypes = [vp, vp, vp]
     L.dg_apply.argtypes = [vp, ctypes.c_int, vp, vp, vp]
     L.dg_apply_transpose.argtypes = [vp, ctypes.c_int, vp, vp, vp]
+    L.dg_apply_multi.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp, vp]
     L.dg_dA_dtheta.argtypes = [vp, vp, vp, vp, vp]
     L.dg_dA_dtheta_noalloc.argtypes = [vp, vp, vp, vp, vp]
     L.dg_diagonal.argtypes = [vp, vp, vp]
@@ -209,6 +210,20 @@ class DGOperator:
         fn = lib().dg_apply_transpose if transpose else lib().dg_apply
         self._check(fn(self._h, PREC[prec], _ptr(x), _ptr(y), _stream(stream, x, y, self.workspace)))
         return y
+
+    def apply_multi(self, X: torch.Tensor, prec: str = "f64", out: Optional[torch.Tensor] = None,
+                    transpose: bool = False, stream=None) -> torch.Tensor:
+        """Y = A X for nrhs vectors: X is a contiguous (nrhs, N_dof) tensor, one vector
+        per row; returns Y of the same shape (output dtype of `prec`)."""
+        if not isinstance(X, torch.Tensor) or not X.is_cuda or X.dtype != _IN_DTYPE[prec] or X.dim() != 2 \
+                or X.shape[1] != self.ndof or not X.is_contiguous():
+            raise ValueError(f"expected a contiguous CUDA tensor (nrhs, {self.ndof}) of dtype {_IN_DTYPE[prec]}")
+        Y = torch.empty(X.shape, dtype=_OUT_DTYPE[prec], device=X.device) if out is None else out
+        if Y.shape != X.shape or Y.dtype != _OUT_DTYPE[prec] or not Y.is_contiguous():
+            raise ValueError("out has the wrong shape or dtype")
+        self._check(lib().dg_apply_multi(self._h, PREC[prec], 1 if transpose else 0, X.shape[0], _ptr(X), _ptr(Y),
+                                         _stream(stream, X, Y, self.workspace)))
+        return Y
 
     def dA_dtheta(self, u: torch.Tensor, v: torch.Tensor, out: Optional[torch.Tensor] = None,
                   stream=None) -> torch.Tensor:
