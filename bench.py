@@ -39,7 +39,8 @@ FP32_PEAK_TFS = 157.3
 # pure FP64 PCG, then the FP64 defect correction with FP32 / BF16 inner solves,
 # restarted per correction or keeping the search direction
 CG_VARIANTS = (("f64", "restart"), ("f32", "restart"), ("bf16", "restart"), ("f32", "keep"), ("bf16", "keep"),
-               ("f64", "single_reduction"), ("f64", "block_jacobi"))
+               ("f64", "single_reduction"), ("f64", "block_jacobi"), ("f32", "keep_block_jacobi"),
+               ("bf16", "keep_block_jacobi"))
 
 
 def cg_kwargs(mode):
@@ -47,6 +48,8 @@ def cg_kwargs(mode):
         return {"variant": "single_reduction"}
     if mode == "block_jacobi":
         return {"precond": "block_jacobi"}
+    if mode.endswith("_block_jacobi"):
+        return {"dc_mode": mode[:-len("_block_jacobi")], "precond": "block_jacobi"}
     return {"dc_mode": mode}
 
 

@@ -73,8 +73,8 @@ enum dg_bc { DG_BC_DIRICHLET0 = 0, DG_BC_PERIODIC = 1 };
  * element blocks (Sec. 3.4's block preconditioners from the element blocks of
  * the DG matrix), inverted exactly by fast diagonalisation: on axis-parallel
  * box elements the block is a Kronecker sum of per-element 1D operators.
- * Affine meshes, FP64 PCG (prec_inner DG_F64, DG_CG_STANDARD) only;
- * DG_ERR_UNSUPPORTED otherwise. */
+ * Affine meshes and DG_CG_STANDARD only (DG_ERR_UNSUPPORTED otherwise); in the
+ * FP64 PCG and in the FP32-vector inner PCG of the defect correction. */
 enum dg_preconditioner { DG_PC_NONE = 0, DG_PC_JACOBI = 1, DG_PC_BLOCK_JACOBI = 2 };
 
 typedef struct {

@@ -44,7 +44,7 @@ struct dg_ctx {
   float *bjQ32, *bjL32;
   double *r64, *p64, *q64;
   double *z64, *s64, *w64;   // single-reduction CG
-  float *r32, *d32, *p32, *q32;
+  float *r32, *d32, *p32, *q32, *z32;
   uint16_t* p16;
   void* fb;              // trilinear meshes: lower-face line scalars between the two apply passes
   double* partials;
@@ -358,7 +358,7 @@ void tables_to_f32(const Tables<double>& a, Tables<float>& b) {
 // ------------------------------------------------------------------ workspace
 struct Layout {
   size_t tab64, tab32, K64, K32, G64, G32, R64, R32, vert64, vert32, dinv64, dinv32, bjQ64, bjL64, bjQ32, bjL32, r64,
-      p64, q64, r32, d32, p32, q32, p16, z64, s64, w64, fb, partials, st, flags, total;
+      p64, q64, r32, d32, p32, q32, z32, p16, z64, s64, w64, fb, partials, st, flags, total;
 };
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
@@ -413,6 +413,7 @@ Layout layout(const dg_mesh_desc* m) {
   L.d32 = take(nd * sizeof(float));
   L.p32 = take(nd * sizeof(float));
   L.q32 = take(nd * sizeof(float));
+  L.z32 = take(tri ? 0 : nd * sizeof(float));  // block-Jacobi z of the inner solves
   L.p16 = take(nd * sizeof(uint16_t));
   L.z64 = take(nd * sizeof(double));
   L.s64 = take(nd * sizeof(double));
@@ -601,6 +602,7 @@ int dg_setup(const dg_mesh_desc* mesh, dg_ctx** out, void* stream) {
   c->d32 = (float*)(w + L.d32);
   c->p32 = (float*)(w + L.p32);
   c->q32 = (float*)(w + L.q32);
+  c->z32 = c->trilinear ? nullptr : (float*)(w + L.z32);
   c->p16 = (uint16_t*)(w + L.p16);
   c->z64 = (double*)(w + L.z64);
   c->s64 = (double*)(w + L.s64);
@@ -936,13 +938,22 @@ int pcg_inner(dg_ctx* c, const dg_cg_opts* o, int prec, bool fresh, double inner
               int& iters, int& last_par, bool& broke, hipStream_t s) {
   const int64_t n = c->ndof;
   const float* dinv = o->precond == DG_PC_JACOBI ? c->dinv32 : nullptr;
+  const bool blk = o->precond == DG_PC_BLOCK_JACOBI;
   CgState* st = &c->st[1];
   TP* p = prec != DG_F32 ? (TP*)c->p16 : (TP*)c->p32;
   const int check = o->check_every > 0 ? o->check_every : 32;
+  const int64_t nbj = element_blocks(c->n, c->E);
   if (fresh) {
     par0 = 0;
-    HIP_TRY(c, (launch_cg_init_inner<float, TP, float>(n, c->r32, c->d32, p, dinv, inner_rtol, st, c->partials,
-                                                       s)));
+    if (blk) {  // z = P r with {<z, r>, <r, r>}, then p = z, d = 0
+      HIP_TRY(c, (launch_bj_apply<float, float>(c->n, c->E, c->bjQ32, c->bjL32, c->r32, c->z32, c->partials, nullptr,
+                                                s)));
+      HIP_TRY(c, launch_init_inner_finish(c->partials, nbj, st, inner_rtol, s));
+      HIP_TRY(c, launch_inner_start<TP>(n, c->z32, c->d32, p, st, s));
+    } else {
+      HIP_TRY(c, (launch_cg_init_inner<float, TP, float>(n, c->r32, c->d32, p, dinv, inner_rtol, st, c->partials,
+                                                         s)));
+    }
   }
   CgState hs;
   int rc = read_state(c, 1, hs, s);
@@ -950,7 +961,7 @@ int pcg_inner(dg_ctx* c, const dg_cg_opts* o, int prec, bool fresh, double inner
   // few block partials: the update kernels sum them themselves (no finish kernels)
   const int64_t nbA = c->trilinear ? element_blocks(c->n, c->E) : affine_tiles(c->n, c->desc.nx, c->desc.ny,
                                                                                c->desc.nz);
-  const bool fused = nbA <= 4096 && 2 * vec_blocks(n) <= 8192;
+  const bool fused = !blk && nbA <= 4096 && 2 * vec_blocks(n) <= 8192;
   double* partA = c->partials;
   double* partB = c->partials + nbA;
   int it = 0;
@@ -958,6 +969,15 @@ int pcg_inner(dg_ctx* c, const dg_cg_opts* o, int prec, bool fresh, double inner
     const int chunk = std::min(check, maxit - it);
     for (int j = 0; j < chunk; ++j, ++it) {
       const int par = (par0 + it) & 1;
+      if (blk) {  // as pcg64_block, on the FP32 inner vectors
+        HIP_TRY(c, apply_any(c, prec, o->transpose, 1, p, c->q32, st, par, &st->done, s));
+        HIP_TRY(c, (launch_cg_update<float, float>(n, c->r32, c->q32, nullptr, par, st, c->partials, s)));
+        HIP_TRY(c, (launch_bj_apply<float, float>(c->n, c->E, c->bjQ32, c->bjL32, c->r32, c->z32, c->partials,
+                                                  &st->done, s)));
+        HIP_TRY(c, launch_bj_finish(c->partials, nbj, st, par ^ 1, s));
+        HIP_TRY(c, (launch_cg_pupdate<float, float, TP, float>(n, c->d32, c->z32, p, nullptr, par, st, 0, s)));
+        continue;
+      }
       if (fused) {
         HIP_TRY(c, apply_any(c, prec, o->transpose, 1, p, c->q32, nullptr, 0, &st->done, s, partA));
         HIP_TRY(c, (launch_cg_update_fused<float, float>(n, c->r32, c->q32, dinv, par, st, partA, nbA, partB, s)));
@@ -1023,6 +1043,11 @@ int dc_solve(dg_ctx* c, const dg_cg_opts* o, int prec, const double* b, double* 
       // replace the residual, keep the direction
       HIP_TRY(c, launch_dc_replace(c->ndof, b, c->q64, dinv, c->r32, &c->st[1], last_par, o->rtol, tin,
                                    c->partials, s));
+      if (o->precond == DG_PC_BLOCK_JACOBI) {  // rho of the kept direction from z = P r
+        HIP_TRY(c, (launch_bj_apply<float, float>(c->n, c->E, c->bjQ32, c->bjL32, c->r32, c->z32, c->partials,
+                                                  &c->st[1].done, s)));
+        HIP_TRY(c, launch_bj_finish(c->partials, element_blocks(c->n, c->E), &c->st[1], last_par ^ 1, s));
+      }
       rc = read_state(c, 1, hs, s);
       if (rc != DG_OK) return rc;
       rel = hs.true_bb > 0 ? std::sqrt(hs.true_rr / hs.true_bb) : std::sqrt(hs.true_rr);
@@ -1031,8 +1056,9 @@ int dc_solve(dg_ctx* c, const dg_cg_opts* o, int prec, const double* b, double* 
         continue;
       }
       if (rel <= o->rtol) break;
-      HIP_TRY(c, (launch_cg_pupdate<float, float, TP, float>(c->ndof, c->d32, c->r32, p, dinv, last_par,
-                                                             &c->st[1], 1, s)));
+      HIP_TRY(c, (launch_cg_pupdate<float, float, TP, float>(
+                     c->ndof, c->d32, o->precond == DG_PC_BLOCK_JACOBI ? c->z32 : c->r32, p, dinv, last_par,
+                     &c->st[1], 1, s)));
       fresh = false;
     } else {
       HIP_TRY(c, launch_dc_residual(c->ndof, b, c->q64, c->r32, &c->st[0], c->partials, s));
@@ -1060,9 +1086,8 @@ int dg_cg_solve(dg_ctx* c, const dg_cg_opts* o, const double* b, double* x, dg_c
     return fail(c, DG_ERR_UNSUPPORTED, "DG_BF16_MFMA needs an affine mesh and degree <= 4");
   if (o->precond != DG_PC_NONE && o->precond != DG_PC_JACOBI && o->precond != DG_PC_BLOCK_JACOBI)
     return fail(c, DG_ERR_ARG, "unknown preconditioner");
-  if (o->precond == DG_PC_BLOCK_JACOBI &&
-      (c->trilinear || o->prec_inner != DG_F64 || o->cg_variant != DG_CG_STANDARD))
-    return fail(c, DG_ERR_UNSUPPORTED, "block-Jacobi is built for FP64 PCG (standard variant) on affine meshes");
+  if (o->precond == DG_PC_BLOCK_JACOBI && (c->trilinear || o->cg_variant != DG_CG_STANDARD))
+    return fail(c, DG_ERR_UNSUPPORTED, "block-Jacobi is built for the standard CG variant on affine meshes");
   if (o->dc_mode != DG_DC_RESTART && o->dc_mode != DG_DC_KEEP) return fail(c, DG_ERR_ARG, "unknown dc_mode");
   if (o->cg_variant != DG_CG_STANDARD && o->cg_variant != DG_CG_SINGLE_REDUCTION)
     return fail(c, DG_ERR_ARG, "unknown cg_variant");

@@ -59,6 +59,12 @@ hipError_t launch_bj_apply(int n, int64_t E, const TQ* Q, const TQ* lam, const T
                            const int* skip, hipStream_t s);
 // st->rho[idx] = <z, r> from the block-Jacobi partials (nothing once the solve stopped)
 hipError_t launch_bj_finish(const double* partials, int64_t nblocks, CgState* st, int idx, hipStream_t s);
+// inner solve started from a stored preconditioned residual z: p = z, d = 0
+// (skipped when st->done), and the finish that turns the block preconditioner's
+// {<z, r>, <r, r>} partials into the start state of the inner solve
+template <typename TP>
+hipError_t launch_inner_start(int64_t n, const float* z, float* d, TP* p, const CgState* st, hipStream_t s);
+hipError_t launch_init_inner_finish(const double* partials, int64_t nb, CgState* st, double rtol, hipStream_t s);
 hipError_t launch_face_coef(const MeshArgs<double>& m, double* G64, float* G32, hipStream_t s);
 hipError_t launch_finish_dot(const double* partials, int64_t nblocks, CgState* st, int par, hipStream_t s);
 // diagonal kernels: run != nullptr && *run == 0 makes them return at once

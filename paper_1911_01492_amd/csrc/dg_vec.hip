@@ -683,6 +683,30 @@ hipError_t launch_resid_norm(int64_t n, const double* b, const double* q, CgStat
   return finish<2, FIN_TRUE>(partials, nb, st, 0, 0.0, s);
 }
 
+// inner solve with a stored preconditioned residual: p = z, d = 0
+template <typename TP>
+__global__ __launch_bounds__(kBlock) void k_inner_start(int64_t n, const float* __restrict__ z, float* __restrict__ d,
+                                                        TP* __restrict__ p, const CgState* st) {
+  if (st->done) return;
+  DG_VEC_LOOP(i, k, n) {
+    p_store<TP>(p, i, (double)z[i]);
+    d[i] = 0.0f;
+  }
+}
+template <typename TP>
+hipError_t launch_inner_start(int64_t n, const float* z, float* d, TP* p, const CgState* st, hipStream_t s) {
+  hipLaunchKernelGGL((k_inner_start<TP>), dim3((unsigned)vec_blocks(n)), dim3(kBlock), 0, s, n, z, d, p, st);
+  return hipGetLastError();
+}
+template hipError_t launch_inner_start<float>(int64_t, const float*, float*, float*, const CgState*, hipStream_t);
+template hipError_t launch_inner_start<uint16_t>(int64_t, const float*, float*, uint16_t*, const CgState*,
+                                                 hipStream_t);
+// {<z, r>, <r, r>} partials of the block preconditioner as the start of an
+// inner solve: rho[0], rr = rr0 = bb, tol2 = rtol^2 rr (FIN_INIT_INNER)
+hipError_t launch_init_inner_finish(const double* partials, int64_t nb, CgState* st, double rtol, hipStream_t s) {
+  return finish<2, FIN_INIT_INNER>(partials, nb, st, 0, rtol, s);
+}
+
 // ---------------------------------------------------------------- elementwise helpers
 // K = exp(theta).  changed != nullptr: set *changed = 1 when any coefficient
 // differs bitwise from the one it replaces (every writer stores the same value).
