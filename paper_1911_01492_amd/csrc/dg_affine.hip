@@ -505,15 +505,20 @@ __global__ __launch_bounds__(256) void k_bj_setup(MeshArgs<double> m, double* __
 // partials {<z, r>, <r, r>}.  n^2 threads per element, one line each per
 // phase: Q_x^T, Q_y^T, Q_z^T, the scaling by 1 / (l_x + l_y + l_z), Q_z,
 // Q_y, Q_x.  TV: vector type (double / float), TQ: type of the stored Q, l.
-template <int N, typename TV, typename TQ>
+// UPD: first the CG residual update r -= lambda q with lambda = rho[par] / pq
+// from the solver state (r is rewritten), so that the update and the
+// preconditioner take one pass over the residual.
+template <int N, typename TV, typename TQ, bool UPD>
 __global__ __launch_bounds__(kBlock) void k_bj_apply(int64_t E, const TQ* __restrict__ Q, const TQ* __restrict__ lam,
-                                                     const TV* __restrict__ r, TV* __restrict__ z, double* partials,
-                                                     const int* skip) {
+                                                     TV* __restrict__ r, TV* __restrict__ z, double* partials,
+                                                     const int* skip, const TV* __restrict__ q, const CgState* st,
+                                                     int par) {
   constexpr int NN = N * N, EPB = elems_per_block(N), PE = Lay<N, TV>::PE;
   __shared__ TV sT[EPB * PE];
   __shared__ TQ sQ[EPB][3 * NN], sL[EPB][3 * N];
   __shared__ double red[kBlock / 64];
   if (skip != nullptr && *skip) return;
+  const double lamb = UPD ? st->rho[par] / st->pq : 0.0;
   const int tid = threadIdx.x, el = tid / NN, t = tid % NN, t1 = t % N, t2 = t / N;
   const int64_t e = (int64_t)blockIdx.x * EPB + el;
   const bool act = el < EPB && e < E;
@@ -529,8 +534,19 @@ __global__ __launch_bounds__(kBlock) void k_bj_apply(int64_t E, const TQ* __rest
   const TQ* qz = sQ[le] + 2 * NN;
   TV rl[N], a[N], b[N];
   // x-lines: w = Q_x^T r
-  if (act) glb_get<N, 0, TV, TV>(r, e, t1, t2, rl);
-  else {
+  if (act) {
+    glb_get<N, 0, TV, TV>(r, e, t1, t2, rl);
+    if (UPD) {
+      TV ql[N];
+      glb_get<N, 0, TV, TV>(q, e, t1, t2, ql);
+      TV* pr = r + e * NN * N;
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        rl[i] = (TV)((double)rl[i] - lamb * (double)ql[i]);
+        pr[lidx<N, 0>(t1, t2, i)] = rl[i];
+      }
+    }
+  } else {
 #pragma unroll
     for (int i = 0; i < N; ++i) rl[i] = TV(0);
   }
@@ -973,29 +989,34 @@ hipError_t launch_bj_setup(int n, const MeshArgs<double>& m, double* Q, double* 
   return hipErrorInvalidValue;
 }
 template <int N, typename TV, typename TQ>
-static hipError_t run_bj_apply(int64_t E, const TQ* Q, const TQ* lam, const TV* r, TV* z, double* partials,
-                               const int* skip, hipStream_t s) {
-  hipLaunchKernelGGL((k_bj_apply<N, TV, TQ>), dim3((unsigned)element_blocks(N, E)), dim3(kBlock), 0, s, E, Q, lam, r, z,
-                     partials, skip);
+static hipError_t run_bj_apply(int64_t E, const TQ* Q, const TQ* lam, TV* r, TV* z, double* partials,
+                               const int* skip, const TV* q, const CgState* st, int par, hipStream_t s) {
+  if (q != nullptr)
+    hipLaunchKernelGGL((k_bj_apply<N, TV, TQ, true>), dim3((unsigned)element_blocks(N, E)), dim3(kBlock), 0, s, E, Q,
+                       lam, r, z, partials, skip, q, st, par);
+  else
+    hipLaunchKernelGGL((k_bj_apply<N, TV, TQ, false>), dim3((unsigned)element_blocks(N, E)), dim3(kBlock), 0, s, E, Q,
+                       lam, r, z, partials, skip, q, st, par);
   return hipGetLastError();
 }
 template <typename TV, typename TQ>
-hipError_t launch_bj_apply(int n, int64_t E, const TQ* Q, const TQ* lam, const TV* r, TV* z, double* partials,
-                           const int* skip, hipStream_t s) {
+hipError_t launch_bj_apply(int n, int64_t E, const TQ* Q, const TQ* lam, TV* r, TV* z, double* partials,
+                           const int* skip, hipStream_t s, const TV* q, const CgState* st, int par) {
   switch (n) {
-    case 2: return run_bj_apply<2, TV, TQ>(E, Q, lam, r, z, partials, skip, s);
-    case 3: return run_bj_apply<3, TV, TQ>(E, Q, lam, r, z, partials, skip, s);
-    case 4: return run_bj_apply<4, TV, TQ>(E, Q, lam, r, z, partials, skip, s);
-    case 5: return run_bj_apply<5, TV, TQ>(E, Q, lam, r, z, partials, skip, s);
-    case 6: return run_bj_apply<6, TV, TQ>(E, Q, lam, r, z, partials, skip, s);
-    case 7: return run_bj_apply<7, TV, TQ>(E, Q, lam, r, z, partials, skip, s);
-    case 8: return run_bj_apply<8, TV, TQ>(E, Q, lam, r, z, partials, skip, s);
+    case 2: return run_bj_apply<2, TV, TQ>(E, Q, lam, r, z, partials, skip, q, st, par, s);
+    case 3: return run_bj_apply<3, TV, TQ>(E, Q, lam, r, z, partials, skip, q, st, par, s);
+    case 4: return run_bj_apply<4, TV, TQ>(E, Q, lam, r, z, partials, skip, q, st, par, s);
+    case 5: return run_bj_apply<5, TV, TQ>(E, Q, lam, r, z, partials, skip, q, st, par, s);
+    case 6: return run_bj_apply<6, TV, TQ>(E, Q, lam, r, z, partials, skip, q, st, par, s);
+    case 7: return run_bj_apply<7, TV, TQ>(E, Q, lam, r, z, partials, skip, q, st, par, s);
+    case 8: return run_bj_apply<8, TV, TQ>(E, Q, lam, r, z, partials, skip, q, st, par, s);
   }
   return hipErrorInvalidValue;
 }
-template hipError_t launch_bj_apply<double, double>(int, int64_t, const double*, const double*, const double*, double*,
-                                                    double*, const int*, hipStream_t);
-template hipError_t launch_bj_apply<float, float>(int, int64_t, const float*, const float*, const float*, float*,
-                                                  double*, const int*, hipStream_t);
+template hipError_t launch_bj_apply<double, double>(int, int64_t, const double*, const double*, double*, double*,
+                                                    double*, const int*, hipStream_t, const double*, const CgState*,
+                                                    int);
+template hipError_t launch_bj_apply<float, float>(int, int64_t, const float*, const float*, float*, float*, double*,
+                                                  const int*, hipStream_t, const float*, const CgState*, int);
 
 }  // namespace dg

@@ -863,10 +863,10 @@ int pcg64_block(dg_ctx* c, const dg_cg_opts* o, const double* b, double* x, int 
     for (int j = 0; j < chunk; ++j, ++it) {
       const int par = it & 1;
       HIP_TRY(c, apply_any(c, DG_F64, o->transpose, 1, c->p64, c->q64, st, par, &st->done, s));
-      HIP_TRY(c, (launch_cg_update<double, double>(n, c->r64, c->q64, nullptr, par, st, c->partials, s)));
+      // r -= lambda q and z = P r in one element pass, then FIN_UPDATE on {<z, r>, <r, r>}
       HIP_TRY(c, (launch_bj_apply<double, double>(c->n, c->E, c->bjQ64, c->bjL64, c->r64, c->z64, c->partials,
-                                                  &st->done, s)));
-      HIP_TRY(c, launch_bj_finish(c->partials, nbj, st, par ^ 1, s));
+                                                  &st->done, s, c->q64, st, par)));
+      HIP_TRY(c, launch_update_finish(c->partials, nbj, st, par, s));
       HIP_TRY(c, (launch_cg_pupdate<double, double, double, double>(n, x, c->z64, c->p64, nullptr, par, st, 0, s)));
     }
     rc = read_state(c, 0, hs, s);
@@ -971,10 +971,9 @@ int pcg_inner(dg_ctx* c, const dg_cg_opts* o, int prec, bool fresh, double inner
       const int par = (par0 + it) & 1;
       if (blk) {  // as pcg64_block, on the FP32 inner vectors
         HIP_TRY(c, apply_any(c, prec, o->transpose, 1, p, c->q32, st, par, &st->done, s));
-        HIP_TRY(c, (launch_cg_update<float, float>(n, c->r32, c->q32, nullptr, par, st, c->partials, s)));
         HIP_TRY(c, (launch_bj_apply<float, float>(c->n, c->E, c->bjQ32, c->bjL32, c->r32, c->z32, c->partials,
-                                                  &st->done, s)));
-        HIP_TRY(c, launch_bj_finish(c->partials, nbj, st, par ^ 1, s));
+                                                  &st->done, s, c->q32, st, par)));
+        HIP_TRY(c, launch_update_finish(c->partials, nbj, st, par, s));
         HIP_TRY(c, (launch_cg_pupdate<float, float, TP, float>(n, c->d32, c->z32, p, nullptr, par, st, 0, s)));
         continue;
       }

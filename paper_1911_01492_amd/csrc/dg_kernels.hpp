@@ -51,12 +51,16 @@ hipError_t launch_apply_affine_multi(int n, int prec, int trans, int nrhs, const
                                      const MeshArgs<float>& m32, const void* x, void* y, hipStream_t s);
 // element block-Jacobi (axis-parallel affine meshes): per element and axis the
 // fast-diagonalisation factors Q_d (n x n) and l_d (n), FP64 and FP32 copies;
-// z = P r with the block partials {<z, r>, <r, r>} (element_blocks(n, E) of them)
+// z = P r with the block partials {<z, r>, <r, r>} (element_blocks(n, E) of them);
+// q != nullptr: first r -= (rho[par] / pq) q from st (r rewritten), the CG update
 hipError_t launch_bj_setup(int n, const MeshArgs<double>& m, double* Q, double* lam, float* Q32, float* lam32,
                            hipStream_t s);
 template <typename TV, typename TQ>
-hipError_t launch_bj_apply(int n, int64_t E, const TQ* Q, const TQ* lam, const TV* r, TV* z, double* partials,
-                           const int* skip, hipStream_t s);
+hipError_t launch_bj_apply(int n, int64_t E, const TQ* Q, const TQ* lam, TV* r, TV* z, double* partials,
+                           const int* skip, hipStream_t s, const TV* q = nullptr, const CgState* st = nullptr,
+                           int par = 0);
+// FIN_UPDATE on {<z, r>, <r, r>} partials (rho[par^1], rr, iteration count, convergence)
+hipError_t launch_update_finish(const double* partials, int64_t nb, CgState* st, int par, hipStream_t s);
 // st->rho[idx] = <z, r> from the block-Jacobi partials (nothing once the solve stopped)
 hipError_t launch_bj_finish(const double* partials, int64_t nblocks, CgState* st, int idx, hipStream_t s);
 // inner solve started from a stored preconditioned residual z: p = z, d = 0

@@ -521,6 +521,9 @@ static hipError_t finish(const double* partials, int64_t nb, CgState* st, int pa
 hipError_t launch_finish_dot(const double* partials, int64_t nblocks, CgState* st, int par, hipStream_t s) {
   return finish<1, FIN_DOT>(partials, nblocks, st, par, 0.0, s);
 }
+hipError_t launch_update_finish(const double* partials, int64_t nb, CgState* st, int par, hipStream_t s) {
+  return finish<2, FIN_UPDATE>(partials, nb, st, par, 0.0, s);
+}
 hipError_t launch_bj_finish(const double* partials, int64_t nblocks, CgState* st, int idx, hipStream_t s) {
   return finish<2, FIN_BJ>(partials, nblocks, st, idx, 0.0, s);
 }
