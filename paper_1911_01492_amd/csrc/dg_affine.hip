@@ -102,7 +102,7 @@ __device__ __forceinline__ void line_op(const Tables<TC>& T, const TC (&u)[N], c
 // Neighbour face scalars along axis D for both sides.  In-brick neighbours
 // publish their own face scalars in F (written by their threads in this
 // phase), out-of-brick neighbours come from HBM, Dirichlet sides are absent.
-template <int N, int D, int BX, int BY, int BZ, typename TC, typename TIN>
+template <int N, int D, int BX, int BY, int BZ, typename TC, typename TIN, bool OFF32 = false>
 struct AxisNeighbours {
   bool inL, inH, glL, glH, hasL, hasH;
   int elL, elH;
@@ -131,8 +131,8 @@ struct AxisNeighbours {
   }
   // issue the HBM loads (before the own work of the phase, to hide latency)
   __device__ __forceinline__ void fetch(const TIN* __restrict__ x, int t1, int t2) {
-    if (glL) glb_get<N, D, TC, TIN>(x, eL, t1, t2, gL);
-    if (glH) glb_get<N, D, TC, TIN>(x, eH, t1, t2, gH);
+    if (glL) glb_get<N, D, TC, TIN, OFF32>(x, eL, t1, t2, gL);
+    if (glH) glb_get<N, D, TC, TIN, OFF32>(x, eH, t1, t2, gH);
   }
   // the HBM neighbour lines reduced to their face scalars (frees the lines)
   TC uL, dL, uH, dH;
@@ -189,18 +189,18 @@ __device__ __forceinline__ void lds_sync() {
 // of the block calls it.  act == false: a thread without an element of its
 // own (it computes on a clamped element, sees no neighbours, and its result
 // is discarded).
-template <int N, int D, int BX, int BY, int BZ, int FS, typename TC, typename TIN, bool TRANS>
+template <int N, int D, int BX, int BY, int BZ, int FS, typename TC, typename TIN, bool TRANS, bool OFF32>
 __device__ __forceinline__ void face_phase(const MeshArgs<TC>& m, const Tables<TC>& T, const TIN* __restrict__ x,
                                            bool act, int64_t e, const int (&c)[3], const int (&o)[3],
                                            const int (&Nd)[3], int t, int t1, int t2, TC* F, TC* Fe, TC K, TC GL,
                                            TC GH, TC cr, TC (&b)[N], TC* own = nullptr) {
   constexpr int NN = N * N;
-  AxisNeighbours<N, D, BX, BY, BZ, TC, TIN> nb;
+  AxisNeighbours<N, D, BX, BY, BZ, TC, TIN, OFF32> nb;
   TC u[N], g0, g1;
   {
     nb.locate(m.nx, m.ny, c, o, Nd, m.periodic, act);
     nb.fetch(x, t1, t2);
-    glb_get<N, D, TC, TIN>(x, e, t1, t2, u);
+    glb_get<N, D, TC, TIN, OFF32>(x, e, t1, t2, u);
     nb.reduce(T);
     g0 = dot_end<N, TC, 0>(T, u);
     g1 = dot_end<N, TC, 1>(T, u);
@@ -244,7 +244,7 @@ __device__ __forceinline__ void face_phase(const MeshArgs<TC>& m, const Tables<T
 //   Z : b_z -> S2, r = M_z S1       (registers)
 //   X3, Y3: S2 <- M_y M_x S2
 //   Z2: y = r + S2
-template <int N, typename TIN, typename TOUT, typename TC, bool TRANS, bool DOT>
+template <int N, typename TIN, typename TOUT, typename TC, bool TRANS, bool DOT, bool OFF32>
 __global__ __launch_bounds__(apply_block(N)) void k_apply_affine(MeshArgs<TC> m, const TIN* __restrict__ x,
                                                          TOUT* __restrict__ y, double* partials,
                                                          const int* skip) {
@@ -294,15 +294,15 @@ __global__ __launch_bounds__(apply_block(N)) void k_apply_affine(MeshArgs<TC> m,
   TC K, G[6], cr = TC(0);
   K = m.K[e];
 #pragma unroll
-  for (int f = 0; f < 6; ++f) G[f] = m.G[6 * e + f];
+  for (int f = 0; f < 6; ++f) G[f] = OFF32 ? m.G[(uint32_t)(6 * e + f)] : m.G[6 * e + f];
   if (m.R) cr = m.R[e] * m.vol;
   TC b[N], v[N], w[N];
   // ---------------- X: b_x -> S1
-  face_phase<N, 0, BX, BY, BZ, FS, TC, TIN, TRANS>(m, T, x, act, e, c, o, Nd, t, t1, t2, F, Fe, K, G[0], G[1], TC(0), b);
+  face_phase<N, 0, BX, BY, BZ, FS, TC, TIN, TRANS, OFF32>(m, T, x, act, e, c, o, Nd, t, t1, t2, F, Fe, K, G[0], G[1], TC(0), b);
   lds_put<N, 0>(S1, t1, t2, b);
   lds_sync<XROW>();  // F (read by the x-neighbours) is rewritten by the next phase
   // ---------------- Y: b_y -> S2, M_y b_x -> S1
-  face_phase<N, 1, BX, BY, BZ, FS, TC, TIN, TRANS>(m, T, x, act, e, c, o, Nd, t, t1, t2, F, Fe, K, G[2], G[3], TC(0), b);
+  face_phase<N, 1, BX, BY, BZ, FS, TC, TIN, TRANS, OFF32>(m, T, x, act, e, c, o, Nd, t, t1, t2, F, Fe, K, G[2], G[3], TC(0), b);
   {
     lds_get<N, 1>(S1, t1, t2, v);
     mass_line<N, TC, TRANS>(T, v, w);
@@ -325,7 +325,7 @@ __global__ __launch_bounds__(apply_block(N)) void k_apply_affine(MeshArgs<TC> m,
   lds_sync<ELEM>();
   // ---------------- Z: b_z -> S2, r = M_z S1
   TC r[N], xz[N];  // xz: the thread's z-line of x, for the fused <x, y>
-  face_phase<N, 2, BX, BY, BZ, FS, TC, TIN, TRANS>(m, T, x, act, e, c, o, Nd, t, t1, t2, F, Fe, K, G[4], G[5], cr, b,
+  face_phase<N, 2, BX, BY, BZ, FS, TC, TIN, TRANS, OFF32>(m, T, x, act, e, c, o, Nd, t, t1, t2, F, Fe, K, G[4], G[5], cr, b,
                                                DOT ? xz : nullptr);
   {
     lds_get<N, 2>(S1, t1, t2, v);
@@ -353,11 +353,14 @@ __global__ __launch_bounds__(apply_block(N)) void k_apply_affine(MeshArgs<TC> m,
   if (act) {
     // y is written once and not read back here: nontemporal stores keep it
     // from displacing in L2 the x lines that neighbouring bricks still read
+    const uint32_t yb = ((uint32_t)e * (uint32_t)N3 + (uint32_t)lidx<N, 2>(t1, t2, 0)) * (uint32_t)sizeof(TOUT);
     TOUT* py = y + e * N3;
 #pragma unroll
     for (int i = 0; i < N; ++i) {
       const TOUT yv = (TOUT)(r[i] + v[i]);
-      __builtin_nontemporal_store(yv, &py[lidx<N, 2>(t1, t2, i)]);
+      TOUT* dst = OFF32 ? (TOUT*)((char*)y + (yb + (uint32_t)(lidx<N, 2>(0, 0, i) * sizeof(TOUT))))
+                        : &py[lidx<N, 2>(t1, t2, i)];
+      __builtin_nontemporal_store(yv, dst);
       if (DOT) part += (double)xz[i] * (double)yv;
     }
   }
@@ -844,9 +847,17 @@ template <int N, typename TIN, typename TOUT, typename TC, bool TRANS, bool DOT>
 static hipError_t run_apply(const MeshArgs<TC>& m, const void* x, void* y, double* partials, CgState* st,
                             int par, const int* skip, hipStream_t s, int nrhs = 1) {
   const int64_t nb = affine_tiles(N, m.nx, m.ny, m.nz);
+  // 32-bit byte offsets when every vector and the face coefficients stay below 4 GiB
+  const double nd = (double)m.E * N * N * N;
+  const bool off32 = nd * (double)(sizeof(TIN) > sizeof(TOUT) ? sizeof(TIN) : sizeof(TOUT)) < 4294967296.0 &&
+                     6.0 * (double)m.E * sizeof(TC) < 4294967296.0;
   hipError_t e;
-  hipLaunchKernelGGL((k_apply_affine<N, TIN, TOUT, TC, TRANS, DOT>), dim3((unsigned)nb, (unsigned)nrhs),
-                     dim3(apply_block(N)), 0, s, m, (const TIN*)x, (TOUT*)y, partials, skip);
+  if (off32)
+    hipLaunchKernelGGL((k_apply_affine<N, TIN, TOUT, TC, TRANS, DOT, true>), dim3((unsigned)nb, (unsigned)nrhs),
+                       dim3(apply_block(N)), 0, s, m, (const TIN*)x, (TOUT*)y, partials, skip);
+  else
+    hipLaunchKernelGGL((k_apply_affine<N, TIN, TOUT, TC, TRANS, DOT, false>), dim3((unsigned)nb, (unsigned)nrhs),
+                       dim3(apply_block(N)), 0, s, m, (const TIN*)x, (TOUT*)y, partials, skip);
   e = hipGetLastError();
   if (e != hipSuccess || !DOT || st == nullptr) return e;  // st == nullptr: partials only
   return launch_finish_dot(partials, nb, st, par, s);
