@@ -176,7 +176,14 @@ __device__ void face_term(const MeshArgs<TC>& m, const Tables<TC>& T, const TIN*
       xin[ax] = xi[ax];
       xin[bx] = xi[bx];
       TC Jn[3][3], An[3][3];
-      trilinear_jacobian(Xn, xin, Jn);
+      if (AFF) {  // the neighbour is a parallelepiped too: J is its three edge vectors
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+          for (int cc = 0; cc < 3; ++cc) Jn[r][cc] = Xn[1 << cc][r] - Xn[0][r];
+      } else {
+        trilinear_jacobian(Xn, xin, Jn);
+      }
       adj3(Jn, An);
       const TC idetn = TC(1) / det3(Jn);
       TC grn[3];
