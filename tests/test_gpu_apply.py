@@ -193,6 +193,29 @@ def test_large_mesh_byte_offsets():
     torch.cuda.empty_cache()
 
 
+def test_vector_beyond_4gib():
+    """206^3 Q3 (559M DOF, 4.5 GB per FP64 vector): above 4 GiB the apply forms
+    64-bit addresses (below it, 32-bit byte offsets); sampled element rows
+    against the oracle, including the last elements of the vector."""
+    N, k = 206, 3
+    banner("apply 206^3 Q3 (vector above 4 GiB)")
+    theta = I.theta(N ** 3)
+    m = O.Mesh(N, N, N, k, theta=theta)
+    op = DGOperator(N, N, N, k, "dirichlet", theta=dev(theta))
+    assert op.ndof * 8 > 2 ** 32
+    el = np.unique(np.r_[0, N ** 3 // 2, N ** 3 - N * N - 1, N ** 3 - 2, N ** 3 - 1,
+                         np.random.default_rng(12).choice(N ** 3, 5, replace=False)]).astype(np.int64)
+    x = I.uniform_vector(m.ndof)
+    X = dev(x)
+    y = op.apply(X)
+    got = host(y.view(-1, m.n3)[torch.as_tensor(el, device="cuda")])
+    err = rel_l2(got, O.apply_rows(m, x, el))
+    print(f"fp64 apply 206^3 Q3: rel err {err:.3e}")
+    assert err <= 1e-12
+    del X, y, op, x
+    torch.cuda.empty_cache()
+
+
 def test_low_precision_errors():
     """FP32 and BF16 (FP32 accumulation) applies against the FP64 oracle.
     FP32: relative error a modest multiple of 2^-24 times the operator's
