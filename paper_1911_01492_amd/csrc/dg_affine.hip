@@ -186,8 +186,8 @@ __device__ __forceinline__ void lds_sync() {
 // One face-aware direction of the affine apply: b = L_D u on this thread's
 // line along axis D (own line from HBM, neighbour face scalars from the
 // brick's exchange area F or from HBM).  Contains one barrier; every thread
-// of the block calls it.  act == false: a thread without an element of its
-// own (it computes on a clamped element, sees no neighbours, and its result
+// of the block calls it.  act == false: the lane's element overhangs the
+// mesh (it computes on a clamped element, sees no neighbours, and its result
 // is discarded).
 template <int N, int D, int BX, int BY, int BZ, int FS, typename TC, typename TIN, bool TRANS, bool OFF32>
 __device__ __forceinline__ void face_phase(const MeshArgs<TC>& m, const Tables<TC>& T, const TIN* __restrict__ x,
@@ -245,7 +245,7 @@ __device__ __forceinline__ void face_phase(const MeshArgs<TC>& m, const Tables<T
 //   X3, Y3: S2 <- M_y M_x S2
 //   Z2: y = r + S2
 template <int N, typename TIN, typename TOUT, typename TC, bool TRANS, bool DOT, bool OFF32>
-__global__ __launch_bounds__(apply_block(N)) void k_apply_affine(MeshArgs<TC> m, const TIN* __restrict__ x,
+__global__ __launch_bounds__(apply_block(N), (N == 5 && sizeof(TC) == 8) ? 8 : 1) void k_apply_affine(MeshArgs<TC> m, const TIN* __restrict__ x,
                                                          TOUT* __restrict__ y, double* partials,
                                                          const int* skip) {
   constexpr int NN = N * N, N3 = NN * N;
@@ -259,8 +259,13 @@ __global__ __launch_bounds__(apply_block(N)) void k_apply_affine(MeshArgs<TC> m,
   // of the brick (XROW, which implies ELEM): those exchanges need only
   // wavefront-level synchronisation
   constexpr bool ELEM = 64 % NN == 0, XROW = 64 % (BX * NN) == 0;
-  // a spare element slot takes the writes of padding threads (if the block has any)
-  constexpr int SLOTS = TE * NN < BLOCK ? TE + 1 : TE;
+  // padding threads (if the block has any) repeat the work of the brick's last
+  // element lane for lane: they write the same values to the same LDS words in
+  // the same instructions as their twins, which share their wavefront (the
+  // brick's last element and the padding lie in the block's last wavefront),
+  // so no slot of their own is needed
+  constexpr int SLOTS = TE;
+  static_assert(TE * NN == BLOCK || BLOCK - (TE - 1) * NN <= 64, "padding lanes and their twins share a wavefront");
   __shared__ TC sS1[SLOTS * PE], sS2[SLOTS * PE];
   __shared__ TC sFx[F_IN_S2 ? 1 : SLOTS * 4 * NN];
   __shared__ double red[BLOCK / 64];
@@ -275,15 +280,18 @@ __global__ __launch_bounds__(apply_block(N)) void k_apply_affine(MeshArgs<TC> m,
   int o[3];
   brick_origin<BX, BY, BZ>(tb, m.nx, m.ny, m.nz, o);
   const int Nd[3] = {m.nx, m.ny, m.nz};
-  const int tid = threadIdx.x, el = tid / NN, t = tid - el * NN, t1 = t % N, t2 = t / N;
+  const int tid = threadIdx.x, el0 = tid / NN, t = tid - el0 * NN, t1 = t % N, t2 = t / N;
+  const int el = min(el0, TE - 1);
   const int lx = el % BX, ly = (el / BX) % BY, lz = el / (BX * BY);
   const int cu[3] = {o[0] + lx, o[1] + ly, o[2] + lz};
-  // act: the thread owns an element of the mesh.  The others (padding lanes,
-  // bricks overhanging the mesh) compute on the nearest mesh element, write
-  // only their own or the spare LDS slot, and store nothing.
-  const bool act = el < TE && cu[0] < m.nx && cu[1] < m.ny && cu[2] < m.nz;
+  // own: the lane's element (for a padding lane its twin's) lies in the mesh;
+  // the lanes of a brick's elements overhanging the mesh compute on the
+  // nearest mesh element, see no neighbours and write only their own LDS slot.
+  // act: own, and not a padding lane; only these store results.
+  const bool own = cu[0] < m.nx && cu[1] < m.ny && cu[2] < m.nz;
+  const bool act = el0 < TE && own;
   const int c[3] = {min(cu[0], m.nx - 1), min(cu[1], m.ny - 1), min(cu[2], m.nz - 1)};
-  const int le = el < TE ? el : TE;
+  const int le = el;
   TC* S1 = sS1 + le * PE;
   TC* S2 = sS2 + le * PE;
   // the face-scalar slot of an element lies inside its own S2 tile (slot
@@ -291,18 +299,17 @@ __global__ __launch_bounds__(apply_block(N)) void k_apply_affine(MeshArgs<TC> m,
   // element-local hand-offs below need no workgroup barrier
   TC* Fe = F + le * FS;
   const int64_t e = c[0] + (int64_t)m.nx * (c[1] + (int64_t)m.ny * c[2]);
-  TC K, G[6], cr = TC(0);
-  K = m.K[e];
-#pragma unroll
-  for (int f = 0; f < 6; ++f) G[f] = OFF32 ? m.G[(uint32_t)(6 * e + f)] : m.G[6 * e + f];
-  if (m.R) cr = m.R[e] * m.vol;
+  const TC K = m.K[e];
+  // face coefficients of the element's faces 2D and 2D+1, loaded in the phase
+  // that uses them (keeps the register count at 64 for n = 5 in FP64)
+  auto gco = [&](int f) { return OFF32 ? m.G[(uint32_t)(6 * e + f)] : m.G[6 * e + f]; };
   TC b[N], v[N], w[N];
   // ---------------- X: b_x -> S1
-  face_phase<N, 0, BX, BY, BZ, FS, TC, TIN, TRANS, OFF32>(m, T, x, act, e, c, o, Nd, t, t1, t2, F, Fe, K, G[0], G[1], TC(0), b);
+  face_phase<N, 0, BX, BY, BZ, FS, TC, TIN, TRANS, OFF32>(m, T, x, own, e, c, o, Nd, t, t1, t2, F, Fe, K, gco(0), gco(1), TC(0), b);
   lds_put<N, 0>(S1, t1, t2, b);
   lds_sync<XROW>();  // F (read by the x-neighbours) is rewritten by the next phase
   // ---------------- Y: b_y -> S2, M_y b_x -> S1
-  face_phase<N, 1, BX, BY, BZ, FS, TC, TIN, TRANS, OFF32>(m, T, x, act, e, c, o, Nd, t, t1, t2, F, Fe, K, G[2], G[3], TC(0), b);
+  face_phase<N, 1, BX, BY, BZ, FS, TC, TIN, TRANS, OFF32>(m, T, x, own, e, c, o, Nd, t, t1, t2, F, Fe, K, gco(2), gco(3), TC(0), b);
   {
     lds_get<N, 1>(S1, t1, t2, v);
     mass_line<N, TC, TRANS>(T, v, w);
@@ -325,7 +332,8 @@ __global__ __launch_bounds__(apply_block(N)) void k_apply_affine(MeshArgs<TC> m,
   lds_sync<ELEM>();
   // ---------------- Z: b_z -> S2, r = M_z S1
   TC r[N], xz[N];  // xz: the thread's z-line of x, for the fused <x, y>
-  face_phase<N, 2, BX, BY, BZ, FS, TC, TIN, TRANS, OFF32>(m, T, x, act, e, c, o, Nd, t, t1, t2, F, Fe, K, G[4], G[5], cr, b,
+  const TC cr = m.R ? m.R[e] * m.vol : TC(0);
+  face_phase<N, 2, BX, BY, BZ, FS, TC, TIN, TRANS, OFF32>(m, T, x, own, e, c, o, Nd, t, t1, t2, F, Fe, K, gco(4), gco(5), cr, b,
                                                DOT ? xz : nullptr);
   {
     lds_get<N, 2>(S1, t1, t2, v);
