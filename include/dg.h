@@ -248,6 +248,17 @@ int64_t dg_num_dofs(const dg_ctx* ctx);
 int64_t dg_num_elements(const dg_ctx* ctx);
 int dg_nodes_per_dir(const dg_ctx* ctx);
 
+/* The apply kernel dg_setup chose for the mesh (Sec. 3.3 benchmarks the
+ * operator on axis-parallel grids, problem A, and on affine geometries,
+ * problem B):  DG_KERNEL_AFFINE for axis-parallel boxes (no vertices given),
+ * DG_KERNEL_TRILINEAR for general trilinear element maps (Jacobian at every
+ * quadrature point), DG_KERNEL_PARALLELEPIPED when every element is the same
+ * parallelepiped (the grid under one affine map: constant metric, the
+ * axis-parallel kernel plus the mixed-derivative terms).  -1 for a NULL
+ * context. */
+enum dg_kernel { DG_KERNEL_AFFINE = 0, DG_KERNEL_TRILINEAR = 1, DG_KERNEL_PARALLELEPIPED = 2 };
+int dg_apply_kernel(const dg_ctx* ctx);
+
 /* Release the context's host memory (the caller frees the workspace). */
 void dg_destroy(dg_ctx* ctx);
 

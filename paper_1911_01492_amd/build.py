@@ -14,7 +14,7 @@ ARCH = "gfx950"
 FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-Wall",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I" + os.path.join(HERE, "..", "include")]
-SOURCES = ["dg_affine.hip", "dg_mfma.hip", "dg_trilinear.hip", "dg_vec.hip", "dg_geom.hip", "dg_api.hip"]
+SOURCES = ["dg_affine.hip", "dg_mfma.hip", "dg_ppd.hip", "dg_trilinear.hip", "dg_vec.hip", "dg_geom.hip", "dg_api.hip"]
 
 
 def _compile(src: str) -> str:

@@ -17,21 +17,23 @@
 // factorisation as the volume term (Sec. 3.3: matrix-free, sum-factorised,
 // no gather/scatter: the kernels index the global element-blocked vectors).
 //
-// Layout: a workgroup owns a brick of BX x BY x BZ elements (tile_dims(n)),
-// n^2 threads per element, three n^3 LDS tiles per element.  Neighbour lines
-// inside the brick come from LDS, the others from HBM (issued up front).
+// Layout: a workgroup owns a brick of BX x BY x BZ elements (tile_x/y/z(n)),
+// n^2 threads per element, two n^3 LDS tiles per element (S1, S2).
+// Neighbour lines inside the brick come from LDS, the others from HBM
+// (issued up front).  The phases of the apply kernel:
 //
-//   phase Z : own z-lines, z-neighbour lines   -> bz = L_z u
-//   phase Y : own y-lines, y-neighbour lines   -> by = L_y u
-//   phase X : own x-lines, x-neighbour lines   -> bx = L_x u,
-//             c = M_x by, e = M_x bz
-//   phase Y2: f = M_y bx + c, g = M_y e
-//   phase Z2: y = M_z f + g -> HBM
+//   X : own x-lines, x-neighbour scalars -> b_x = L_x u            -> S1
+//   Y : own y-lines, y-neighbour scalars -> b_y = L_y u -> S2, M_y S1 -> S1
+//   X2: S1 + M_x S2                                                -> S1
+//   Z : own z-lines, z-neighbour scalars -> b_z = L_z u -> S2, r = M_z S1
+//   X3, Y3: M_y M_x S2                                             -> S2
+//   Z2: y = r + S2 -> HBM
 //
-// so that y = M_z (M_y bx + M_x by) + M_y M_x bz.
+// so that y = M_z (M_y b_x + M_x b_y) + M_y M_x b_z.
 #include "dg_internal.hpp"
 #include "dg_kernels.hpp"
 #include "dg_lines.hpp"
+#include "dg_faces.hpp"
 
 namespace dg {
 
@@ -98,136 +100,6 @@ __device__ __forceinline__ void line_op(const Tables<TC>& T, const TC (&u)[N], c
   }
 }
 
-
-// Neighbour face scalars along axis D for both sides.  In-brick neighbours
-// publish their own face scalars in F (written by their threads in this
-// phase), out-of-brick neighbours come from HBM, Dirichlet sides are absent.
-template <int N, int D, int BX, int BY, int BZ, typename TC, typename TIN, bool OFF32 = false>
-struct AxisNeighbours {
-  bool inL, inH, glL, glH, hasL, hasH;
-  int elL, elH;
-  int64_t eL, eH;
-  TC gL[N], gH[N];
-  __device__ __forceinline__ void locate(int nx, int ny, const int (&c)[3], const int (&o)[3],
-                                         const int (&Nd)[3], int periodic, bool slot = true) {
-    constexpr int Bd = D == 0 ? BX : (D == 1 ? BY : BZ);
-    constexpr int sD = D == 0 ? 1 : (D == 1 ? BX : BX * BY);
-    const int el = (c[0] - o[0]) + BX * ((c[1] - o[1]) + BY * (c[2] - o[2]));
-    const int cl = nb_coord(c[D], 0, Nd[D], periodic), ch = nb_coord(c[D], 1, Nd[D], periodic);
-    hasL = slot && cl >= 0;
-    hasH = slot && ch >= 0;
-    const int ll = cl - o[D], lh = ch - o[D];
-    inL = hasL && ll >= 0 && ll < Bd;
-    inH = hasH && lh >= 0 && lh < Bd;
-    glL = hasL && !inL;
-    glH = hasH && !inH;
-    elL = el + (ll - (c[D] - o[D])) * sD;
-    elH = el + (lh - (c[D] - o[D])) * sD;
-    int g[3] = {c[0], c[1], c[2]};
-    g[D] = cl < 0 ? 0 : cl;
-    eL = g[0] + (int64_t)nx * (g[1] + (int64_t)ny * g[2]);
-    g[D] = ch < 0 ? 0 : ch;
-    eH = g[0] + (int64_t)nx * (g[1] + (int64_t)ny * g[2]);
-  }
-  // issue the HBM loads (before the own work of the phase, to hide latency)
-  __device__ __forceinline__ void fetch(const TIN* __restrict__ x, int t1, int t2) {
-    if (glL) glb_get<N, D, TC, TIN, OFF32>(x, eL, t1, t2, gL);
-    if (glH) glb_get<N, D, TC, TIN, OFF32>(x, eH, t1, t2, gH);
-  }
-  // the HBM neighbour lines reduced to their face scalars (frees the lines)
-  TC uL, dL, uH, dH;
-  __device__ __forceinline__ void reduce(const Tables<TC>& T) {
-    uL = dL = uH = dH = TC(0);
-    if (glL) {
-      uL = gL[N - 1];
-      dL = dot_end<N, TC, 1>(T, gL);
-    }
-    if (glH) {
-      uH = gH[0];
-      dH = dot_end<N, TC, 0>(T, gH);
-    }
-  }
-  // neighbour scalars: low side -> its upper-face (U, d1.u), high side -> its lower-face (U, d0.u);
-  // element slots of FS values in F
-  template <int FS>
-  __device__ __forceinline__ void scalars(const TC* F, int t, TC& UL, TC& GLr, TC& UH, TC& GHr) const {
-    constexpr int NN = N * N;
-    UL = uL;
-    GLr = dL;
-    UH = uH;
-    GHr = dH;
-    if (inL) {
-      UL = F[elL * FS + 2 * NN + t];
-      GLr = F[elL * FS + 3 * NN + t];
-    }
-    if (inH) {
-      UH = F[elH * FS + 0 * NN + t];
-      GHr = F[elH * FS + 1 * NN + t];
-    }
-  }
-};
-
-// Barrier over the threads that exchange data through LDS at one point of
-// the apply.  WAVE: every thread whose LDS writes the readers depend on lies
-// in the reader's wavefront (the lanes of a wavefront execute together and
-// its LDS operations complete in order), so only the compiler has to be kept
-// from moving LDS accesses across it; otherwise the workgroup barrier.
-template <bool WAVE>
-__device__ __forceinline__ void lds_sync() {
-  if constexpr (WAVE) {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  } else {
-    __syncthreads();
-  }
-}
-
-// One face-aware direction of the affine apply: b = L_D u on this thread's
-// line along axis D (own line from HBM, neighbour face scalars from the
-// brick's exchange area F or from HBM).  Contains one barrier; every thread
-// of the block calls it.  act == false: the lane's element overhangs the
-// mesh (it computes on a clamped element, sees no neighbours, and its result
-// is discarded).
-template <int N, int D, int BX, int BY, int BZ, int FS, typename TC, typename TIN, bool TRANS, bool OFF32>
-__device__ __forceinline__ void face_phase(const MeshArgs<TC>& m, const Tables<TC>& T, const TIN* __restrict__ x,
-                                           bool act, int64_t e, const int (&c)[3], const int (&o)[3],
-                                           const int (&Nd)[3], int t, int t1, int t2, TC* F, TC* Fe, TC K, TC GL,
-                                           TC GH, TC cr, TC (&b)[N], TC* own = nullptr) {
-  constexpr int NN = N * N;
-  AxisNeighbours<N, D, BX, BY, BZ, TC, TIN, OFF32> nb;
-  TC u[N], g0, g1;
-  {
-    nb.locate(m.nx, m.ny, c, o, Nd, m.periodic, act);
-    nb.fetch(x, t1, t2);
-    glb_get<N, D, TC, TIN, OFF32>(x, e, t1, t2, u);
-    nb.reduce(T);
-    g0 = dot_end<N, TC, 0>(T, u);
-    g1 = dot_end<N, TC, 1>(T, u);
-    Fe[0 * NN + t] = u[0];
-    Fe[1 * NN + t] = g0;
-    Fe[2 * NN + t] = u[N - 1];
-    Fe[3 * NN + t] = g1;
-  }
-  // x-neighbours inside the brick share the wavefront when a brick row does
-  lds_sync<D == 0 && 64 % (BX * NN) == 0>();
-  {
-    TC UL, GLr, UH, GHr;
-    nb.template scalars<FS>(F, t, UL, GLr, UH, GHr);
-    line_op_s<N, TC, TRANS>(T, u, g0, g1, UL, GLr, UH, GHr, nb.hasL, nb.hasH, GL, GH, K * m.vs[D], m.ih[D],
-                            m.sg[D], m.At[D], b);
-    if (own != nullptr) {  // the caller keeps the line (x along D at (t1, t2))
-#pragma unroll
-      for (int i = 0; i < N; ++i) own[i] = u[i];
-    }
-    if (cr != TC(0)) {  // reaction c |T| M u along this line (the other two masses follow)
-      TC mu[N];
-      mass_line<N, TC, false>(T, u, mu);
-#pragma unroll
-      for (int i = 0; i < N; ++i) b[i] += cr * mu[i];
-    }
-  }
-}
 
 // y = A x (TRANS: A^T x) on affine meshes.  DOT: also the block partials of
 // <x, y> (y as stored) for the CG scalar <p, A p>.  skip != nullptr &&

@@ -36,6 +36,11 @@ struct dg_ctx {
   float* R32;
   bool reaction;
   bool affine_geom;      // trilinear mesh whose elements are all parallelepipeds
+  bool ppd;              // ... and all the same parallelepiped (an affine image of the grid):
+                         // the apply takes the constant-metric kernel
+  double pG[6];          // its metric |det J| J^-1 J^-T: xx, yy, zz, xy, xz, yz
+  double parea[3];       // face areas |J e_a x J e_b| of the faces normal to d
+  double pdet;           // det J
   double* vert64;
   float* vert32;
   double* dinv64;
@@ -288,18 +293,21 @@ bool build_tables(int n, Tables<double>& T) {
       for (int k = 0; k < n; ++k) D[q * n + i] += l[k] * Dn[k * n + i];
     }
   }
-  std::vector<double> Mv((size_t)n * n), Sv((size_t)n * n);
+  std::vector<double> Mv((size_t)n * n), Sv((size_t)n * n), Cv((size_t)n * n);
   for (int i = 0; i < n; ++i)
     for (int j = 0; j < n; ++j) {
-      double m = 0.0, s = 0.0;
+      double m = 0.0, s = 0.0, cm = 0.0;
       for (int q = 0; q < n; ++q) {
         m += gw[q] * B[q * n + i] * B[q * n + j];
         s += gw[q] * D[q * n + i] * D[q * n + j];
+        cm += gw[q] * B[q * n + i] * D[q * n + j];
       }
       T.M[i * kMaxN + j] = m;
       T.S[i * kMaxN + j] = s;
+      T.Cd[i * kMaxN + j] = cm;
       Mv[i * n + j] = m;
       Sv[i * n + j] = s;
+      Cv[i * n + j] = cm;
       T.B[i * kMaxN + j] = B[i * n + j];
       T.D[i * kMaxN + j] = D[i * n + j];
     }
@@ -330,7 +338,8 @@ bool build_tables(int n, Tables<double>& T) {
     }
   }
   return even_odd(n, Mv, 1, T.eM) && even_odd(n, Sv, 1, T.eS) && even_odd(n, B, 1, T.eB) &&
-         even_odd(n, Bt, 1, T.eBt) && even_odd(n, Dg, -1, T.eDg) && even_odd(n, Dgt, -1, T.eDgt);
+         even_odd(n, Bt, 1, T.eBt) && even_odd(n, Dg, -1, T.eDg) && even_odd(n, Dgt, -1, T.eDgt) &&
+         even_odd(n, Cv, -1, T.eC);
 }
 
 void tables_to_f32(const Tables<double>& a, Tables<float>& b) {
@@ -340,6 +349,7 @@ void tables_to_f32(const Tables<double>& a, Tables<float>& b) {
     b.S[i] = (float)a.S[i];
     b.B[i] = (float)a.B[i];
     b.D[i] = (float)a.D[i];
+    b.Cd[i] = (float)a.Cd[i];
   }
   for (int i = 0; i < kMaxN; ++i) {
     b.d0[i] = (float)a.d0[i];
@@ -353,6 +363,7 @@ void tables_to_f32(const Tables<double>& a, Tables<float>& b) {
   even_odd_to_f32(a.eBt, b.eBt);
   even_odd_to_f32(a.eDg, b.eDg);
   even_odd_to_f32(a.eDgt, b.eDgt);
+  even_odd_to_f32(a.eC, b.eC);
 }
 
 // ------------------------------------------------------------------ workspace
@@ -461,6 +472,7 @@ MeshArgs<double> args64(const dg_ctx* c) {
   m.vol = (1.0 / c->desc.nx) * (1.0 / c->desc.ny) * (1.0 / c->desc.nz);
   m.affg = c->affine_geom ? 1 : 0;
   m.fb = (double*)c->fb;
+  m.go[0] = m.go[1] = m.go[2] = 0.0;
   fill_scales(m);
   return m;
 }
@@ -483,17 +495,45 @@ MeshArgs<float> args32(const dg_ctx* c) {
   m.vol = (float)((1.0 / c->desc.nx) * (1.0 / c->desc.ny) * (1.0 / c->desc.nz));
   m.affg = c->affine_geom ? 1 : 0;
   m.fb = (float*)c->fb;
+  m.go[0] = m.go[1] = m.go[2] = 0.0f;
   fill_scales(m);
+  return m;
+}
+
+// The scalars of the constant-metric apply on a mesh of equal
+// parallelepipeds: the line operators take the diagonal metric entries (volume
+// and normal-flux scale G_dd) and the face areas, the off-diagonal entries
+// couple the axes; computed in FP64 from the mesh's J.
+template <typename T>
+MeshArgs<T> ppd_args(const dg_ctx* c, MeshArgs<T> m) {
+  for (int d = 0; d < 3; ++d) {
+    m.vs[d] = (T)c->pG[d];
+    m.At[d] = (T)c->parea[d];
+    m.ih[d] = (T)(c->pG[d] / c->parea[d]);
+  }
+  m.go[0] = (T)c->pG[3];
+  m.go[1] = (T)c->pG[4];
+  m.go[2] = (T)c->pG[5];
+  m.vol = (T)c->pdet;
   return m;
 }
 
 // dot != 0: <x, A x> into st->pq (st must then be given; par selects rho for the
 // breakdown check)
+// block partials of the fused <x, A x> of an apply: one per brick of the
+// affine and parallelepiped kernels, one per element block of the trilinear one
+int64_t apply_partials(const dg_ctx* c) {
+  if (c->trilinear && !c->ppd) return element_blocks(c->n, c->E);
+  return affine_tiles(c->n, c->desc.nx, c->desc.ny, c->desc.nz);
+}
+
 hipError_t apply_any(dg_ctx* c, int prec, int trans, int dot, const void* x, void* y, CgState* st, int par,
                      const int* skip, hipStream_t s, double* partials = nullptr) {
   const MeshArgs<double> m64 = args64(c);
   const MeshArgs<float> m32 = args32(c);
   double* part = partials ? partials : c->partials;
+  if (c->ppd)  // the form is symmetric: the transpose is the same operator
+    return launch_apply_ppd(c->n, prec, dot, ppd_args(c, m64), ppd_args(c, m32), x, y, part, st, par, skip, s);
   if (c->trilinear)
     return launch_apply_trilinear(c->n, prec, trans, dot, m64, m32, x, y, part, st, par, skip, s);
   return launch_apply_affine(c->n, prec, trans, dot, m64, m32, x, y, part, st, par, skip, s);
@@ -559,6 +599,54 @@ static bool all_parallelepipeds(int nx, int ny, int nz, const std::vector<double
   return true;
 }
 
+// Every element is the same parallelepiped: J from the extent of the whole
+// mesh (the grid's affine image), each element's edge vectors equal to its
+// columns within 8 ulps of the largest coordinate, det J > 0.  Fills the
+// metric, face areas and determinant of c.  Call only when every element is
+// a parallelepiped.
+static bool uniform_parallelepipeds(int nx, int ny, int nz, const std::vector<double>& v, dg_ctx* c) {
+  auto X = [&](int ix, int iy, int iz, int a) { return v[3 * (ix + (size_t)(nx + 1) * (iy + (size_t)(ny + 1) * iz)) + a]; };
+  double J[3][3], xmax = 0.0;
+  for (int a = 0; a < 3; ++a) {
+    J[a][0] = (X(nx, 0, 0, a) - X(0, 0, 0, a)) / nx;
+    J[a][1] = (X(0, ny, 0, a) - X(0, 0, 0, a)) / ny;
+    J[a][2] = (X(0, 0, nz, a) - X(0, 0, 0, a)) / nz;
+  }
+  for (double q : v) xmax = std::max(xmax, std::fabs(q));
+  const double tol = 8.0 * 2.220446049250313e-16 * std::max(1.0, xmax);
+  for (int z = 0; z < nz; ++z)
+    for (int y = 0; y < ny; ++y)
+      for (int x = 0; x < nx; ++x)
+        for (int a = 0; a < 3; ++a) {
+          const double o = X(x, y, z, a);
+          if (std::fabs(X(x + 1, y, z, a) - o - J[a][0]) > tol || std::fabs(X(x, y + 1, z, a) - o - J[a][1]) > tol ||
+              std::fabs(X(x, y, z + 1, a) - o - J[a][2]) > tol)
+            return false;
+        }
+  // cofactors: adj[r][a] = (J e_{a+1} x J e_{a+2})_r = det J (J^-T)_{ra}
+  double adj[3][3];
+  for (int a = 0; a < 3; ++a) {
+    const int p = (a + 1) % 3, q = (a + 2) % 3;
+    adj[0][a] = J[1][p] * J[2][q] - J[2][p] * J[1][q];
+    adj[1][a] = J[2][p] * J[0][q] - J[0][p] * J[2][q];
+    adj[2][a] = J[0][p] * J[1][q] - J[1][p] * J[0][q];
+  }
+  const double det = J[0][0] * adj[0][0] + J[1][0] * adj[1][0] + J[2][0] * adj[2][0];
+  if (!(det > 0.0)) return false;
+  // G = det J^-1 J^-T = adj^T adj / det
+  auto G = [&](int a, int b) { return (adj[0][a] * adj[0][b] + adj[1][a] * adj[1][b] + adj[2][a] * adj[2][b]) / det; };
+  c->pG[0] = G(0, 0);
+  c->pG[1] = G(1, 1);
+  c->pG[2] = G(2, 2);
+  c->pG[3] = G(0, 1);
+  c->pG[4] = G(0, 2);
+  c->pG[5] = G(1, 2);
+  for (int d = 0; d < 3; ++d)
+    c->parea[d] = std::sqrt(adj[0][d] * adj[0][d] + adj[1][d] * adj[1][d] + adj[2][d] * adj[2][d]);
+  c->pdet = det;
+  return true;
+}
+
 int dg_setup(const dg_mesh_desc* mesh, dg_ctx** out, void* stream) {
   if (!out) return fail(nullptr, DG_ERR_ARG, "out is NULL");
   *out = nullptr;
@@ -587,6 +675,7 @@ int dg_setup(const dg_mesh_desc* mesh, dg_ctx** out, void* stream) {
   c->R32 = (float*)(w + L.R32);
   c->reaction = false;
   c->affine_geom = false;
+  c->ppd = false;
   c->vert64 = c->trilinear ? (double*)(w + L.vert64) : nullptr;
   c->vert32 = c->trilinear ? (float*)(w + L.vert32) : nullptr;
   c->dinv64 = (double*)(w + L.dinv64);
@@ -640,6 +729,7 @@ int dg_setup(const dg_mesh_desc* mesh, dg_ctx** out, void* stream) {
     SETUP_TRY(hipMemcpyAsync(hv.data(), mesh->vertices, nv3 * sizeof(double), hipMemcpyDeviceToHost, s));
     SETUP_TRY(hipStreamSynchronize(s));
     c->affine_geom = all_parallelepipeds(mesh->nx, mesh->ny, mesh->nz, hv);
+    c->ppd = c->affine_geom && uniform_parallelepipeds(mesh->nx, mesh->ny, mesh->nz, hv, c);
   }
   SETUP_TRY(compute_dinv(c, s));
   SETUP_TRY(hipStreamSynchronize(s));
@@ -806,8 +896,7 @@ int pcg64(dg_ctx* c, const dg_cg_opts* o, const double* b, double* x, int maxit,
   int rc = read_state(c, 0, hs, s);
   if (rc != DG_OK) return rc;
   // few block partials: the update kernels sum them themselves (no finish kernels)
-  const int64_t nbA = c->trilinear ? element_blocks(c->n, c->E) : affine_tiles(c->n, c->desc.nx, c->desc.ny,
-                                                                               c->desc.nz);
+  const int64_t nbA = apply_partials(c);
   const bool fused = nbA <= 4096 && 2 * vec_blocks(n) <= 8192;
   double* partA = c->partials;
   double* partB = c->partials + nbA;
@@ -889,8 +978,7 @@ int pcg64_single(dg_ctx* c, const dg_cg_opts* o, const double* b, double* x, int
   const int64_t nvb = vec_blocks(n);
   double* partA = c->partials;             // <r, z>, <r, r> of the update (2 per vector block)
   double* partB = c->partials + 2 * nvb;   // <z, w> of the apply
-  const int64_t nbB = c->trilinear ? element_blocks(c->n, c->E) : affine_tiles(c->n, c->desc.nx, c->desc.ny,
-                                                                                c->desc.nz);
+  const int64_t nbB = apply_partials(c);
   HIP_TRY(c, apply_any(c, DG_F64, o->transpose, 0, x, c->q64, nullptr, 0, nullptr, s));
   // r = b - A x0, z = Dinv r (into z), gamma = <r, z>, <r, r>, <b, b>
   HIP_TRY(c, (launch_cg_init<double, double, double, double>(n, b, c->q64, c->r64, c->z64, dinv, o->rtol, st,
@@ -959,8 +1047,7 @@ int pcg_inner(dg_ctx* c, const dg_cg_opts* o, int prec, bool fresh, double inner
   int rc = read_state(c, 1, hs, s);
   if (rc != DG_OK) return rc;
   // few block partials: the update kernels sum them themselves (no finish kernels)
-  const int64_t nbA = c->trilinear ? element_blocks(c->n, c->E) : affine_tiles(c->n, c->desc.nx, c->desc.ny,
-                                                                               c->desc.nz);
+  const int64_t nbA = apply_partials(c);
   const bool fused = !blk && nbA <= 4096 && 2 * vec_blocks(n) <= 8192;
   double* partA = c->partials;
   double* partB = c->partials + nbA;
@@ -1134,6 +1221,10 @@ int dg_cg_solve(dg_ctx* c, const dg_cg_opts* o, const double* b, double* x, dg_c
 int64_t dg_num_dofs(const dg_ctx* c) { return c ? c->ndof : -1; }
 int64_t dg_num_elements(const dg_ctx* c) { return c ? c->E : -1; }
 int dg_nodes_per_dir(const dg_ctx* c) { return c ? c->n : -1; }
+int dg_apply_kernel(const dg_ctx* c) {
+  if (!c) return -1;
+  return c->ppd ? DG_KERNEL_PARALLELEPIPED : (c->trilinear ? DG_KERNEL_TRILINEAR : DG_KERNEL_AFFINE);
+}
 
 void dg_destroy(dg_ctx* c) { delete c; }
 

@@ -47,6 +47,8 @@ struct Tables {
                         // points (Dg B = D; centro-antisymmetric)
   T Mis[kMaxN * kMaxN]; // M^{-1/2} (symmetric), for the generalized eigenproblems of
                         // the element block-Jacobi preconditioner
+  T Cd[kMaxN * kMaxN];  // mixed matrix C_ij = sum_q w_q l_i(x_q) l_j'(x_q) = int l_i l_j'
+  EvenOdd<T> eC;        // C by its even-odd halves (centro-antisymmetric)
 };
 
 // Eigen-decomposition of a symmetric n x n matrix (row stride kMaxN) by the
@@ -108,7 +110,9 @@ struct MeshArgs {
   T At[3];              // face area h_t1 h_t2 of faces normal to d
   T vs[3];              // At_d / h_d (volume stiffness scale along d, without K)
   const T* R;           // E reaction coefficients c_T, or nullptr (no reaction term)
-  T vol;                // h_x h_y h_z (affine element volume)
+  T vol;                // h_x h_y h_z (affine element volume; |det J| on parallelepipeds)
+  T go[3];              // parallelepiped meshes: the off-diagonal metric entries G_xy, G_xz,
+                        // G_yz of G = |det J| J^-1 J^-T (zero on axis-parallel boxes)
   int affg;             // trilinear meshes: 1 when every element is a parallelepiped
   T* fb;                // trilinear meshes: per element and axis d, the 2 n^2 line scalars of
                         // its lower face (d, 0), written by the neighbour that evaluates the

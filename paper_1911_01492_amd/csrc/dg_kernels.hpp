@@ -80,6 +80,11 @@ hipError_t launch_dA_affine(int n, const MeshArgs<double>& m, const double* u, c
 hipError_t launch_apply_trilinear(int n, int prec, int trans, int dot, const MeshArgs<double>& m64,
                                   const MeshArgs<float>& m32, const void* x, void* y, double* partials,
                                   CgState* st, int par, const int* skip, hipStream_t s);
+// meshes of equal parallelepipeds (constant metric; m64 / m32 carry the
+// metric scalars): y = A x, the form being symmetric also A^T x
+hipError_t launch_apply_ppd(int n, int prec, int dot, const MeshArgs<double>& m64, const MeshArgs<float>& m32,
+                            const void* x, void* y, double* partials, CgState* st, int par, const int* skip,
+                            hipStream_t s);
 hipError_t launch_diag_trilinear(int n, const MeshArgs<double>& m, double* d, const int* run, hipStream_t s);
 // g_T = u^T dA/dtheta_T v on trilinear meshes; parts: 7 E doubles of scratch
 hipError_t launch_dA_trilinear(int n, const MeshArgs<double>& m, const double* u, const double* v, double* parts,

@@ -1,0 +1,346 @@
+// dg_ppd.hip -- sum-factorised SWIPDG apply on meshes whose elements are all
+// the same parallelepiped: an affine image x = J xi of the axis-parallel grid
+// (problem B of Sec. 3.3: affine geometries, coefficients per cell).
+//
+// With the constant metric G = |det J| J^-1 J^-T the element form is the
+// axis-parallel one with a full 3 x 3 coefficient: on the reference grid
+//
+//     K grad u . grad v |det J| = K sum_ab G_ab d_a u d_b v,
+//
+// and on a face normal to axis d the area-weighted conormal is G e_d.  The
+// diagonal entries G_dd, the face areas |J e_a x J e_b| and the penalty
+// sigma_e = sig_hat / h_d (h_d = 1 / n_d, as on axis-parallel meshes) enter
+// the 1D line operators L_d of the axis-parallel apply unchanged (volume
+// scale G_dd, normal-flux scale G_dd, penalty area |F_d|).  Each
+// off-diagonal entry G_ab (a < b, c the third axis) adds
+//
+//     G_ab M_c (x) P_ab,
+//
+// P_ab the mixed-derivative part of the form in the (a, b) plane: the volume
+// term K (C_a (x) C_b^T + C_a^T (x) C_b) with C_ij = int l_i l_j', and the
+// tangential parts of the consistency and symmetry terms on the a- and
+// b-faces.  Since C + C^T = E = diag(-1, 0, ..., 0, 1) (integration by
+// parts on GLL nodes), the volume term is -2 K C_a (x) C_b plus E terms on
+// the element's faces, and face by face the three pieces combine to
+//
+//     a-face at the upper end:  C_b X_hi + G_hi E_b (U_hi - u_hi),
+//     a-face at the lower end: -C_b X_lo + G_lo E_b (u_lo - U_lo),
+//     X = K u - 2 G U,
+//
+// with u the element's trace on the face, U the neighbour's (0 on a
+// Dirichlet face), G the face coefficient (gamma / 2 on interior faces, K on
+// Dirichlet faces).  So
+//
+//     P_ab = C_b (-2 K C_a u + a-face rows X) + C_a (b-face rows X) + corners,
+//
+// the a-face rows riding on the a-line contraction, the b-face rows needing
+// one contraction along a of the face row, and the E terms landing on the
+// four edges of the (a, b) plane.  The transpose is the same operator (the
+// form is symmetric).
+//
+// Phases (two more LDS tiles than the axis-parallel apply, S3 and S4, and
+// small per-element exchange rows):
+//   X : b_x -> S1; c_x = -2K C u + x-face rows -> S3; x-face jumps
+//   Y : b_y -> S2; S1 <- M_y S1 + G_xy P_xy (P_xy = C_y c_x + y-face rows along x
+//       + corners); c_y = -2K C u + y-face rows -> S4; y-face rows and jumps
+//   X2: S1 += M_x S2
+//   Z : b_z -> S2; r = M_z S1; S3 <- P_xz = C_z c_x + ...; S4 <- P_yz = C_z c_y + ...
+//   X3: S2 <- M_x S2 + G_xz S3; S4 <- G_yz M_x S4
+//   Y3: S2 <- M_y S2
+//   Z2: y = r + S2 + S4
+// so that y = M_z (M_y b_x + M_x b_y + G_xy P_xy) + M_y (M_x b_z + G_xz P_xz)
+//         + G_yz M_x P_yz.
+#include "dg_internal.hpp"
+#include "dg_kernels.hpp"
+#include "dg_lines.hpp"
+#include "dg_faces.hpp"
+
+namespace dg {
+
+// out = C a along the line (C centro-antisymmetric: even-odd halves from n = 5)
+template <int N, typename TC>
+__device__ __forceinline__ void cd_line(const Tables<TC>& T, const TC (&a)[N], TC (&out)[N]) {
+  if constexpr (N >= 5) {
+    contract_eo<N, TC, -1>(T.eC, a, out);
+  } else {
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      TC s = TC(0);
+#pragma unroll
+      for (int j = 0; j < N; ++j) s += T.Cd[i * kMaxN + j] * a[j];
+      out[i] = s;
+    }
+  }
+}
+
+template <int N, typename TIN, typename TOUT, typename TC, bool DOT, bool OFF32>
+__global__ __launch_bounds__(apply_block(N)) void k_apply_ppd(MeshArgs<TC> m, const TIN* __restrict__ x,
+                                                              TOUT* __restrict__ y, double* partials,
+                                                              const int* skip) {
+  constexpr int NN = N * N, N3 = NN * N;
+  constexpr int BX = tile_x(N), BY = tile_y(N), BZ = tile_z(N), TE = BX * BY * BZ;
+  constexpr int PE = Lay<N, TC>::PE;
+  constexpr bool F_IN_S2 = 4 * NN <= PE;
+  constexpr int FS = F_IN_S2 ? PE : 4 * NN;
+  constexpr int BLOCK = apply_block(N);
+  static_assert(TE * NN <= BLOCK && BLOCK <= kBlock, "brick too large");
+  // padding lanes repeat the work of the brick's last element lane for lane
+  // (same values to the same LDS words, in the same wavefront)
+  static_assert(TE * NN == BLOCK || BLOCK - (TE - 1) * NN <= 64, "padding lanes and their twins share a wavefront");
+  __shared__ TC sS1[TE * PE], sS2[TE * PE], sS3[TE * PE], sS4[TE * PE];
+  __shared__ TC sFx[F_IN_S2 ? 1 : TE * 4 * NN];
+  // per element: x-face jumps (lo, hi), y-face jumps, y-face rows X, z-face rows X
+  __shared__ TC sP[TE * 8 * NN];
+  __shared__ TC sC[NN];  // C, row-major, for lane-indexed rows
+  __shared__ double red[BLOCK / 64];
+  if (skip != nullptr && *skip) return;
+  TC* F = F_IN_S2 ? sS2 : sFx;
+  const Tables<TC>& T = *m.tab;
+  const int tb = (int)xcd_remap(blockIdx.x, gridDim.x);
+  int o[3];
+  brick_origin<BX, BY, BZ>(tb, m.nx, m.ny, m.nz, o);
+  const int Nd[3] = {m.nx, m.ny, m.nz};
+  const int tid = threadIdx.x, el0 = tid / NN, t = tid - el0 * NN, t1 = t % N, t2 = t / N;
+  const int el = min(el0, TE - 1);
+  const int lx = el % BX, ly = (el / BX) % BY, lz = el / (BX * BY);
+  const int cu[3] = {o[0] + lx, o[1] + ly, o[2] + lz};
+  // own: the lane's element lies in the mesh (overhanging elements compute on
+  // the nearest mesh element without neighbours); act: own and not padding
+  const bool own = cu[0] < m.nx && cu[1] < m.ny && cu[2] < m.nz;
+  const bool act = el0 < TE && own;
+  const int c[3] = {min(cu[0], m.nx - 1), min(cu[1], m.ny - 1), min(cu[2], m.nz - 1)};
+  TC* S1 = sS1 + el * PE;
+  TC* S2 = sS2 + el * PE;
+  TC* S3 = sS3 + el * PE;
+  TC* S4 = sS4 + el * PE;
+  TC* Fe = F + el * FS;
+  TC* P = sP + el * 8 * NN;
+  if (tid < NN) sC[tid] = T.Cd[(tid / N) * kMaxN + tid % N];
+  const int64_t e = c[0] + (int64_t)m.nx * (c[1] + (int64_t)m.ny * c[2]);
+  const TC K = m.K[e], K2 = TC(-2) * K;
+  auto gco = [&](int f) { return OFF32 ? m.G[(uint32_t)(6 * e + f)] : m.G[6 * e + f]; };
+  const TC gxy = m.go[0], gxz = m.go[1], gyz = m.go[2];
+  TC b[N], v[N], w[N], u[N], tr[2];
+  // ---------------- X: b_x -> S1, c_x -> S3, x-face jumps
+  {
+    const TC GL = gco(0), GH = gco(1);
+    face_phase<N, 0, BX, BY, BZ, FS, TC, TIN, false, OFF32>(m, T, x, own, e, c, o, Nd, t, t1, t2, F, Fe, K, GL, GH,
+                                                            TC(0), b, u, tr);
+    lds_put<N, 0>(S1, t1, t2, b);
+    cd_line<N, TC>(T, u, w);
+#pragma unroll
+    for (int i = 0; i < N; ++i) w[i] *= K2;
+    w[N - 1] += K * u[N - 1] - TC(2) * GH * tr[1];
+    w[0] -= K * u[0] - TC(2) * GL * tr[0];
+    lds_put<N, 0>(S3, t1, t2, w);
+    P[0 * NN + t] = GL * (u[0] - tr[0]);      // jump at the lower x-face, (y, z) = (t1, t2)
+    P[1 * NN + t] = GH * (tr[1] - u[N - 1]);  // upper x-face
+  }
+  __syncthreads();
+  // ---------------- Y: b_y -> S2, S1 <- M_y S1 + G_xy P_xy, c_y -> S4
+  {
+    const TC GL = gco(2), GH = gco(3);
+    face_phase<N, 1, BX, BY, BZ, FS, TC, TIN, false, OFF32>(m, T, x, own, e, c, o, Nd, t, t1, t2, F, Fe, K, GL, GH,
+                                                            TC(0), b, u, tr);
+    lds_get<N, 1>(S1, t1, t2, v);
+    mass_line<N, TC, false>(T, v, w);
+    const TC Xlo = K * u[0] - TC(2) * GL * tr[0], Xhi = K * u[N - 1] - TC(2) * GH * tr[1];
+    const TC jlo = GL * (u[0] - tr[0]), jhi = GH * (tr[1] - u[N - 1]);
+    P[2 * NN + t] = jlo;  // y-face jumps and rows at (x, z) = (t1, t2)
+    P[3 * NN + t] = jhi;
+    P[4 * NN + t] = Xlo;
+    P[5 * NN + t] = Xhi;
+    TC cy[N], pxy[N];
+    cd_line<N, TC>(T, u, cy);
+#pragma unroll
+    for (int i = 0; i < N; ++i) cy[i] *= K2;
+    cy[N - 1] += Xhi;
+    cy[0] -= Xlo;
+    lds_get<N, 1>(S3, t1, t2, v);
+    cd_line<N, TC>(T, v, pxy);
+    __syncthreads();  // the y-face rows are published; the face scalars in S2 have been read
+    {  // y-face rows contracted along x, at x = t1
+      TC sh = TC(0), sl = TC(0);
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+        const TC cj = sC[t1 * N + j];
+        sh += cj * P[5 * NN + j + N * t2];
+        sl += cj * P[4 * NN + j + N * t2];
+      }
+      pxy[N - 1] += sh;
+      pxy[0] -= sl;
+    }
+    if (t1 == N - 1) {  // the edges of the (x, y) plane
+      pxy[N - 1] += P[1 * NN + (N - 1) + N * t2] + jhi;
+      pxy[0] += jlo - P[1 * NN + N * t2];
+    } else if (t1 == 0) {
+      pxy[N - 1] += P[0 * NN + (N - 1) + N * t2] - jhi;
+      pxy[0] -= P[0 * NN + N * t2] + jlo;
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i) w[i] += gxy * pxy[i];
+    lds_put<N, 1>(S2, t1, t2, b);
+    lds_put<N, 1>(S1, t1, t2, w);
+    lds_put<N, 1>(S4, t1, t2, cy);
+  }
+  __syncthreads();
+  // ---------------- X2: S1 += M_x S2
+  {
+    lds_get<N, 0>(S2, t1, t2, v);
+    lds_get<N, 0>(S1, t1, t2, w);
+    mass_line<N, TC, false>(T, v, b);
+#pragma unroll
+    for (int i = 0; i < N; ++i) w[i] += b[i];
+    lds_put<N, 0>(S1, t1, t2, w);
+  }
+  __syncthreads();
+  // ---------------- Z: b_z -> S2, r = M_z S1, P_xz -> S3, P_yz -> S4
+  TC r[N];
+  {
+    const TC GL = gco(4), GH = gco(5);
+    const TC cr = m.R ? m.R[e] * m.vol : TC(0);
+    face_phase<N, 2, BX, BY, BZ, FS, TC, TIN, false, OFF32>(m, T, x, own, e, c, o, Nd, t, t1, t2, F, Fe, K, GL, GH,
+                                                            cr, b, u, tr);
+    lds_get<N, 2>(S1, t1, t2, v);
+    mass_line<N, TC, false>(T, v, r);
+    const TC jlo = GL * (u[0] - tr[0]), jhi = GH * (tr[1] - u[N - 1]);
+    P[6 * NN + t] = K * u[0] - TC(2) * GL * tr[0];  // z-face rows at (x, y) = (t1, t2)
+    P[7 * NN + t] = K * u[N - 1] - TC(2) * GH * tr[1];
+    TC pxz[N], pyz[N];
+    lds_get<N, 2>(S3, t1, t2, v);
+    cd_line<N, TC>(T, v, pxz);
+    lds_get<N, 2>(S4, t1, t2, v);
+    cd_line<N, TC>(T, v, pyz);
+    __syncthreads();  // the z-face rows are published; the face scalars in S2 have been read
+    {  // z-face rows contracted along x (at x = t1) and along y (at y = t2)
+      TC ah = TC(0), al = TC(0), bh = TC(0), bl = TC(0);
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+        const TC cx = sC[t1 * N + j], cy = sC[t2 * N + j];
+        ah += cx * P[7 * NN + j + N * t2];
+        al += cx * P[6 * NN + j + N * t2];
+        bh += cy * P[7 * NN + t1 + N * j];
+        bl += cy * P[6 * NN + t1 + N * j];
+      }
+      pxz[N - 1] += ah;
+      pxz[0] -= al;
+      pyz[N - 1] += bh;
+      pyz[0] -= bl;
+    }
+    if (t1 == N - 1) {  // the edges of the (x, z) plane: x-face jumps at (y, z) = (t2, 0 / n-1)
+      pxz[N - 1] += P[1 * NN + t2 + N * (N - 1)] + jhi;
+      pxz[0] += jlo - P[1 * NN + t2];
+    } else if (t1 == 0) {
+      pxz[N - 1] += P[0 * NN + t2 + N * (N - 1)] - jhi;
+      pxz[0] -= P[0 * NN + t2] + jlo;
+    }
+    if (t2 == N - 1) {  // the edges of the (y, z) plane: y-face jumps at (x, z) = (t1, 0 / n-1)
+      pyz[N - 1] += P[3 * NN + t1 + N * (N - 1)] + jhi;
+      pyz[0] += jlo - P[3 * NN + t1];
+    } else if (t2 == 0) {
+      pyz[N - 1] += P[2 * NN + t1 + N * (N - 1)] - jhi;
+      pyz[0] -= P[2 * NN + t1] + jlo;
+    }
+    lds_put<N, 2>(S2, t1, t2, b);
+    lds_put<N, 2>(S3, t1, t2, pxz);
+    lds_put<N, 2>(S4, t1, t2, pyz);
+  }
+  __syncthreads();
+  // ---------------- X3: S2 <- M_x S2 + G_xz S3, S4 <- G_yz M_x S4
+  {
+    lds_get<N, 0>(S2, t1, t2, v);
+    mass_line<N, TC, false>(T, v, w);
+    lds_get<N, 0>(S3, t1, t2, v);
+#pragma unroll
+    for (int i = 0; i < N; ++i) w[i] += gxz * v[i];
+    lds_put<N, 0>(S2, t1, t2, w);
+    lds_get<N, 0>(S4, t1, t2, v);
+    mass_line<N, TC, false>(T, v, w);
+#pragma unroll
+    for (int i = 0; i < N; ++i) w[i] *= gyz;
+    lds_put<N, 0>(S4, t1, t2, w);
+  }
+  __syncthreads();
+  // ---------------- Y3: S2 <- M_y S2
+  {
+    lds_get<N, 1>(S2, t1, t2, v);
+    mass_line<N, TC, false>(T, v, w);
+    lds_put<N, 1>(S2, t1, t2, w);
+  }
+  __syncthreads();
+  // ---------------- Z2: y = r + S2 + S4
+  double part = 0.0;
+  lds_get<N, 2>(S2, t1, t2, v);
+  lds_get<N, 2>(S4, t1, t2, w);
+  if (act) {
+    const uint32_t yb = ((uint32_t)e * (uint32_t)N3 + (uint32_t)lidx<N, 2>(t1, t2, 0)) * (uint32_t)sizeof(TOUT);
+    TOUT* py = y + e * N3;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      const TOUT yv = (TOUT)(r[i] + v[i] + w[i]);
+      TOUT* dst = OFF32 ? (TOUT*)((char*)y + (yb + (uint32_t)(lidx<N, 2>(0, 0, i) * sizeof(TOUT))))
+                        : &py[lidx<N, 2>(t1, t2, i)];
+      __builtin_nontemporal_store(yv, dst);
+      if (DOT) part += (double)u[i] * (double)yv;
+    }
+  }
+  if (DOT) {
+    const double mine[1] = {block_sum<BLOCK>(part, red)};
+    store_partials<1>(mine, partials, blockIdx.x);
+  }
+}
+
+// ---------------------------------------------------------------- launchers
+template <int N, typename TIN, typename TOUT, typename TC, bool DOT>
+static hipError_t run_ppd(const MeshArgs<TC>& m, const void* x, void* y, double* partials, CgState* st, int par,
+                          const int* skip, hipStream_t s) {
+  const int64_t nb = affine_tiles(N, m.nx, m.ny, m.nz);
+  const double nd = (double)m.E * N * N * N;
+  const bool off32 = nd * (double)(sizeof(TIN) > sizeof(TOUT) ? sizeof(TIN) : sizeof(TOUT)) < 4294967296.0 &&
+                     6.0 * (double)m.E * sizeof(TC) < 4294967296.0;
+  if (off32)
+    hipLaunchKernelGGL((k_apply_ppd<N, TIN, TOUT, TC, DOT, true>), dim3((unsigned)nb), dim3(apply_block(N)), 0, s, m,
+                       (const TIN*)x, (TOUT*)y, partials, skip);
+  else
+    hipLaunchKernelGGL((k_apply_ppd<N, TIN, TOUT, TC, DOT, false>), dim3((unsigned)nb), dim3(apply_block(N)), 0, s, m,
+                       (const TIN*)x, (TOUT*)y, partials, skip);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess || !DOT || st == nullptr) return e;
+  return launch_finish_dot(partials, nb, st, par, s);
+}
+
+template <int N, bool DOT>
+static hipError_t run_ppd_prec(int prec, const MeshArgs<double>& m64, const MeshArgs<float>& m32, const void* x,
+                               void* y, double* partials, CgState* st, int par, const int* skip, hipStream_t s) {
+  switch (prec) {
+    case 0: return run_ppd<N, double, double, double, DOT>(m64, x, y, partials, st, par, skip, s);
+    case 1: return run_ppd<N, float, float, float, DOT>(m32, x, y, partials, st, par, skip, s);
+    case 2: return run_ppd<N, uint16_t, float, float, DOT>(m32, x, y, partials, st, par, skip, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int N>
+static hipError_t run_ppd_n(int prec, int dot, const MeshArgs<double>& m64, const MeshArgs<float>& m32,
+                            const void* x, void* y, double* partials, CgState* st, int par, const int* skip,
+                            hipStream_t s) {
+  return dot ? run_ppd_prec<N, true>(prec, m64, m32, x, y, partials, st, par, skip, s)
+             : run_ppd_prec<N, false>(prec, m64, m32, x, y, partials, st, par, skip, s);
+}
+
+hipError_t launch_apply_ppd(int n, int prec, int dot, const MeshArgs<double>& m64, const MeshArgs<float>& m32,
+                            const void* x, void* y, double* partials, CgState* st, int par, const int* skip,
+                            hipStream_t s) {
+  switch (n) {
+    case 2: return run_ppd_n<2>(prec, dot, m64, m32, x, y, partials, st, par, skip, s);
+    case 3: return run_ppd_n<3>(prec, dot, m64, m32, x, y, partials, st, par, skip, s);
+    case 4: return run_ppd_n<4>(prec, dot, m64, m32, x, y, partials, st, par, skip, s);
+    case 5: return run_ppd_n<5>(prec, dot, m64, m32, x, y, partials, st, par, skip, s);
+    case 6: return run_ppd_n<6>(prec, dot, m64, m32, x, y, partials, st, par, skip, s);
+    case 7: return run_ppd_n<7>(prec, dot, m64, m32, x, y, partials, st, par, skip, s);
+    case 8: return run_ppd_n<8>(prec, dot, m64, m32, x, y, partials, st, par, skip, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace dg

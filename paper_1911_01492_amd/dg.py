@@ -32,7 +32,8 @@ _OUT_DTYPE = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.float32,
 #: every function declared in include/dg.h
 ABI_FUNCTIONS = ["dg_query_workspace", "dg_setup", "dg_set_theta", "dg_set_reaction", "dg_apply", "dg_apply_transpose", "dg_apply_multi",
                  "dg_dA_dtheta", "dg_dA_dtheta_noalloc", "dg_diagonal", "dg_quadrature_points", "dg_load_vector", "dg_cg_solve",
-                 "dg_num_dofs", "dg_num_elements", "dg_nodes_per_dir", "dg_destroy", "dg_last_error"]
+                 "dg_num_dofs", "dg_num_elements", "dg_nodes_per_dir", "dg_apply_kernel", "dg_destroy",
+                 "dg_last_error"]
 
 
 class DGError(RuntimeError):
@@ -96,6 +97,7 @@ def lib() -> ctypes.CDLL:
     L.dg_num_elements.argtypes = [vp]
     L.dg_num_elements.restype = ctypes.c_int64
     L.dg_nodes_per_dir.argtypes = [vp]
+    L.dg_apply_kernel.argtypes = [vp]
     L.dg_destroy.argtypes = [vp]
     L.dg_destroy.restype = None
     L.dg_last_error.argtypes = [vp]
@@ -160,6 +162,13 @@ class DGOperator:
         if rc != DG_OK:
             raise DGError(rc, L.dg_last_error(None).decode())
         self._h = h
+
+    KERNELS = {0: "affine", 1: "trilinear", 2: "parallelepiped"}
+
+    @property
+    def kernel(self) -> str:
+        """The apply kernel chosen at setup: "affine", "trilinear" or "parallelepiped"."""
+        return self.KERNELS[self._check(lib().dg_apply_kernel(self._h))]
 
     # -------------------------------------------------------------- helpers
     def _check(self, rc: int):

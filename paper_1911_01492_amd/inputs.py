@@ -54,6 +54,16 @@ def sheared_vertices(nx: int, ny: int, nz: int, s: float = 0.25) -> np.ndarray:
     return V
 
 
+def layered_shear_vertices(nx: int, ny: int, nz: int, s: float = 0.3, seed: int = 23) -> np.ndarray:
+    """Vertices of the uniform grid sheared along x by a different U(-s, s)
+    slope in every layer of elements along y: every element is a
+    parallelepiped, but not all the same one."""
+    V = uniform_vertices(nx, ny, nz).reshape(nz + 1, ny + 1, nx + 1, 3).copy()
+    slope = rng(seed).uniform(-s, s, ny)
+    V[..., 0] += (np.concatenate([[0.0], np.cumsum(slope)]) / ny)[None, :, None]
+    return V.reshape(-1, 3)
+
+
 def uniform_vector(n: int, seed: int = S_X) -> np.ndarray:
     """x ~ U(-1, 1) i.i.d."""
     return rng(seed).uniform(-1.0, 1.0, n)

@@ -16,7 +16,7 @@ SAN = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined
 
 @pytest.mark.skipif(not os.path.exists(HIPCC), reason="hipcc not available")
 @pytest.mark.skipif(not all(os.path.exists(os.path.join(BUILD, f + ".o"))
-                            for f in ("dg_affine", "dg_mfma", "dg_trilinear", "dg_geom")),
+                            for f in ("dg_affine", "dg_mfma", "dg_ppd", "dg_trilinear", "dg_geom")),
                     reason="library objects not built")
 def test_host_code_under_asan_ubsan(tmp_path):
     objs = []
@@ -34,7 +34,7 @@ def test_host_code_under_asan_ubsan(tmp_path):
     exe = str(tmp_path / "drv")
     subprocess.run([HIPCC, "--offload-arch=gfx950", "-fsanitize=address", "-fsanitize=undefined",
                     "-fno-gpu-sanitize", drv] + objs +
-                   [os.path.join(BUILD, f + ".o") for f in ("dg_affine", "dg_mfma", "dg_trilinear", "dg_geom")] +
+                   [os.path.join(BUILD, f + ".o") for f in ("dg_affine", "dg_mfma", "dg_ppd", "dg_trilinear", "dg_geom")] +
                    ["-o", exe],
                    check=True, capture_output=True)
     # the HIP runtime's own allocations are not this library's: leak checking off
