@@ -38,16 +38,18 @@
 // four edges of the (a, b) plane.  The transpose is the same operator (the
 // form is symmetric).
 //
-// Phases (two more LDS tiles than the axis-parallel apply, S3 and S4, and
-// small per-element exchange rows):
-//   X : b_x -> S1; c_x = -2K C u + x-face rows -> S3; x-face jumps
-//   Y : b_y -> S2; S1 <- M_y S1 + G_xy P_xy (P_xy = C_y c_x + y-face rows along x
-//       + corners); c_y = -2K C u + y-face rows -> S4; y-face rows and jumps
-//   X2: S1 += M_x S2
-//   Z : b_z -> S2; r = M_z S1; S3 <- P_xz = C_z c_x + ...; S4 <- P_yz = C_z c_y + ...
-//   X3: S2 <- M_x S2 + G_xz S3; S4 <- G_yz M_x S4
+// Phases (one more LDS tile than the axis-parallel apply, S3, and small
+// per-element exchange rows; P_ab is symmetric in a and b, so each pair is
+// formed in the phase whose lines suit it):
+//   X : b_x -> S1; x-face rows X and jumps
+//   Y : b_y -> S2; S1 <- M_y S1; c_y = -2K C u + y-face rows -> S3; y-face jumps
+//   X2: S1 <- S1 + M_x S2 + G_xy P_xy,  P_xy = C_x c_y + C_y (x-face rows) + corners
+//   Z : b_z -> S2; r = M_z S1; S1 <- P_yz = C_z c_y + C_y (z-face rows) + corners;
+//       c_z = -2K C u + z-face rows -> S3
+//   X3: S2 <- M_x S2 + G_xz P_xz,  P_xz = C_x c_z + C_z (x-face rows) + corners;
+//       S1 <- G_yz M_x S1
 //   Y3: S2 <- M_y S2
-//   Z2: y = r + S2 + S4
+//   Z2: y = r + S2 + S1
 // so that y = M_z (M_y b_x + M_x b_y + G_xy P_xy) + M_y (M_x b_z + G_xz P_xz)
 //         + G_yz M_x P_yz.
 #include "dg_internal.hpp"
@@ -84,12 +86,16 @@ __global__ __launch_bounds__(apply_block(N)) void k_apply_ppd(MeshArgs<TC> m, co
   constexpr int FS = F_IN_S2 ? PE : 4 * NN;
   constexpr int BLOCK = apply_block(N);
   static_assert(TE * NN <= BLOCK && BLOCK <= kBlock, "brick too large");
+  // an element's threads lie in one wavefront (ELEM), and so does each x-row
+  // of the brick (XROW): exchanges inside an element then need only
+  // wavefront-level synchronisation (every exchange outside the face phases is)
+  constexpr bool ELEM = 64 % NN == 0, XROW = 64 % (BX * NN) == 0;
   // padding lanes repeat the work of the brick's last element lane for lane
   // (same values to the same LDS words, in the same wavefront)
   static_assert(TE * NN == BLOCK || BLOCK - (TE - 1) * NN <= 64, "padding lanes and their twins share a wavefront");
-  __shared__ TC sS1[TE * PE], sS2[TE * PE], sS3[TE * PE], sS4[TE * PE];
+  __shared__ TC sS1[TE * PE], sS2[TE * PE], sS3[TE * PE];
   __shared__ TC sFx[F_IN_S2 ? 1 : TE * 4 * NN];
-  // per element: x-face jumps (lo, hi), y-face jumps, y-face rows X, z-face rows X
+  // per element, lower and upper side each: x-face rows X, y-face jumps, z-face rows X, z-face jumps
   __shared__ TC sP[TE * 8 * NN];
   __shared__ TC sC[NN];  // C, row-major, for lane-indexed rows
   __shared__ double red[BLOCK / 64];
@@ -112,7 +118,6 @@ __global__ __launch_bounds__(apply_block(N)) void k_apply_ppd(MeshArgs<TC> m, co
   TC* S1 = sS1 + el * PE;
   TC* S2 = sS2 + el * PE;
   TC* S3 = sS3 + el * PE;
-  TC* S4 = sS4 + el * PE;
   TC* Fe = F + el * FS;
   TC* P = sP + el * 8 * NN;
   if (tid < NN) sC[tid] = T.Cd[(tid / N) * kMaxN + tid % N];
@@ -121,80 +126,71 @@ __global__ __launch_bounds__(apply_block(N)) void k_apply_ppd(MeshArgs<TC> m, co
   auto gco = [&](int f) { return OFF32 ? m.G[(uint32_t)(6 * e + f)] : m.G[6 * e + f]; };
   const TC gxy = m.go[0], gxz = m.go[1], gyz = m.go[2];
   TC b[N], v[N], w[N], u[N], tr[2];
-  // ---------------- X: b_x -> S1, c_x -> S3, x-face jumps
+  TC jxl, jxh;  // this thread's x-face jumps at (y, z) = (t1, t2), used again in X2 and X3
+  // ---------------- X: b_x -> S1, x-face rows and jumps
   {
     const TC GL = gco(0), GH = gco(1);
     face_phase<N, 0, BX, BY, BZ, FS, TC, TIN, false, OFF32>(m, T, x, own, e, c, o, Nd, t, t1, t2, F, Fe, K, GL, GH,
                                                             TC(0), b, u, tr);
     lds_put<N, 0>(S1, t1, t2, b);
-    cd_line<N, TC>(T, u, w);
-#pragma unroll
-    for (int i = 0; i < N; ++i) w[i] *= K2;
-    w[N - 1] += K * u[N - 1] - TC(2) * GH * tr[1];
-    w[0] -= K * u[0] - TC(2) * GL * tr[0];
-    lds_put<N, 0>(S3, t1, t2, w);
-    P[0 * NN + t] = GL * (u[0] - tr[0]);      // jump at the lower x-face, (y, z) = (t1, t2)
-    P[1 * NN + t] = GH * (tr[1] - u[N - 1]);  // upper x-face
+    P[0 * NN + t] = K * u[0] - TC(2) * GL * tr[0];
+    P[1 * NN + t] = K * u[N - 1] - TC(2) * GH * tr[1];
+    jxl = GL * (u[0] - tr[0]);
+    jxh = GH * (tr[1] - u[N - 1]);
   }
-  __syncthreads();
-  // ---------------- Y: b_y -> S2, S1 <- M_y S1 + G_xy P_xy, c_y -> S4
+  lds_sync<XROW>();  // F (read by the x-neighbours) is rewritten by the next phase
+  // ---------------- Y: b_y -> S2, S1 <- M_y S1, c_y -> S3, y-face jumps
   {
     const TC GL = gco(2), GH = gco(3);
     face_phase<N, 1, BX, BY, BZ, FS, TC, TIN, false, OFF32>(m, T, x, own, e, c, o, Nd, t, t1, t2, F, Fe, K, GL, GH,
                                                             TC(0), b, u, tr);
     lds_get<N, 1>(S1, t1, t2, v);
     mass_line<N, TC, false>(T, v, w);
-    const TC Xlo = K * u[0] - TC(2) * GL * tr[0], Xhi = K * u[N - 1] - TC(2) * GH * tr[1];
-    const TC jlo = GL * (u[0] - tr[0]), jhi = GH * (tr[1] - u[N - 1]);
-    P[2 * NN + t] = jlo;  // y-face jumps and rows at (x, z) = (t1, t2)
-    P[3 * NN + t] = jhi;
-    P[4 * NN + t] = Xlo;
-    P[5 * NN + t] = Xhi;
-    TC cy[N], pxy[N];
-    cd_line<N, TC>(T, u, cy);
+    cd_line<N, TC>(T, u, v);
 #pragma unroll
-    for (int i = 0; i < N; ++i) cy[i] *= K2;
-    cy[N - 1] += Xhi;
-    cy[0] -= Xlo;
-    lds_get<N, 1>(S3, t1, t2, v);
-    cd_line<N, TC>(T, v, pxy);
-    __syncthreads();  // the y-face rows are published; the face scalars in S2 have been read
-    {  // y-face rows contracted along x, at x = t1
-      TC sh = TC(0), sl = TC(0);
-#pragma unroll
-      for (int j = 0; j < N; ++j) {
-        const TC cj = sC[t1 * N + j];
-        sh += cj * P[5 * NN + j + N * t2];
-        sl += cj * P[4 * NN + j + N * t2];
-      }
-      pxy[N - 1] += sh;
-      pxy[0] -= sl;
-    }
-    if (t1 == N - 1) {  // the edges of the (x, y) plane
-      pxy[N - 1] += P[1 * NN + (N - 1) + N * t2] + jhi;
-      pxy[0] += jlo - P[1 * NN + N * t2];
-    } else if (t1 == 0) {
-      pxy[N - 1] += P[0 * NN + (N - 1) + N * t2] - jhi;
-      pxy[0] -= P[0 * NN + N * t2] + jlo;
-    }
-#pragma unroll
-    for (int i = 0; i < N; ++i) w[i] += gxy * pxy[i];
+    for (int i = 0; i < N; ++i) v[i] *= K2;
+    v[N - 1] += K * u[N - 1] - TC(2) * GH * tr[1];  // the y-face rows ride on c_y
+    v[0] -= K * u[0] - TC(2) * GL * tr[0];
+    P[2 * NN + t] = GL * (u[0] - tr[0]);  // y-face jumps at (x, z) = (t1, t2)
+    P[3 * NN + t] = GH * (tr[1] - u[N - 1]);
+    if (F_IN_S2) __syncthreads();  // the face scalars in S2 have been read
     lds_put<N, 1>(S2, t1, t2, b);
     lds_put<N, 1>(S1, t1, t2, w);
-    lds_put<N, 1>(S4, t1, t2, cy);
+    lds_put<N, 1>(S3, t1, t2, v);
   }
-  __syncthreads();
-  // ---------------- X2: S1 += M_x S2
+  lds_sync<ELEM>();
+  // ---------------- X2: S1 <- S1 + M_x S2 + G_xy P_xy,  P_xy = C_x c_y + C_y (x-face rows) + corners
   {
     lds_get<N, 0>(S2, t1, t2, v);
     lds_get<N, 0>(S1, t1, t2, w);
     mass_line<N, TC, false>(T, v, b);
 #pragma unroll
     for (int i = 0; i < N; ++i) w[i] += b[i];
+    lds_get<N, 0>(S3, t1, t2, v);
+    TC p[N];
+    cd_line<N, TC>(T, v, p);
+    TC sh = TC(0), sl = TC(0);  // x-face rows contracted along y, at y = t1
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      const TC cj = sC[t1 * N + j];
+      sh += cj * P[1 * NN + j + N * t2];
+      sl += cj * P[0 * NN + j + N * t2];
+    }
+    p[N - 1] += sh;
+    p[0] -= sl;
+    if (t1 == N - 1) {  // edges of the (x, y) plane: own x-face jumps, y-face jumps at x = 0 / n-1
+      p[N - 1] += jxh + P[3 * NN + (N - 1) + N * t2];
+      p[0] += jxl - P[3 * NN + N * t2];
+    } else if (t1 == 0) {
+      p[N - 1] += P[2 * NN + (N - 1) + N * t2] - jxh;
+      p[0] -= jxl + P[2 * NN + N * t2];
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i) w[i] += gxy * p[i];
     lds_put<N, 0>(S1, t1, t2, w);
   }
-  __syncthreads();
-  // ---------------- Z: b_z -> S2, r = M_z S1, P_xz -> S3, P_yz -> S4
+  lds_sync<ELEM>();
+  // ---------------- Z: b_z -> S2, r = M_z S1, P_yz -> S1, c_z -> S3, z-face rows and jumps
   TC r[N];
   {
     const TC GL = gco(4), GH = gco(5);
@@ -203,75 +199,88 @@ __global__ __launch_bounds__(apply_block(N)) void k_apply_ppd(MeshArgs<TC> m, co
                                                             cr, b, u, tr);
     lds_get<N, 2>(S1, t1, t2, v);
     mass_line<N, TC, false>(T, v, r);
-    const TC jlo = GL * (u[0] - tr[0]), jhi = GH * (tr[1] - u[N - 1]);
-    P[6 * NN + t] = K * u[0] - TC(2) * GL * tr[0];  // z-face rows at (x, y) = (t1, t2)
-    P[7 * NN + t] = K * u[N - 1] - TC(2) * GH * tr[1];
-    TC pxz[N], pyz[N];
+    const TC Xlo = K * u[0] - TC(2) * GL * tr[0], Xhi = K * u[N - 1] - TC(2) * GH * tr[1];
+    const TC jzl = GL * (u[0] - tr[0]), jzh = GH * (tr[1] - u[N - 1]);
+    P[4 * NN + t] = Xlo;  // z-face rows and jumps at (x, y) = (t1, t2)
+    P[5 * NN + t] = Xhi;
+    P[6 * NN + t] = jzl;
+    P[7 * NN + t] = jzh;
+    TC p[N];
     lds_get<N, 2>(S3, t1, t2, v);
-    cd_line<N, TC>(T, v, pxz);
-    lds_get<N, 2>(S4, t1, t2, v);
-    cd_line<N, TC>(T, v, pyz);
-    __syncthreads();  // the z-face rows are published; the face scalars in S2 have been read
-    {  // z-face rows contracted along x (at x = t1) and along y (at y = t2)
-      TC ah = TC(0), al = TC(0), bh = TC(0), bl = TC(0);
+    cd_line<N, TC>(T, v, p);  // P_yz = C_z c_y + ...
+    cd_line<N, TC>(T, u, w);  // c_z
 #pragma unroll
-      for (int j = 0; j < N; ++j) {
-        const TC cx = sC[t1 * N + j], cy = sC[t2 * N + j];
-        ah += cx * P[7 * NN + j + N * t2];
-        al += cx * P[6 * NN + j + N * t2];
-        bh += cy * P[7 * NN + t1 + N * j];
-        bl += cy * P[6 * NN + t1 + N * j];
-      }
-      pxz[N - 1] += ah;
-      pxz[0] -= al;
-      pyz[N - 1] += bh;
-      pyz[0] -= bl;
+    for (int i = 0; i < N; ++i) w[i] *= K2;
+    w[N - 1] += Xhi;
+    w[0] -= Xlo;
+    if (F_IN_S2) __syncthreads();  // the face scalars in S2 have been read; the z-face rows are published
+    else lds_sync<ELEM>();
+    TC sh = TC(0), sl = TC(0);  // z-face rows contracted along y, at y = t2
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      const TC cj = sC[t2 * N + j];
+      sh += cj * P[5 * NN + t1 + N * j];
+      sl += cj * P[4 * NN + t1 + N * j];
     }
-    if (t1 == N - 1) {  // the edges of the (x, z) plane: x-face jumps at (y, z) = (t2, 0 / n-1)
-      pxz[N - 1] += P[1 * NN + t2 + N * (N - 1)] + jhi;
-      pxz[0] += jlo - P[1 * NN + t2];
-    } else if (t1 == 0) {
-      pxz[N - 1] += P[0 * NN + t2 + N * (N - 1)] - jhi;
-      pxz[0] -= P[0 * NN + t2] + jlo;
-    }
-    if (t2 == N - 1) {  // the edges of the (y, z) plane: y-face jumps at (x, z) = (t1, 0 / n-1)
-      pyz[N - 1] += P[3 * NN + t1 + N * (N - 1)] + jhi;
-      pyz[0] += jlo - P[3 * NN + t1];
+    p[N - 1] += sh;
+    p[0] -= sl;
+    if (t2 == N - 1) {  // edges of the (y, z) plane: y-face jumps at z = 0 / n-1, own z-face jumps
+      p[N - 1] += P[3 * NN + t1 + N * (N - 1)] + jzh;
+      p[0] += jzl - P[3 * NN + t1];
     } else if (t2 == 0) {
-      pyz[N - 1] += P[2 * NN + t1 + N * (N - 1)] - jhi;
-      pyz[0] -= P[2 * NN + t1] + jlo;
+      p[N - 1] += P[2 * NN + t1 + N * (N - 1)] - jzh;
+      p[0] -= P[2 * NN + t1] + jzl;
     }
     lds_put<N, 2>(S2, t1, t2, b);
-    lds_put<N, 2>(S3, t1, t2, pxz);
-    lds_put<N, 2>(S4, t1, t2, pyz);
+    lds_put<N, 2>(S1, t1, t2, p);  // the thread's own z-lines of S1 and S3 were read above
+    lds_put<N, 2>(S3, t1, t2, w);
   }
-  __syncthreads();
-  // ---------------- X3: S2 <- M_x S2 + G_xz S3, S4 <- G_yz M_x S4
+  lds_sync<ELEM>();
+  // ---------------- X3: S2 <- M_x S2 + G_xz P_xz (P_xz = C_x c_z + C_z (x-face rows) + corners),
+  //                      S1 <- G_yz M_x S1
   {
     lds_get<N, 0>(S2, t1, t2, v);
     mass_line<N, TC, false>(T, v, w);
     lds_get<N, 0>(S3, t1, t2, v);
+    TC p[N];
+    cd_line<N, TC>(T, v, p);
+    TC sh = TC(0), sl = TC(0);  // x-face rows contracted along z, at z = t2
 #pragma unroll
-    for (int i = 0; i < N; ++i) w[i] += gxz * v[i];
+    for (int j = 0; j < N; ++j) {
+      const TC cj = sC[t2 * N + j];
+      sh += cj * P[1 * NN + t1 + N * j];
+      sl += cj * P[0 * NN + t1 + N * j];
+    }
+    p[N - 1] += sh;
+    p[0] -= sl;
+    if (t2 == N - 1) {  // edges of the (x, z) plane: own x-face jumps, z-face jumps at x = 0 / n-1
+      p[N - 1] += jxh + P[7 * NN + (N - 1) + N * t1];
+      p[0] += jxl - P[7 * NN + N * t1];
+    } else if (t2 == 0) {
+      p[N - 1] += P[6 * NN + (N - 1) + N * t1] - jxh;
+      p[0] -= jxl + P[6 * NN + N * t1];
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i) w[i] += gxz * p[i];
     lds_put<N, 0>(S2, t1, t2, w);
-    lds_get<N, 0>(S4, t1, t2, v);
+    lds_get<N, 0>(S1, t1, t2, v);
     mass_line<N, TC, false>(T, v, w);
 #pragma unroll
     for (int i = 0; i < N; ++i) w[i] *= gyz;
-    lds_put<N, 0>(S4, t1, t2, w);
+    lds_put<N, 0>(S1, t1, t2, w);
   }
-  __syncthreads();
+  lds_sync<ELEM>();
   // ---------------- Y3: S2 <- M_y S2
   {
     lds_get<N, 1>(S2, t1, t2, v);
     mass_line<N, TC, false>(T, v, w);
     lds_put<N, 1>(S2, t1, t2, w);
   }
-  __syncthreads();
-  // ---------------- Z2: y = r + S2 + S4
+  lds_sync<ELEM>();
+  // ---------------- Z2: y = r + S2 + S1
   double part = 0.0;
   lds_get<N, 2>(S2, t1, t2, v);
-  lds_get<N, 2>(S4, t1, t2, w);
+  lds_get<N, 2>(S1, t1, t2, w);
   if (act) {
     const uint32_t yb = ((uint32_t)e * (uint32_t)N3 + (uint32_t)lidx<N, 2>(t1, t2, 0)) * (uint32_t)sizeof(TOUT);
     TOUT* py = y + e * N3;
