@@ -59,10 +59,11 @@
 
 namespace dg {
 
-// out = C a along the line (C centro-antisymmetric: even-odd halves from n = 5)
+// out = C a along the line (C centro-antisymmetric: even-odd halves from n = 4,
+// where they cost no more operations and hold half the table in scalar registers)
 template <int N, typename TC>
 __device__ __forceinline__ void cd_line(const Tables<TC>& T, const TC (&a)[N], TC (&out)[N]) {
-  if constexpr (N >= 5) {
+  if constexpr (N >= 4) {
     contract_eo<N, TC, -1>(T.eC, a, out);
   } else {
 #pragma unroll
@@ -101,7 +102,16 @@ __global__ __launch_bounds__(apply_block(N)) void k_apply_ppd(MeshArgs<TC> m, co
   __shared__ double red[BLOCK / 64];
   if (skip != nullptr && *skip) return;
   TC* F = F_IN_S2 ? sS2 : sFx;
-  const Tables<TC>& T = *m.tab;
+  // The 1D tables are read through the scalar cache.  Each phase re-derives
+  // their address, which keeps the compiler from holding every table in
+  // scalar registers across the whole kernel (at n >= 4 they do not fit and
+  // spill into vector-register lanes): a phase loads the tables it uses.
+  auto tabs = [&]() -> const Tables<TC>& {
+    uint64_t a = (uint64_t)m.tab;
+    asm volatile("" : "+s"(a));
+    typedef const __attribute__((address_space(4))) Tables<TC>* ConstTab;
+    return *(const Tables<TC>*)(ConstTab)a;
+  };
   const int tb = (int)xcd_remap(blockIdx.x, gridDim.x);
   int o[3];
   brick_origin<BX, BY, BZ>(tb, m.nx, m.ny, m.nz, o);
@@ -120,7 +130,7 @@ __global__ __launch_bounds__(apply_block(N)) void k_apply_ppd(MeshArgs<TC> m, co
   TC* S3 = sS3 + el * PE;
   TC* Fe = F + el * FS;
   TC* P = sP + el * 8 * NN;
-  if (tid < NN) sC[tid] = T.Cd[(tid / N) * kMaxN + tid % N];
+  if (tid < NN) sC[tid] = tabs().Cd[(tid / N) * kMaxN + tid % N];
   const int64_t e = c[0] + (int64_t)m.nx * (c[1] + (int64_t)m.ny * c[2]);
   const TC K = m.K[e], K2 = TC(-2) * K;
   auto gco = [&](int f) { return OFF32 ? m.G[(uint32_t)(6 * e + f)] : m.G[6 * e + f]; };
@@ -129,6 +139,7 @@ __global__ __launch_bounds__(apply_block(N)) void k_apply_ppd(MeshArgs<TC> m, co
   TC jxl, jxh;  // this thread's x-face jumps at (y, z) = (t1, t2), used again in X2 and X3
   // ---------------- X: b_x -> S1, x-face rows and jumps
   {
+    const Tables<TC>& T = tabs();
     const TC GL = gco(0), GH = gco(1);
     face_phase<N, 0, BX, BY, BZ, FS, TC, TIN, false, OFF32>(m, T, x, own, e, c, o, Nd, t, t1, t2, F, Fe, K, GL, GH,
                                                             TC(0), b, u, tr);
@@ -141,6 +152,7 @@ __global__ __launch_bounds__(apply_block(N)) void k_apply_ppd(MeshArgs<TC> m, co
   lds_sync<XROW>();  // F (read by the x-neighbours) is rewritten by the next phase
   // ---------------- Y: b_y -> S2, S1 <- M_y S1, c_y -> S3, y-face jumps
   {
+    const Tables<TC>& T = tabs();
     const TC GL = gco(2), GH = gco(3);
     face_phase<N, 1, BX, BY, BZ, FS, TC, TIN, false, OFF32>(m, T, x, own, e, c, o, Nd, t, t1, t2, F, Fe, K, GL, GH,
                                                             TC(0), b, u, tr);
@@ -161,6 +173,7 @@ __global__ __launch_bounds__(apply_block(N)) void k_apply_ppd(MeshArgs<TC> m, co
   lds_sync<ELEM>();
   // ---------------- X2: S1 <- S1 + M_x S2 + G_xy P_xy,  P_xy = C_x c_y + C_y (x-face rows) + corners
   {
+    const Tables<TC>& T = tabs();
     lds_get<N, 0>(S2, t1, t2, v);
     lds_get<N, 0>(S1, t1, t2, w);
     mass_line<N, TC, false>(T, v, b);
@@ -193,6 +206,7 @@ __global__ __launch_bounds__(apply_block(N)) void k_apply_ppd(MeshArgs<TC> m, co
   // ---------------- Z: b_z -> S2, r = M_z S1, P_yz -> S1, c_z -> S3, z-face rows and jumps
   TC r[N];
   {
+    const Tables<TC>& T = tabs();
     const TC GL = gco(4), GH = gco(5);
     const TC cr = m.R ? m.R[e] * m.vol : TC(0);
     face_phase<N, 2, BX, BY, BZ, FS, TC, TIN, false, OFF32>(m, T, x, own, e, c, o, Nd, t, t1, t2, F, Fe, K, GL, GH,
@@ -239,6 +253,7 @@ __global__ __launch_bounds__(apply_block(N)) void k_apply_ppd(MeshArgs<TC> m, co
   // ---------------- X3: S2 <- M_x S2 + G_xz P_xz (P_xz = C_x c_z + C_z (x-face rows) + corners),
   //                      S1 <- G_yz M_x S1
   {
+    const Tables<TC>& T = tabs();
     lds_get<N, 0>(S2, t1, t2, v);
     mass_line<N, TC, false>(T, v, w);
     lds_get<N, 0>(S3, t1, t2, v);
@@ -272,6 +287,7 @@ __global__ __launch_bounds__(apply_block(N)) void k_apply_ppd(MeshArgs<TC> m, co
   lds_sync<ELEM>();
   // ---------------- Y3: S2 <- M_y S2
   {
+    const Tables<TC>& T = tabs();
     lds_get<N, 1>(S2, t1, t2, v);
     mass_line<N, TC, false>(T, v, w);
     lds_put<N, 1>(S2, t1, t2, w);
