@@ -141,8 +141,8 @@ def cold_apply(op, x, prec, reps, torch):
 
 
 HEADLINE = "mixed_q4_64"
-KERNEL_SOURCES = ("paper_1911_01492_amd/csrc/dg_affine.hip", "paper_1911_01492_amd/csrc/dg_lines.hpp",
-                  "paper_1911_01492_amd/csrc/dg_internal.hpp")
+KERNEL_SOURCES = ("paper_1911_01492_amd/csrc/dg_affine.hip", "paper_1911_01492_amd/csrc/dg_faces.hpp",
+                  "paper_1911_01492_amd/csrc/dg_lines.hpp", "paper_1911_01492_amd/csrc/dg_internal.hpp")
 TRAFFIC_PROFILE = "profiles/k_apply_affine_q4_64_f64.txt"
 
 
@@ -215,6 +215,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", default="", help="comma list of extras to run (default: all)")
+    ap.add_argument("--paper-degrees", default="1,2,3,4,5,6,7",
+                    help="comma list of the degrees p of the operator-throughput table")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (reference for the HBM byte counters)")
     args = ap.parse_args()
@@ -462,14 +464,16 @@ def main():
     if want("paper_table"):
         # full operator application, diffusion-reaction with coefficients per cell:
         # problem A on axis-parallel cells (affine kernel), problem B on affine
-        # (here: sheared parallelepiped) cells (trilinear kernel); DOF/s of the
-        # paper's 32-core Xeon run quoted next to each degree as context only
+        # cells (the grid sheared by one affine map: parallelepiped kernel); DOF/s
+        # of the paper's 32-core Xeon run quoted next to each degree as context only
         paper_A = {1: 170158953.8, 2: 392974786.3, 3: 537750268.0, 4: 595014243.3, 5: 617156313.6,
                    6: 598962766.1, 7: 570054393.2}
         paper_B = {1: 118979587.7, 2: 252483269.1, 3: 330453992.0, 4: 388214296.4, 5: 403296404.4,
                    6: 406075144.9, 7: 398006289.99}
         rows = []
-        for p in range(1, 8):
+        for p in sorted({int(q) for q in args.paper_degrees.split(",")}):
+            if not 1 <= p <= 7:
+                raise SystemExit(f"--paper-degrees: p = {p} outside 1..7")
             Np = max(4, int(round((4.0e6) ** (1 / 3) / (p + 1))))
             E = Np ** 3
             th = dev(I.theta(E))
@@ -481,9 +485,11 @@ def main():
                 xp = dev(I.uniform_vector(opp.ndof))
                 tt, yy = time_apply(opp, xp, "f64", 20, 5, torch)
                 ent[f"gdofs_{name}"] = round(opp.ndof * 20 / tt / 1e9, 3)
+                ent[f"kernel_{name}"] = opp.kernel
                 ent[f"paper_gdofs_{name}"] = round((paper_A if name == "A" else paper_B)[p] / 1e9, 4)
                 del opp, xp, yy
             ent["ndof"] = E * (p + 1) ** 3
+            ent["A_over_B"] = round(ent["gdofs_A"] / ent["gdofs_B"], 3)
             rows.append(ent)
             log(f"paper table p={p}: {ent}")
         extras["paper_table_fp64"] = rows
