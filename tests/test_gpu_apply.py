@@ -304,16 +304,19 @@ def test_repeatable_with_changing_inputs():
     banner("repeatability with changing inputs")
     # trilinear k = 2, 4, 5, 6: an element's n^2 threads span two wavefronts,
     # so the face phases depend on workgroup barriers; perturbed meshes take
-    # the general kernel, sheared ones the constant-metric (parallelepiped) one
+    # the general trilinear kernel, layered shears its constant-metric
+    # variant, sheared meshes (one affine map) the parallelepiped kernel
     cases = [(32, 3, None), (12, 1, None), (6, 7, None), (8, 3, I.perturbed_vertices(8, 0.1, seed=3)),
              (4, 7, I.perturbed_vertices(4, 0.1, seed=4)),
              (9, 2, I.perturbed_vertices(9, 0.1, seed=5)), (7, 4, I.sheared_vertices(7, 7, 7)),
              (6, 5, I.perturbed_vertices(6, 0.1, seed=6)), (5, 6, I.sheared_vertices(5, 5, 5)),
-             (5, 4, I.perturbed_vertices(5, 0.1, seed=8)), (6, 2, I.sheared_vertices(6, 6, 6))]
+             (5, 4, I.perturbed_vertices(5, 0.1, seed=8)), (6, 2, I.sheared_vertices(6, 6, 6)),
+             (9, 3, I.sheared_vertices(9, 9, 9)), (6, 4, I.layered_shear_vertices(6, 6, 6)),
+             (5, 5, I.layered_shear_vertices(5, 5, 5)), (7, 2, I.layered_shear_vertices(7, 7, 7))]
     for N, k, verts in cases:
-        print(f"repeatability N={N} k={k} {'affine' if verts is None else 'trilinear'}", flush=True)
         op = DGOperator(N, N, N, k, "dirichlet", theta=dev(I.theta(N ** 3)),
                         vertices=None if verts is None else dev(verts))
+        print(f"repeatability N={N} k={k} {op.kernel} kernel", flush=True)
         xs = [dev(I.uniform_vector(op.ndof, seed=s)) for s in (21, 22)]
         for prec, conv in (("f64", lambda v: v), ("f32", lambda v: v.float().contiguous()),
                            ("bf16", lambda v: v.float().to(torch.bfloat16).contiguous())):
