@@ -479,13 +479,22 @@ __device__ __forceinline__ void lower_line(const MeshArgs<TC>& m, const Tables<T
 // upper faces (evaluated once for both of their elements; the T^+ side goes
 // to m.fb) + its lower faces on a Dirichlet boundary.  The second pass
 // (k_tri_lower) adds the lower interior faces from m.fb.
+// Waves per SIMD the first pass asks the register allocator for: three in
+// FP64 at n = 5, 6, where the face rows sharing the volume scratch tiles
+// leave LDS for three workgroups per CU (n = 6: 8% faster than with two;
+// at n = 7, 8 the registers would spill and the pass ran slower)
+__host__ __device__ constexpr int tri_min_waves(int n, int bytes) { return bytes == 8 && (n == 5 || n == 6) ? 3 : 1; }
+
 template <int N, typename TIN, typename TOUT, typename TC, bool AFF>
-__global__ __launch_bounds__(kBlock) void k_apply_trilinear(MeshArgs<TC> m, const TIN* __restrict__ x,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(tri_min_waves(N, sizeof(TC))))) void k_apply_trilinear(MeshArgs<TC> m, const TIN* __restrict__ x,
                                                             TOUT* __restrict__ y, const int* skip) {
   constexpr int NN = N * N, N3 = NN * N, EPB = elems_per_block(N), PE = Lay<N, TC>::PE;
-  __shared__ TC sA[EPB * PE], sB[EPB * PE], sC[EPB * PE];
+  // the face rows (10 n^2 per element) live in the volume scratch tiles A, B
+  // once the volume term is done, when they fit there (n >= 5)
+  constexpr bool F_IN_AB = 10 * NN <= 2 * PE;
+  __shared__ TC sAB[2 * EPB * PE], sC[EPB * PE];
   __shared__ TC sX[EPB][8][3], sXn[EPB][8][3];
-  __shared__ TC sF[EPB][10][NN];
+  __shared__ TC sFx[F_IN_AB ? 1 : EPB * 10 * NN];
   if (skip != nullptr && *skip) return;
   const Tables<TC>& T = *m.tab;
   const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
@@ -493,9 +502,10 @@ __global__ __launch_bounds__(kBlock) void k_apply_trilinear(MeshArgs<TC> m, cons
   const int64_t e = blk * EPB + el;
   const bool act = (el < EPB) && (e < m.E);
   const int le = act ? el : 0;
-  TC* A = sA + le * PE;
-  TC* B = sB + le * PE;
+  TC* A = sAB + le * PE;
+  TC* B = sAB + (EPB + le) * PE;
   TC* C = sC + le * PE;
+  TC(*F)[NN] = (TC(*)[NN])((F_IN_AB ? sAB : sFx) + le * 10 * NN);
   int ex = 0, ey = 0, ez = 0;
   TC K = TC(1);
   if (act) {
@@ -505,6 +515,8 @@ __global__ __launch_bounds__(kBlock) void k_apply_trilinear(MeshArgs<TC> m, cons
     K = m.K[e];
   }
   tri_volume<N, TC, TIN, AFF>(m, T, x, e, act, t, t1, t2, K, sX[le], A, B, C);
+  // F_IN_AB: the face rows of an element overlap other elements' scratch tiles
+  if (F_IN_AB) __syncthreads();
   const TC (&X)[8][3] = sX[le];
   TC Gc[19];  // AFF: constant J, adj J, det J of the element
   if (AFF) {
@@ -526,14 +538,14 @@ __global__ __launch_bounds__(kBlock) void k_apply_trilinear(MeshArgs<TC> m, cons
   const bool bx0 = act && neighbour<0>(m, ex, ey, ez, 0) < 0;
   const bool by0 = act && neighbour<1>(m, ex, ey, ez, 0) < 0;
   const bool bz0 = act && neighbour<2>(m, ex, ey, ez, 0) < 0;
-  face_term<N, 0, TC, TIN, false, AFF, true>(m, T, x, e, ex, ey, ez, X, sXn[le], K, t1, t2, C, sF[le], act, 1, Gc);
-  face_term<N, 0, TC, TIN, false, AFF>(m, T, x, e, ex, ey, ez, X, sXn[le], K, t1, t2, C, sF[le], bx0, 0, Gc);
+  face_term<N, 0, TC, TIN, false, AFF, true>(m, T, x, e, ex, ey, ez, X, sXn[le], K, t1, t2, C, F, act, 1, Gc);
+  face_term<N, 0, TC, TIN, false, AFF>(m, T, x, e, ex, ey, ez, X, sXn[le], K, t1, t2, C, F, bx0, 0, Gc);
   elem_sync<N>();
-  face_term<N, 1, TC, TIN, false, AFF, true>(m, T, x, e, ex, ey, ez, X, sXn[le], K, t1, t2, C, sF[le], act, 1, Gc);
-  face_term<N, 1, TC, TIN, false, AFF>(m, T, x, e, ex, ey, ez, X, sXn[le], K, t1, t2, C, sF[le], by0, 0, Gc);
+  face_term<N, 1, TC, TIN, false, AFF, true>(m, T, x, e, ex, ey, ez, X, sXn[le], K, t1, t2, C, F, act, 1, Gc);
+  face_term<N, 1, TC, TIN, false, AFF>(m, T, x, e, ex, ey, ez, X, sXn[le], K, t1, t2, C, F, by0, 0, Gc);
   elem_sync<N>();
-  face_term<N, 2, TC, TIN, false, AFF, true>(m, T, x, e, ex, ey, ez, X, sXn[le], K, t1, t2, C, sF[le], act, 1, Gc);
-  face_term<N, 2, TC, TIN, false, AFF>(m, T, x, e, ex, ey, ez, X, sXn[le], K, t1, t2, C, sF[le], bz0, 0, Gc);
+  face_term<N, 2, TC, TIN, false, AFF, true>(m, T, x, e, ex, ey, ez, X, sXn[le], K, t1, t2, C, F, act, 1, Gc);
+  face_term<N, 2, TC, TIN, false, AFF>(m, T, x, e, ex, ey, ez, X, sXn[le], K, t1, t2, C, F, bz0, 0, Gc);
   elem_sync<N>();
   if (act) {
     TC o[N];
