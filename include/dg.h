@@ -101,7 +101,10 @@ int dg_query_workspace(const dg_mesh_desc* mesh, size_t* bytes);
  * space, the coefficient K) in the cell-blocked storage of the Sec. 3.3 DG
  * codepath: 1D tables (Gauss-Lobatto nodes, Gauss points, basis values and
  * derivatives) in FP64 on the host, K = exp(theta) in FP64 and FP32,
- * geometry, Jacobi diagonal.  Synchronises `stream`.  *out receives the
+ * geometry, Jacobi diagonal.  With vertices, setup checks whether every
+ * element is the same parallelepiped (the grid under one affine map, problem
+ * B of Sec. 3.3) and then applies the operator with the constant-metric
+ * kernel; dg_apply_kernel reports the choice.  Synchronises `stream`.  *out receives the
  * context (host memory owned by the library until dg_destroy).  Errors:
  * DG_ERR_ARG for a bad descriptor or a workspace below dg_query_workspace,
  * DG_ERR_UNSUPPORTED for a degree outside 1..7, DG_ERR_DEVICE for a failed HIP
@@ -126,9 +129,10 @@ int dg_set_reaction(dg_ctx* ctx, const double* c, void* stream);
 /* y = A x (Sec. 3.3 operator application; form of Sec. 4.1).  x and y are
  * device vectors of N_dof = nx*ny*nz*(k+1)^3 entries of the types given by
  * `prec` (enum dg_precision); x == y is rejected (DG_ERR_ARG).  On trilinear
- * meshes the apply runs in two passes that exchange face data through the
- * context's workspace, so applies (and solves) on one such context must not
- * overlap in time: issue them on one stream or order them with events. */
+ * meshes (other than equal parallelepipeds) the apply runs in two passes that
+ * exchange face data through the context's workspace, so applies (and solves)
+ * on one such context must not overlap in time: issue them on one stream or
+ * order them with events. */
 int dg_apply(dg_ctx* ctx, int prec, const void* x, void* y, void* stream);
 
 /* y = A^T x, the operator of the adjoint problems.  The symmetric weighted
