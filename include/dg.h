@@ -140,16 +140,18 @@ int dg_apply(dg_ctx* ctx, int prec, const void* x, void* y, void* stream);
  * consistency and symmetry terms are mirror images and the penalty term is
  * symmetric), so A^T = A.  Affine meshes: evaluated from the transposed 1D
  * operators and the transposed face algebra (equal to A x up to rounding);
- * trilinear meshes: the apply itself.  Arguments and errors as dg_apply. */
+ * parallelepiped and trilinear meshes: the apply itself.  Arguments and errors
+ * as dg_apply. */
 int dg_apply_transpose(dg_ctx* ctx, int prec, const void* x, void* y, void* stream);
 
 /* Y = A X (transpose = 1: A^T X) for nrhs vectors at once, the multiple
  * right-hand sides of the block Krylov methods of Sec. 3.5 ("Horizontal
  * vectorization of Block Krylov methods").  X and Y hold nrhs device vectors of
  * N_dof entries each, one after another (vector j starts at entry j N_dof),
- * of the types given by `prec`; 1 <= nrhs <= 65535.  Affine meshes: one launch
- * with the vectors as the second grid dimension; trilinear meshes: one apply
- * per vector.  Errors as dg_apply (overlap of the X and Y ranges: DG_ERR_ARG). */
+ * of the types given by `prec`; 1 <= nrhs <= 65535.  Affine meshes and meshes
+ * of equal parallelepipeds: one launch with the vectors as the second grid
+ * dimension; other trilinear meshes: one apply per vector.  Errors as dg_apply
+ * (overlap of the X and Y ranges: DG_ERR_ARG). */
 int dg_apply_multi(dg_ctx* ctx, int prec, int transpose, int nrhs, const void* X, void* Y, void* stream);
 
 /* g_T = u^T (dA / dtheta_T) v for every element T (device: u, v N_dof

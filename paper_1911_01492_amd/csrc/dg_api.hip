@@ -807,6 +807,10 @@ int dg_apply_multi(dg_ctx* c, int prec, int transpose, int nrhs, const void* X, 
   const size_t tot = (size_t)nrhs * (size_t)c->ndof;
   if (xb < yb + tot * eout && yb < xb + tot * ein) return fail(c, DG_ERR_ARG, "X and Y overlap");
   hipStream_t s = (hipStream_t)stream;
+  if (c->ppd) {  // the form is symmetric: the transpose is the same operator
+    HIP_TRY(c, launch_apply_ppd_multi(c->n, prec, nrhs, ppd_args(c, args64(c)), ppd_args(c, args32(c)), X, Y, s));
+    return DG_OK;
+  }
   if (c->trilinear) {  // the two-pass apply shares its face buffer: one vector after the other
     for (int j = 0; j < nrhs; ++j)
       HIP_TRY(c, apply_any(c, prec, transpose, 0, xb + (size_t)j * c->ndof * ein, (char*)Y + (size_t)j * c->ndof * eout,

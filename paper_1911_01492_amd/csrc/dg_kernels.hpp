@@ -85,6 +85,10 @@ hipError_t launch_apply_trilinear(int n, int prec, int trans, int dot, const Mes
 hipError_t launch_apply_ppd(int n, int prec, int dot, const MeshArgs<double>& m64, const MeshArgs<float>& m32,
                             const void* x, void* y, double* partials, CgState* st, int par, const int* skip,
                             hipStream_t s);
+// Y = A X for nrhs vectors stored one after another (the vector index is the
+// second grid dimension; no fused dot)
+hipError_t launch_apply_ppd_multi(int n, int prec, int nrhs, const MeshArgs<double>& m64, const MeshArgs<float>& m32,
+                                  const void* x, void* y, hipStream_t s);
 hipError_t launch_diag_trilinear(int n, const MeshArgs<double>& m, double* d, const int* run, hipStream_t s);
 // g_T = u^T dA/dtheta_T v on trilinear meshes; parts: 7 E doubles of scratch
 hipError_t launch_dA_trilinear(int n, const MeshArgs<double>& m, const double* u, const double* v, double* parts,

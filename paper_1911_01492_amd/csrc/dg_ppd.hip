@@ -101,6 +101,9 @@ __global__ __launch_bounds__(apply_block(N)) void k_apply_ppd(MeshArgs<TC> m, co
   __shared__ TC sC[NN];  // C, row-major, for lane-indexed rows
   __shared__ double red[BLOCK / 64];
   if (skip != nullptr && *skip) return;
+  // vector blockIdx.y of a multi-vector apply (the vectors follow each other)
+  x += (size_t)blockIdx.y * (size_t)m.E * N3;
+  y += (size_t)blockIdx.y * (size_t)m.E * N3;
   TC* F = F_IN_S2 ? sS2 : sFx;
   // The 1D tables are read through the scalar cache.  Each phase re-derives
   // their address, which keeps the compiler from holding every table in
@@ -318,17 +321,17 @@ __global__ __launch_bounds__(apply_block(N)) void k_apply_ppd(MeshArgs<TC> m, co
 // ---------------------------------------------------------------- launchers
 template <int N, typename TIN, typename TOUT, typename TC, bool DOT>
 static hipError_t run_ppd(const MeshArgs<TC>& m, const void* x, void* y, double* partials, CgState* st, int par,
-                          const int* skip, hipStream_t s) {
+                          const int* skip, hipStream_t s, int nrhs = 1) {
   const int64_t nb = affine_tiles(N, m.nx, m.ny, m.nz);
   const double nd = (double)m.E * N * N * N;
   const bool off32 = nd * (double)(sizeof(TIN) > sizeof(TOUT) ? sizeof(TIN) : sizeof(TOUT)) < 4294967296.0 &&
                      6.0 * (double)m.E * sizeof(TC) < 4294967296.0;
   if (off32)
-    hipLaunchKernelGGL((k_apply_ppd<N, TIN, TOUT, TC, DOT, true>), dim3((unsigned)nb), dim3(apply_block(N)), 0, s, m,
-                       (const TIN*)x, (TOUT*)y, partials, skip);
+    hipLaunchKernelGGL((k_apply_ppd<N, TIN, TOUT, TC, DOT, true>), dim3((unsigned)nb, (unsigned)nrhs),
+                       dim3(apply_block(N)), 0, s, m, (const TIN*)x, (TOUT*)y, partials, skip);
   else
-    hipLaunchKernelGGL((k_apply_ppd<N, TIN, TOUT, TC, DOT, false>), dim3((unsigned)nb), dim3(apply_block(N)), 0, s, m,
-                       (const TIN*)x, (TOUT*)y, partials, skip);
+    hipLaunchKernelGGL((k_apply_ppd<N, TIN, TOUT, TC, DOT, false>), dim3((unsigned)nb, (unsigned)nrhs),
+                       dim3(apply_block(N)), 0, s, m, (const TIN*)x, (TOUT*)y, partials, skip);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess || !DOT || st == nullptr) return e;
   return launch_finish_dot(partials, nb, st, par, s);
@@ -351,6 +354,31 @@ static hipError_t run_ppd_n(int prec, int dot, const MeshArgs<double>& m64, cons
                             hipStream_t s) {
   return dot ? run_ppd_prec<N, true>(prec, m64, m32, x, y, partials, st, par, skip, s)
              : run_ppd_prec<N, false>(prec, m64, m32, x, y, partials, st, par, skip, s);
+}
+
+template <int N>
+static hipError_t run_ppd_multi(int prec, int nrhs, const MeshArgs<double>& m64, const MeshArgs<float>& m32,
+                                const void* x, void* y, hipStream_t s) {
+  switch (prec) {
+    case 0: return run_ppd<N, double, double, double, false>(m64, x, y, nullptr, nullptr, 0, nullptr, s, nrhs);
+    case 1: return run_ppd<N, float, float, float, false>(m32, x, y, nullptr, nullptr, 0, nullptr, s, nrhs);
+    case 2: return run_ppd<N, uint16_t, float, float, false>(m32, x, y, nullptr, nullptr, 0, nullptr, s, nrhs);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_apply_ppd_multi(int n, int prec, int nrhs, const MeshArgs<double>& m64, const MeshArgs<float>& m32,
+                                  const void* x, void* y, hipStream_t s) {
+  switch (n) {
+    case 2: return run_ppd_multi<2>(prec, nrhs, m64, m32, x, y, s);
+    case 3: return run_ppd_multi<3>(prec, nrhs, m64, m32, x, y, s);
+    case 4: return run_ppd_multi<4>(prec, nrhs, m64, m32, x, y, s);
+    case 5: return run_ppd_multi<5>(prec, nrhs, m64, m32, x, y, s);
+    case 6: return run_ppd_multi<6>(prec, nrhs, m64, m32, x, y, s);
+    case 7: return run_ppd_multi<7>(prec, nrhs, m64, m32, x, y, s);
+    case 8: return run_ppd_multi<8>(prec, nrhs, m64, m32, x, y, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_apply_ppd(int n, int prec, int dot, const MeshArgs<double>& m64, const MeshArgs<float>& m32,

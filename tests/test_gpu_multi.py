@@ -55,6 +55,16 @@ def test_multi_trilinear_and_errors():
     Y = op.apply_multi(X)
     for j in range(2):
         assert torch.equal(Y[j], op.apply(X[j].contiguous()))
+    # meshes of equal parallelepipeds: one launch, the vector as the second grid dimension
+    opp = DGOperator(5, 4, 3, 3, "dirichlet", theta=dev(I.theta(60)), vertices=dev(I.sheared_vertices(5, 4, 3)))
+    assert opp.kernel == "parallelepiped"
+    for prec, conv in (("f64", lambda v: v), ("f32", lambda v: v.float()),
+                       ("bf16", lambda v: v.float().to(torch.bfloat16))):
+        Xp = conv(dev(np.stack([I.uniform_vector(opp.ndof, seed=60 + j) for j in range(3)]))).contiguous()
+        for trans in (False, True):
+            Yp = opp.apply_multi(Xp, prec=prec, transpose=trans)
+            for j in range(3):
+                assert torch.equal(Yp[j], opp.apply(Xp[j].contiguous(), prec=prec, transpose=trans)), (prec, trans, j)
     L = dg.lib()
     s = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
     for nrhs in (0, -1, 70000):
