@@ -146,7 +146,20 @@ __global__ __launch_bounds__(apply_block(N), (N == 5 && sizeof(TC) == 8) ? 8 : 1
   x += (size_t)blockIdx.y * (size_t)m.E * N3;
   y += (size_t)blockIdx.y * (size_t)m.E * N3;
   TC* F = F_IN_S2 ? sS2 : sFx;
-  const Tables<TC>& T = *m.tab;
+  // The 1D tables are read through the scalar cache.  At n = 8 in FP64 they
+  // do not fit in scalar registers for the whole kernel (the compiler spills
+  // them into vector-register lanes): there each use re-derives their address
+  // through a constant-address pointer, so each phase loads what it uses.
+  auto tabs = [&]() -> const Tables<TC>& {
+    if constexpr (N >= 8 && sizeof(TC) == 8) {
+      uint64_t a = (uint64_t)m.tab;
+      asm volatile("" : "+s"(a));
+      typedef const __attribute__((address_space(4))) Tables<TC>* ConstTab;
+      return *(const Tables<TC>*)(ConstTab)a;
+    } else {
+      return *m.tab;
+    }
+  };
   // brick coordinates: uniform per workgroup (scalar arithmetic)
   const int tb = (int)xcd_remap(blockIdx.x, gridDim.x);
   int o[3];
@@ -177,14 +190,14 @@ __global__ __launch_bounds__(apply_block(N), (N == 5 && sizeof(TC) == 8) ? 8 : 1
   auto gco = [&](int f) { return OFF32 ? m.G[(uint32_t)(6 * e + f)] : m.G[6 * e + f]; };
   TC b[N], v[N], w[N];
   // ---------------- X: b_x -> S1
-  face_phase<N, 0, BX, BY, BZ, FS, TC, TIN, TRANS, OFF32>(m, T, x, own, e, c, o, Nd, t, t1, t2, F, Fe, K, gco(0), gco(1), TC(0), b);
+  face_phase<N, 0, BX, BY, BZ, FS, TC, TIN, TRANS, OFF32>(m, tabs(), x, own, e, c, o, Nd, t, t1, t2, F, Fe, K, gco(0), gco(1), TC(0), b);
   lds_put<N, 0>(S1, t1, t2, b);
   lds_sync<XROW>();  // F (read by the x-neighbours) is rewritten by the next phase
   // ---------------- Y: b_y -> S2, M_y b_x -> S1
-  face_phase<N, 1, BX, BY, BZ, FS, TC, TIN, TRANS, OFF32>(m, T, x, own, e, c, o, Nd, t, t1, t2, F, Fe, K, gco(2), gco(3), TC(0), b);
+  face_phase<N, 1, BX, BY, BZ, FS, TC, TIN, TRANS, OFF32>(m, tabs(), x, own, e, c, o, Nd, t, t1, t2, F, Fe, K, gco(2), gco(3), TC(0), b);
   {
     lds_get<N, 1>(S1, t1, t2, v);
-    mass_line<N, TC, TRANS>(T, v, w);
+    mass_line<N, TC, TRANS>(tabs(), v, w);
   }
   if (F_IN_S2) __syncthreads();  // the face scalars in S2 have been read
   {
@@ -196,7 +209,7 @@ __global__ __launch_bounds__(apply_block(N), (N == 5 && sizeof(TC) == 8) ? 8 : 1
   {
     lds_get<N, 0>(S2, t1, t2, v);
     lds_get<N, 0>(S1, t1, t2, w);
-    mass_line<N, TC, TRANS>(T, v, b);
+    mass_line<N, TC, TRANS>(tabs(), v, b);
 #pragma unroll
     for (int i = 0; i < N; ++i) w[i] += b[i];
     lds_put<N, 0>(S1, t1, t2, w);
@@ -205,11 +218,11 @@ __global__ __launch_bounds__(apply_block(N), (N == 5 && sizeof(TC) == 8) ? 8 : 1
   // ---------------- Z: b_z -> S2, r = M_z S1
   TC r[N], xz[N];  // xz: the thread's z-line of x, for the fused <x, y>
   const TC cr = m.R ? m.R[e] * m.vol : TC(0);
-  face_phase<N, 2, BX, BY, BZ, FS, TC, TIN, TRANS, OFF32>(m, T, x, own, e, c, o, Nd, t, t1, t2, F, Fe, K, gco(4), gco(5), cr, b,
+  face_phase<N, 2, BX, BY, BZ, FS, TC, TIN, TRANS, OFF32>(m, tabs(), x, own, e, c, o, Nd, t, t1, t2, F, Fe, K, gco(4), gco(5), cr, b,
                                                DOT ? xz : nullptr);
   {
     lds_get<N, 2>(S1, t1, t2, v);
-    mass_line<N, TC, TRANS>(T, v, r);
+    mass_line<N, TC, TRANS>(tabs(), v, r);
   }
   if (F_IN_S2) __syncthreads();
   lds_put<N, 2>(S2, t1, t2, b);
@@ -217,13 +230,13 @@ __global__ __launch_bounds__(apply_block(N), (N == 5 && sizeof(TC) == 8) ? 8 : 1
   // ---------------- X3, Y3: S2 <- M_y M_x S2
   {
     lds_get<N, 0>(S2, t1, t2, v);
-    mass_line<N, TC, TRANS>(T, v, w);
+    mass_line<N, TC, TRANS>(tabs(), v, w);
     lds_put<N, 0>(S2, t1, t2, w);
   }
   lds_sync<ELEM>();
   {
     lds_get<N, 1>(S2, t1, t2, v);
-    mass_line<N, TC, TRANS>(T, v, w);
+    mass_line<N, TC, TRANS>(tabs(), v, w);
     lds_put<N, 1>(S2, t1, t2, w);
   }
   lds_sync<ELEM>();
