@@ -153,7 +153,7 @@ __device__ void face_term(const MeshArgs<TC>& m, const Tables<TC>& T, const TIN*
         }
       deto = Gc[18];
     } else {
-      trilinear_jacobian(X, xi, Jo);
+      face_jacobian<D>(X, s, xi[ax], xi[bx], Jo);
       adj3(Jo, Ao);
       deto = det3(Jo);
     }
@@ -182,7 +182,7 @@ __device__ void face_term(const MeshArgs<TC>& m, const Tables<TC>& T, const TIN*
 #pragma unroll
           for (int cc = 0; cc < 3; ++cc) Jn[r][cc] = Xn[1 << cc][r] - Xn[0][r];
       } else {
-        trilinear_jacobian(Xn, xin, Jn);
+        face_jacobian<D>(Xn, 1 - s, xi[ax], xi[bx], Jn);
       }
       adj3(Jn, An);
       const TC idetn = TC(1) / det3(Jn);
@@ -380,6 +380,7 @@ __device__ void tri_volume(const MeshArgs<TC>& m, const Tables<TC>& T, const TIN
           G0[cc][r] = G0[r][cc];
         }
     }
+    const JacZLine<TC> jz(X, T.gx[t1], T.gx[t2]);  // unused (and dropped) for AFF
 #pragma unroll
     for (int q = 0; q < N; ++q) {
       TC Gm[3][3];
@@ -391,9 +392,8 @@ __device__ void tri_volume(const MeshArgs<TC>& m, const Tables<TC>& T, const TIN
 #pragma unroll
           for (int cc = 0; cc < 3; ++cc) Gm[r][cc] = c * G0[r][cc];
       } else {
-        const TC xi[3] = {T.gx[t1], T.gx[t2], T.gx[q]};
         TC J[3][3], Aj[3][3];
-        trilinear_jacobian(X, xi, J);
+        jz.at(T.gx[q], J);
         adj3(J, Aj);
         const TC dJ = fabs(det3(J));
         const TC c = wq12 * T.gw[q] / dJ;
