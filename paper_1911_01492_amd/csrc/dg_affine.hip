@@ -184,17 +184,18 @@ __global__ __launch_bounds__(apply_block(N), (N == 5 && sizeof(TC) == 8) ? 8 : 1
   // element-local hand-offs below need no workgroup barrier
   TC* Fe = F + le * FS;
   const int64_t e = c[0] + (int64_t)m.nx * (c[1] + (int64_t)m.ny * c[2]);
+  const uint32_t eo = (uint32_t)e * (uint32_t)N3;  // the element's first entry (N_dof < 2^31)
   const TC K = m.K[e];
   // face coefficients of the element's faces 2D and 2D+1, loaded in the phase
   // that uses them (keeps the register count at 64 for n = 5 in FP64)
   auto gco = [&](int f) { return OFF32 ? m.G[(uint32_t)(6 * e + f)] : m.G[6 * e + f]; };
   TC b[N], v[N], w[N];
   // ---------------- X: b_x -> S1
-  face_phase<N, 0, BX, BY, BZ, FS, TC, TIN, TRANS, OFF32>(m, tabs(), x, own, e, c, o, Nd, t, t1, t2, F, Fe, K, gco(0), gco(1), TC(0), b);
+  face_phase<N, 0, BX, BY, BZ, FS, TC, TIN, TRANS, OFF32>(m, tabs(), x, own, eo, c, o, Nd, t, t1, t2, F, Fe, K, gco(0), gco(1), TC(0), b);
   lds_put<N, 0>(S1, t1, t2, b);
   lds_sync<XROW>();  // F (read by the x-neighbours) is rewritten by the next phase
   // ---------------- Y: b_y -> S2, M_y b_x -> S1
-  face_phase<N, 1, BX, BY, BZ, FS, TC, TIN, TRANS, OFF32>(m, tabs(), x, own, e, c, o, Nd, t, t1, t2, F, Fe, K, gco(2), gco(3), TC(0), b);
+  face_phase<N, 1, BX, BY, BZ, FS, TC, TIN, TRANS, OFF32>(m, tabs(), x, own, eo, c, o, Nd, t, t1, t2, F, Fe, K, gco(2), gco(3), TC(0), b);
   {
     lds_get<N, 1>(S1, t1, t2, v);
     mass_line<N, TC, TRANS>(tabs(), v, w);
@@ -218,7 +219,7 @@ __global__ __launch_bounds__(apply_block(N), (N == 5 && sizeof(TC) == 8) ? 8 : 1
   // ---------------- Z: b_z -> S2, r = M_z S1
   TC r[N], xz[N];  // xz: the thread's z-line of x, for the fused <x, y>
   const TC cr = m.R ? m.R[e] * m.vol : TC(0);
-  face_phase<N, 2, BX, BY, BZ, FS, TC, TIN, TRANS, OFF32>(m, tabs(), x, own, e, c, o, Nd, t, t1, t2, F, Fe, K, gco(4), gco(5), cr, b,
+  face_phase<N, 2, BX, BY, BZ, FS, TC, TIN, TRANS, OFF32>(m, tabs(), x, own, eo, c, o, Nd, t, t1, t2, F, Fe, K, gco(4), gco(5), cr, b,
                                                DOT ? xz : nullptr);
   {
     lds_get<N, 2>(S1, t1, t2, v);
@@ -246,7 +247,7 @@ __global__ __launch_bounds__(apply_block(N), (N == 5 && sizeof(TC) == 8) ? 8 : 1
   if (act) {
     // y is written once and not read back here: nontemporal stores keep it
     // from displacing in L2 the x lines that neighbouring bricks still read
-    const uint32_t yb = ((uint32_t)e * (uint32_t)N3 + (uint32_t)lidx<N, 2>(t1, t2, 0)) * (uint32_t)sizeof(TOUT);
+    const uint32_t yb = (eo + (uint32_t)lidx<N, 2>(t1, t2, 0)) * (uint32_t)sizeof(TOUT);
     TOUT* py = y + e * N3;
 #pragma unroll
     for (int i = 0; i < N; ++i) {

@@ -14,14 +14,16 @@ namespace dg {
 template <int N, int D, int BX, int BY, int BZ, typename TC, typename TIN, bool OFF32 = false>
 struct AxisNeighbours {
   bool inL, inH, glL, glH, hasL, hasH;
-  int elL, elH;
-  int64_t eL, eH;
+  int fL, fH;  // exchange-slot offsets of in-brick neighbours from the own slot
+  uint32_t eoL, eoH;  // first entries of the neighbour elements
   TC gL[N], gH[N];
-  __device__ __forceinline__ void locate(int nx, int ny, const int (&c)[3], const int (&o)[3],
+  // eo: the element's first entry (element index times n^3, below 2^31);
+  // FS: element stride of the exchange slots
+  template <int FS>
+  __device__ __forceinline__ void locate(int nx, int ny, uint32_t eo, const int (&c)[3], const int (&o)[3],
                                          const int (&Nd)[3], int periodic, bool slot = true) {
     constexpr int Bd = D == 0 ? BX : (D == 1 ? BY : BZ);
     constexpr int sD = D == 0 ? 1 : (D == 1 ? BX : BX * BY);
-    const int el = (c[0] - o[0]) + BX * ((c[1] - o[1]) + BY * (c[2] - o[2]));
     const int cl = nb_coord(c[D], 0, Nd[D], periodic), ch = nb_coord(c[D], 1, Nd[D], periodic);
     hasL = slot && cl >= 0;
     hasH = slot && ch >= 0;
@@ -30,18 +32,23 @@ struct AxisNeighbours {
     inH = hasH && lh >= 0 && lh < Bd;
     glL = hasL && !inL;
     glH = hasH && !inH;
-    elL = el + (ll - (c[D] - o[D])) * sD;
-    elH = el + (lh - (c[D] - o[D])) * sD;
-    int g[3] = {c[0], c[1], c[2]};
-    g[D] = cl < 0 ? 0 : cl;
-    eL = g[0] + (int64_t)nx * (g[1] + (int64_t)ny * g[2]);
-    g[D] = ch < 0 ? 0 : ch;
-    eH = g[0] + (int64_t)nx * (g[1] + (int64_t)ny * g[2]);
+    // an in-brick neighbour is the next slot along D, or across the brick
+    // when the brick spans the periodic axis (uniform choices, no multiply)
+    fL = c[D] > 0 ? -sD * FS : (Nd[D] - 1) * sD * FS;
+    fH = c[D] < Nd[D] - 1 ? sD * FS : -(Nd[D] - 1) * sD * FS;
+    // the neighbours' first entries as uniform offsets from the element's: one
+    // element stride along D, or the periodic wrap across the mesh (no
+    // per-lane multiply; unused on a side without neighbour)
+    constexpr uint32_t N3 = N * N * N;
+    const uint32_t sd = D == 0 ? N3 : (D == 1 ? (uint32_t)nx * N3 : (uint32_t)nx * (uint32_t)ny * N3);
+    const uint32_t wrap = (uint32_t)(Nd[D] - 1) * sd;
+    eoL = c[D] > 0 ? eo - sd : eo + wrap;
+    eoH = c[D] < Nd[D] - 1 ? eo + sd : eo - wrap;
   }
   // issue the HBM loads (before the own work of the phase, to hide latency)
   __device__ __forceinline__ void fetch(const TIN* __restrict__ x, int t1, int t2) {
-    if (glL) glb_get<N, D, TC, TIN, OFF32>(x, eL, t1, t2, gL);
-    if (glH) glb_get<N, D, TC, TIN, OFF32>(x, eH, t1, t2, gH);
+    if (glL) glb_get_at<N, D, TC, TIN, OFF32>(x, eoL, t1, t2, gL);
+    if (glH) glb_get_at<N, D, TC, TIN, OFF32>(x, eoH, t1, t2, gH);
   }
   // the HBM neighbour lines reduced to their face scalars (frees the lines)
   TC uL, dL, uH, dH;
@@ -57,21 +64,20 @@ struct AxisNeighbours {
     }
   }
   // neighbour scalars: low side -> its upper-face (U, d1.u), high side -> its lower-face (U, d0.u);
-  // element slots of FS values in F
-  template <int FS>
-  __device__ __forceinline__ void scalars(const TC* F, int t, TC& UL, TC& GLr, TC& UH, TC& GHr) const {
+  // Fe: the own element's exchange slot
+  __device__ __forceinline__ void scalars(const TC* Fe, int t, TC& UL, TC& GLr, TC& UH, TC& GHr) const {
     constexpr int NN = N * N;
     UL = uL;
     GLr = dL;
     UH = uH;
     GHr = dH;
     if (inL) {
-      UL = F[elL * FS + 2 * NN + t];
-      GLr = F[elL * FS + 3 * NN + t];
+      UL = Fe[fL + 2 * NN + t];
+      GLr = Fe[fL + 3 * NN + t];
     }
     if (inH) {
-      UH = F[elH * FS + 0 * NN + t];
-      GHr = F[elH * FS + 1 * NN + t];
+      UH = Fe[fH + 0 * NN + t];
+      GHr = Fe[fH + 1 * NN + t];
     }
   }
 };
@@ -100,16 +106,16 @@ __device__ __forceinline__ void lds_sync() {
 // is discarded).
 template <int N, int D, int BX, int BY, int BZ, int FS, typename TC, typename TIN, bool TRANS, bool OFF32>
 __device__ __forceinline__ void face_phase(const MeshArgs<TC>& m, const Tables<TC>& T, const TIN* __restrict__ x,
-                                           bool act, int64_t e, const int (&c)[3], const int (&o)[3],
+                                           bool act, uint32_t eo, const int (&c)[3], const int (&o)[3],
                                            const int (&Nd)[3], int t, int t1, int t2, TC* F, TC* Fe, TC K, TC GL,
                                            TC GH, TC cr, TC (&b)[N], TC* own = nullptr, TC* nbt = nullptr) {
   constexpr int NN = N * N;
   AxisNeighbours<N, D, BX, BY, BZ, TC, TIN, OFF32> nb;
   TC u[N], g0, g1;
   {
-    nb.locate(m.nx, m.ny, c, o, Nd, m.periodic, act);
+    nb.template locate<FS>(m.nx, m.ny, eo, c, o, Nd, m.periodic, act);
     nb.fetch(x, t1, t2);
-    glb_get<N, D, TC, TIN, OFF32>(x, e, t1, t2, u);
+    glb_get_at<N, D, TC, TIN, OFF32>(x, eo, t1, t2, u);
     nb.reduce(T);
     g0 = dot_end<N, TC, 0>(T, u);
     g1 = dot_end<N, TC, 1>(T, u);
@@ -122,7 +128,7 @@ __device__ __forceinline__ void face_phase(const MeshArgs<TC>& m, const Tables<T
   lds_sync<D == 0 && 64 % (BX * NN) == 0>();
   {
     TC UL, GLr, UH, GHr;
-    nb.template scalars<FS>(F, t, UL, GLr, UH, GHr);
+    nb.scalars(Fe, t, UL, GLr, UH, GHr);
     line_op_s<N, TC, TRANS>(T, u, g0, g1, UL, GLr, UH, GHr, nb.hasL, nb.hasH, GL, GH, K * m.vs[D], m.ih[D],
                             m.sg[D], m.At[D], b);
     if (own != nullptr) {  // the caller keeps the line (x along D at (t1, t2))

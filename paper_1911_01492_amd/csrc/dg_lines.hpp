@@ -76,18 +76,23 @@ __device__ __forceinline__ void lds_put(TC* tile, int t1, int t2, const TC (&v)[
 // formed in 32 bits, which lets the load take the scalar-base form with a
 // 32-bit vector offset instead of a 64-bit address computed per load.
 template <int N, int D, typename TC, typename TIN, bool OFF32 = false>
-__device__ __forceinline__ void glb_get(const TIN* __restrict__ x, int64_t e, int t1, int t2,
-                                        TC (&v)[N]) {
+__device__ __forceinline__ void glb_get_at(const TIN* __restrict__ x, uint32_t eo, int t1, int t2, TC (&v)[N]) {
+  // eo: the element's first entry (element index times n^3)
   if constexpr (OFF32) {
-    const uint32_t b = ((uint32_t)e * (uint32_t)(N * N * N) + (uint32_t)lidx<N, D>(t1, t2, 0)) * (uint32_t)sizeof(TIN);
+    const uint32_t b = (eo + (uint32_t)lidx<N, D>(t1, t2, 0)) * (uint32_t)sizeof(TIN);
 #pragma unroll
     for (int i = 0; i < N; ++i)
       v[i] = load_as<TC, TIN>((const TIN*)((const char*)x + (b + (uint32_t)(lidx<N, D>(0, 0, i) * sizeof(TIN)))));
   } else {
-    const uint32_t base = (uint32_t)e * (uint32_t)(N * N * N) + (uint32_t)lidx<N, D>(t1, t2, 0);
+    const uint32_t base = eo + (uint32_t)lidx<N, D>(t1, t2, 0);
 #pragma unroll
     for (int i = 0; i < N; ++i) v[i] = load_as<TC, TIN>(x + (base + (uint32_t)(lidx<N, D>(0, 0, i))));
   }
+}
+template <int N, int D, typename TC, typename TIN, bool OFF32 = false>
+__device__ __forceinline__ void glb_get(const TIN* __restrict__ x, int64_t e, int t1, int t2,
+                                        TC (&v)[N]) {
+  glb_get_at<N, D, TC, TIN, OFF32>(x, (uint32_t)e * (uint32_t)(N * N * N), t1, t2, v);
 }
 
 // out = A a for A given by its even-odd halves (SIGN: A[n-1-i][n-1-j] = SIGN A[i][j]):

@@ -135,6 +135,11 @@ __global__ __launch_bounds__(apply_block(N)) void k_apply_ppd(MeshArgs<TC> m, co
   TC* P = sP + el * 8 * NN;
   if (tid < NN) sC[tid] = tabs().Cd[(tid / N) * kMaxN + tid % N];
   const int64_t e = c[0] + (int64_t)m.nx * (c[1] + (int64_t)m.ny * c[2]);
+  // the element's first entry (N_dof < 2^31), opaque to the compiler so that
+  // the neighbour entries below stay offsets from it rather than being
+  // re-derived per load from the element index by 32-bit multiplies
+  uint32_t eo = (uint32_t)e * (uint32_t)N3;
+  asm volatile("" : "+v"(eo));
   const TC K = m.K[e], K2 = TC(-2) * K;
   auto gco = [&](int f) { return OFF32 ? m.G[(uint32_t)(6 * e + f)] : m.G[6 * e + f]; };
   const TC gxy = m.go[0], gxz = m.go[1], gyz = m.go[2];
@@ -144,7 +149,7 @@ __global__ __launch_bounds__(apply_block(N)) void k_apply_ppd(MeshArgs<TC> m, co
   {
     const Tables<TC>& T = tabs();
     const TC GL = gco(0), GH = gco(1);
-    face_phase<N, 0, BX, BY, BZ, FS, TC, TIN, false, OFF32>(m, T, x, own, e, c, o, Nd, t, t1, t2, F, Fe, K, GL, GH,
+    face_phase<N, 0, BX, BY, BZ, FS, TC, TIN, false, OFF32>(m, T, x, own, eo, c, o, Nd, t, t1, t2, F, Fe, K, GL, GH,
                                                             TC(0), b, u, tr);
     lds_put<N, 0>(S1, t1, t2, b);
     P[0 * NN + t] = K * u[0] - TC(2) * GL * tr[0];
@@ -157,7 +162,7 @@ __global__ __launch_bounds__(apply_block(N)) void k_apply_ppd(MeshArgs<TC> m, co
   {
     const Tables<TC>& T = tabs();
     const TC GL = gco(2), GH = gco(3);
-    face_phase<N, 1, BX, BY, BZ, FS, TC, TIN, false, OFF32>(m, T, x, own, e, c, o, Nd, t, t1, t2, F, Fe, K, GL, GH,
+    face_phase<N, 1, BX, BY, BZ, FS, TC, TIN, false, OFF32>(m, T, x, own, eo, c, o, Nd, t, t1, t2, F, Fe, K, GL, GH,
                                                             TC(0), b, u, tr);
     lds_get<N, 1>(S1, t1, t2, v);
     mass_line<N, TC, false>(T, v, w);
@@ -212,7 +217,7 @@ __global__ __launch_bounds__(apply_block(N)) void k_apply_ppd(MeshArgs<TC> m, co
     const Tables<TC>& T = tabs();
     const TC GL = gco(4), GH = gco(5);
     const TC cr = m.R ? m.R[e] * m.vol : TC(0);
-    face_phase<N, 2, BX, BY, BZ, FS, TC, TIN, false, OFF32>(m, T, x, own, e, c, o, Nd, t, t1, t2, F, Fe, K, GL, GH,
+    face_phase<N, 2, BX, BY, BZ, FS, TC, TIN, false, OFF32>(m, T, x, own, eo, c, o, Nd, t, t1, t2, F, Fe, K, GL, GH,
                                                             cr, b, u, tr);
     lds_get<N, 2>(S1, t1, t2, v);
     mass_line<N, TC, false>(T, v, r);
@@ -301,7 +306,7 @@ __global__ __launch_bounds__(apply_block(N)) void k_apply_ppd(MeshArgs<TC> m, co
   lds_get<N, 2>(S2, t1, t2, v);
   lds_get<N, 2>(S1, t1, t2, w);
   if (act) {
-    const uint32_t yb = ((uint32_t)e * (uint32_t)N3 + (uint32_t)lidx<N, 2>(t1, t2, 0)) * (uint32_t)sizeof(TOUT);
+    const uint32_t yb = (eo + (uint32_t)lidx<N, 2>(t1, t2, 0)) * (uint32_t)sizeof(TOUT);
     TOUT* py = y + e * N3;
 #pragma unroll
     for (int i = 0; i < N; ++i) {

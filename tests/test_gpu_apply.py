@@ -306,20 +306,27 @@ def test_repeatable_with_changing_inputs():
     # so the face phases depend on workgroup barriers; perturbed meshes take
     # the general trilinear kernel, layered shears its constant-metric
     # variant, sheared meshes (one affine map) the parallelepiped kernel
-    cases = [(32, 3, None), (12, 1, None), (6, 7, None), (8, 3, I.perturbed_vertices(8, 0.1, seed=3)),
+    # affine k = 2, 4, 5, 6: an element spans two wavefronts (workgroup barriers)
+    cases = [(32, 3, None), (12, 1, None), (6, 7, None), (10, 2, None), (12, 4, None), (7, 5, None),
+             (6, 6, None), (8, 3, I.perturbed_vertices(8, 0.1, seed=3)),
              (4, 7, I.perturbed_vertices(4, 0.1, seed=4)),
              (9, 2, I.perturbed_vertices(9, 0.1, seed=5)), (7, 4, I.sheared_vertices(7, 7, 7)),
              (6, 5, I.perturbed_vertices(6, 0.1, seed=6)), (5, 6, I.sheared_vertices(5, 5, 5)),
              (5, 4, I.perturbed_vertices(5, 0.1, seed=8)), (6, 2, I.sheared_vertices(6, 6, 6)),
              (9, 3, I.sheared_vertices(9, 9, 9)), (6, 4, I.layered_shear_vertices(6, 6, 6)),
-             (5, 5, I.layered_shear_vertices(5, 5, 5)), (7, 2, I.layered_shear_vertices(7, 7, 7))]
+             (5, 5, I.layered_shear_vertices(5, 5, 5)), (7, 2, I.layered_shear_vertices(7, 7, 7)),
+             (6, 5, I.sheared_vertices(6, 6, 6)), (4, 7, I.sheared_vertices(4, 4, 4)),
+             (9, 1, I.sheared_vertices(9, 9, 9))]
     for N, k, verts in cases:
         op = DGOperator(N, N, N, k, "dirichlet", theta=dev(I.theta(N ** 3)),
                         vertices=None if verts is None else dev(verts))
         print(f"repeatability N={N} k={k} {op.kernel} kernel", flush=True)
         xs = [dev(I.uniform_vector(op.ndof, seed=s)) for s in (21, 22)]
-        for prec, conv in (("f64", lambda v: v), ("f32", lambda v: v.float().contiguous()),
-                           ("bf16", lambda v: v.float().to(torch.bfloat16).contiguous())):
+        bf16 = lambda v: v.float().to(torch.bfloat16).contiguous()  # noqa: E731
+        precs = [("f64", lambda v: v), ("f32", lambda v: v.float().contiguous()), ("bf16", bf16)]
+        if op.kernel == "affine" and k <= 4:
+            precs.append(("bf16_mfma", bf16))
+        for prec, conv in precs:
             X = [conv(v) for v in xs]
             ref = [op.apply(X[0], prec=prec).clone(), op.apply(X[1], prec=prec).clone()]
             for r in range(40):

@@ -106,3 +106,20 @@ def test_block_jacobi_refusals():
     with pytest.raises(DGError) as ei:
         tri.cg_solve(dev(I.uniform_vector(tri.ndof)), precond="block_jacobi")
     assert ei.value.code == DG_ERR_UNSUPPORTED
+
+
+def test_block_jacobi_repeatable():
+    """Solves that alternate between two right-hand sides give bit-identical
+    solutions and iteration counts for the same right-hand side (FP64 PCG and
+    the FP32 keep-mode defect correction, 12^3 Q4: an element's 25 threads
+    span two wavefronts of the block-apply kernel)."""
+    N, k = 12, 4
+    banner("block-jacobi repeatability 12^3 Q4")
+    op = DGOperator(N, N, N, k, "dirichlet", theta=dev(I.theta(N ** 3, seed=40)))
+    bs = [dev(I.uniform_vector(op.ndof, seed=s)) for s in (41, 42)]
+    for prec, mode in (("f64", "restart"), ("f32", "keep")):
+        ref = [op.cg_solve(b, prec_inner=prec, dc_mode=mode, precond="block_jacobi", rtol=1e-10) for b in bs]
+        ref = [(u.clone(), info["iters"]) for u, info in ref]
+        for r in range(6):
+            u, info = op.cg_solve(bs[r % 2], prec_inner=prec, dc_mode=mode, precond="block_jacobi", rtol=1e-10)
+            assert info["iters"] == ref[r % 2][1] and torch.equal(u, ref[r % 2][0]), (prec, r)
