@@ -22,15 +22,16 @@ CONV = {"f64": lambda v: v, "f32": lambda v: v.float(), "bf16": lambda v: v.floa
         "bf16_mfma": lambda v: v.float().to(torch.bfloat16)}
 
 
-@pytest.mark.parametrize("shape,k,bc", [((5, 3, 2), 4, "dirichlet"), ((4, 4, 3), 3, "periodic"),
-                                        ((3, 2, 2), 6, "dirichlet"), ((7, 5, 3), 1, "dirichlet")])
-def test_multi_matches_single_applies(shape, k, bc):
-    banner(f"apply_multi {shape} k={k} {bc}")
+@pytest.mark.parametrize("shape,k,bc,nrhs", [((5, 3, 2), 4, "dirichlet", 3), ((4, 4, 3), 3, "periodic", 3),
+                                             ((3, 2, 2), 6, "dirichlet", 3), ((7, 5, 3), 1, "dirichlet", 3),
+                                             ((6, 5, 3), 2, "periodic", 4), ((3, 3, 2), 5, "dirichlet", 4),
+                                             ((2, 2, 3), 7, "periodic", 3)])
+def test_multi_matches_single_applies(shape, k, bc, nrhs):
+    banner(f"apply_multi {shape} k={k} {bc} nrhs={nrhs}")
     E = int(np.prod(shape))
     theta = I.theta(E, seed=2)
     op = DGOperator(*shape, k, bc, theta=dev(theta))
     A = O.assemble(O.Mesh(*shape, k, bc=O.PERIODIC if bc == "periodic" else O.DIRICHLET, theta=theta))
-    nrhs = 3
     X64 = dev(np.stack([I.uniform_vector(op.ndof, seed=40 + j) for j in range(nrhs)]))
     for prec in ("f64", "f32", "bf16", "bf16_mfma"):
         if prec == "bf16_mfma" and k > 4:
@@ -44,6 +45,22 @@ def test_multi_matches_single_applies(shape, k, bc):
             Yh = host(op.apply_multi(X))
             for j in range(nrhs):
                 assert rel_l2(Yh[j], A @ host(X64[j])) <= 1e-12
+
+
+def test_multi_reaction_and_repeats():
+    """With a reaction term, and repeated with alternating inputs: every vector
+    bit-identical to its single apply each time."""
+    shape, k = (6, 4, 3), 4
+    banner(f"apply_multi reaction {shape} k={k}")
+    E = int(np.prod(shape))
+    op = DGOperator(*shape, k, "dirichlet", theta=dev(I.theta(E, seed=5)))
+    op.set_reaction(dev(I.reaction(E, seed=6)))
+    Xs = [dev(np.stack([I.uniform_vector(op.ndof, seed=70 + 4 * r + j) for j in range(4)])) for r in range(2)]
+    for prec in ("f64", "f32", "bf16"):
+        Xp = [CONV[prec](X).contiguous() for X in Xs]
+        ref = [torch.stack([op.apply(X[j].contiguous(), prec=prec) for j in range(4)]) for X in Xp]
+        for r in range(10):
+            assert torch.equal(op.apply_multi(Xp[r % 2], prec=prec), ref[r % 2]), (prec, r)
 
 
 def test_multi_trilinear_and_errors():
