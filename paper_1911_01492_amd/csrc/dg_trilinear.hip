@@ -482,8 +482,12 @@ __device__ __forceinline__ void lower_line(const MeshArgs<TC>& m, const Tables<T
 // Waves per SIMD the first pass asks the register allocator for: three in
 // FP64 at n = 5, 6, where the face rows sharing the volume scratch tiles
 // leave LDS for three workgroups per CU (n = 6: 8% faster than with two;
-// at n = 7, 8 the registers would spill and the pass ran slower)
-__host__ __device__ constexpr int tri_min_waves(int n, int bytes) { return bytes == 8 && (n == 5 || n == 6) ? 3 : 1; }
+// at n = 7, 8 the registers would spill and the pass ran slower); five in
+// FP32 from n = 6 on (at most 96 VGPRs instead of 97-104; LDS leaves room
+// for five workgroups; 48^3 Q7 1-2% faster, 26^3 Q5 up to 4%)
+__host__ __device__ constexpr int tri_min_waves(int n, int bytes) {
+  return bytes == 8 && (n == 5 || n == 6) ? 3 : (bytes == 4 && n >= 6 ? 5 : 1);
+}
 
 template <int N, typename TIN, typename TOUT, typename TC, bool AFF>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(tri_min_waves(N, sizeof(TC))))) void k_apply_trilinear(MeshArgs<TC> m, const TIN* __restrict__ x,
