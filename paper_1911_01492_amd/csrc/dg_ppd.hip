@@ -135,11 +135,7 @@ __global__ __launch_bounds__(apply_block(N)) void k_apply_ppd(MeshArgs<TC> m, co
   TC* P = sP + el * 8 * NN;
   if (tid < NN) sC[tid] = tabs().Cd[(tid / N) * kMaxN + tid % N];
   const int64_t e = c[0] + (int64_t)m.nx * (c[1] + (int64_t)m.ny * c[2]);
-  // the element's first entry (N_dof < 2^31), opaque to the compiler so that
-  // the neighbour entries below stay offsets from it rather than being
-  // re-derived per load from the element index by 32-bit multiplies
-  uint32_t eo = (uint32_t)e * (uint32_t)N3;
-  asm volatile("" : "+v"(eo));
+  const uint32_t eo = (uint32_t)e * (uint32_t)N3;  // the element's first entry (N_dof < 2^31)
   const TC K = m.K[e], K2 = TC(-2) * K;
   auto gco = [&](int f) { return OFF32 ? m.G[(uint32_t)(6 * e + f)] : m.G[6 * e + f]; };
   const TC gxy = m.go[0], gxz = m.go[1], gyz = m.go[2];
