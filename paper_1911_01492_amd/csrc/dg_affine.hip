@@ -404,18 +404,48 @@ __global__ __launch_bounds__(256) void k_bj_setup(MeshArgs<double> m, double* __
 // Q_y, Q_x.  TV: vector type (double / float), TQ: type of the stored Q, l.
 // UPD: first the CG residual update r -= lambda q with lambda = rho[par] / pq
 // from the solver state (r is rewritten), so that the update and the
-// preconditioner take one pass over the residual.
-template <int N, typename TV, typename TQ, bool UPD>
+// preconditioner take one pass over the residual.  FUSED (with UPD): pq is
+// summed here from the apply's nbA partials (partA) by every block in the
+// same order, so all blocks obtain the same lambda; block 0 records pq and
+// the pending x update, or stops the solve on a breakdown (no block writes a
+// state field that another block of this kernel reads).
+template <int N, typename TV, typename TQ, bool UPD, bool FUSED>
 __global__ __launch_bounds__(kBlock) void k_bj_apply(int64_t E, const TQ* __restrict__ Q, const TQ* __restrict__ lam,
                                                      TV* __restrict__ r, TV* __restrict__ z, double* partials,
-                                                     const int* skip, const TV* __restrict__ q, const CgState* st,
-                                                     int par) {
+                                                     const int* skip, const TV* __restrict__ q, CgState* st,
+                                                     int par, const double* partA, int64_t nbA) {
   constexpr int NN = N * N, EPB = elems_per_block(N), PE = Lay<N, TV>::PE;
   __shared__ TV sT[EPB * PE];
   __shared__ TQ sQ[EPB][3 * NN], sL[EPB][3 * N];
   __shared__ double red[kBlock / 64];
   if (skip != nullptr && *skip) return;
-  const double lamb = UPD ? st->rho[par] / st->pq : 0.0;
+  double lamb = 0.0;
+  if constexpr (FUSED) {
+    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+    if (st->done) {
+      if (lead) st->xpend = 0;
+      return;
+    }
+    double t[1];
+    sum_partials<1, kBlock>(partA, nbA, t);
+    const double pq = t[0];
+    lamb = st->rho[par] / pq;
+    if (!(pq > 0.0) || !(lamb == lamb && lamb - lamb == 0.0)) {  // not positive, or lambda not finite
+      if (lead) {
+        st->pq = pq;
+        st->xpend = 0;
+        st->breakdown = 1;
+        st->done = 1;
+      }
+      return;
+    }
+    if (lead) {
+      st->pq = pq;
+      st->xpend = 1;
+    }
+  } else if constexpr (UPD) {
+    lamb = st->rho[par] / st->pq;
+  }
   const int tid = threadIdx.x, el = tid / NN, t = tid % NN, t1 = t % N, t2 = t / N;
   const int64_t e = (int64_t)blockIdx.x * EPB + el;
   const bool act = el < EPB && e < E;
@@ -895,33 +925,40 @@ hipError_t launch_bj_setup(int n, const MeshArgs<double>& m, double* Q, double* 
 }
 template <int N, typename TV, typename TQ>
 static hipError_t run_bj_apply(int64_t E, const TQ* Q, const TQ* lam, TV* r, TV* z, double* partials,
-                               const int* skip, const TV* q, const CgState* st, int par, hipStream_t s) {
-  if (q != nullptr)
-    hipLaunchKernelGGL((k_bj_apply<N, TV, TQ, true>), dim3((unsigned)element_blocks(N, E)), dim3(kBlock), 0, s, E, Q,
-                       lam, r, z, partials, skip, q, st, par);
+                               const int* skip, const TV* q, CgState* st, int par, const double* partA, int64_t nbA,
+                               hipStream_t s) {
+  const dim3 grid((unsigned)element_blocks(N, E));
+  if (q != nullptr && partA != nullptr)
+    hipLaunchKernelGGL((k_bj_apply<N, TV, TQ, true, true>), grid, dim3(kBlock), 0, s, E, Q, lam, r, z, partials,
+                       skip, q, st, par, partA, nbA);
+  else if (q != nullptr)
+    hipLaunchKernelGGL((k_bj_apply<N, TV, TQ, true, false>), grid, dim3(kBlock), 0, s, E, Q, lam, r, z, partials,
+                       skip, q, st, par, partA, nbA);
   else
-    hipLaunchKernelGGL((k_bj_apply<N, TV, TQ, false>), dim3((unsigned)element_blocks(N, E)), dim3(kBlock), 0, s, E, Q,
-                       lam, r, z, partials, skip, q, st, par);
+    hipLaunchKernelGGL((k_bj_apply<N, TV, TQ, false, false>), grid, dim3(kBlock), 0, s, E, Q, lam, r, z, partials,
+                       skip, q, st, par, partA, nbA);
   return hipGetLastError();
 }
 template <typename TV, typename TQ>
 hipError_t launch_bj_apply(int n, int64_t E, const TQ* Q, const TQ* lam, TV* r, TV* z, double* partials,
-                           const int* skip, hipStream_t s, const TV* q, const CgState* st, int par) {
+                           const int* skip, hipStream_t s, const TV* q, CgState* st, int par, const double* partA,
+                           int64_t nbA) {
   switch (n) {
-    case 2: return run_bj_apply<2, TV, TQ>(E, Q, lam, r, z, partials, skip, q, st, par, s);
-    case 3: return run_bj_apply<3, TV, TQ>(E, Q, lam, r, z, partials, skip, q, st, par, s);
-    case 4: return run_bj_apply<4, TV, TQ>(E, Q, lam, r, z, partials, skip, q, st, par, s);
-    case 5: return run_bj_apply<5, TV, TQ>(E, Q, lam, r, z, partials, skip, q, st, par, s);
-    case 6: return run_bj_apply<6, TV, TQ>(E, Q, lam, r, z, partials, skip, q, st, par, s);
-    case 7: return run_bj_apply<7, TV, TQ>(E, Q, lam, r, z, partials, skip, q, st, par, s);
-    case 8: return run_bj_apply<8, TV, TQ>(E, Q, lam, r, z, partials, skip, q, st, par, s);
+    case 2: return run_bj_apply<2, TV, TQ>(E, Q, lam, r, z, partials, skip, q, st, par, partA, nbA, s);
+    case 3: return run_bj_apply<3, TV, TQ>(E, Q, lam, r, z, partials, skip, q, st, par, partA, nbA, s);
+    case 4: return run_bj_apply<4, TV, TQ>(E, Q, lam, r, z, partials, skip, q, st, par, partA, nbA, s);
+    case 5: return run_bj_apply<5, TV, TQ>(E, Q, lam, r, z, partials, skip, q, st, par, partA, nbA, s);
+    case 6: return run_bj_apply<6, TV, TQ>(E, Q, lam, r, z, partials, skip, q, st, par, partA, nbA, s);
+    case 7: return run_bj_apply<7, TV, TQ>(E, Q, lam, r, z, partials, skip, q, st, par, partA, nbA, s);
+    case 8: return run_bj_apply<8, TV, TQ>(E, Q, lam, r, z, partials, skip, q, st, par, partA, nbA, s);
   }
   return hipErrorInvalidValue;
 }
 template hipError_t launch_bj_apply<double, double>(int, int64_t, const double*, const double*, double*, double*,
-                                                    double*, const int*, hipStream_t, const double*, const CgState*,
-                                                    int);
+                                                    double*, const int*, hipStream_t, const double*, CgState*, int,
+                                                    const double*, int64_t);
 template hipError_t launch_bj_apply<float, float>(int, int64_t, const float*, const float*, float*, float*, double*,
-                                                  const int*, hipStream_t, const float*, const CgState*, int);
+                                                  const int*, hipStream_t, const float*, CgState*, int,
+                                                  const double*, int64_t);
 
 }  // namespace dg

@@ -950,11 +950,25 @@ int pcg64_block(dg_ctx* c, const dg_cg_opts* o, const double* b, double* x, int 
   CgState hs;
   int rc = read_state(c, 0, hs, s);
   if (rc != DG_OK) return rc;
+  // few block partials: the block apply and the direction update sum them
+  // themselves (no finish kernels)
+  const int64_t nbA = apply_partials(c);
+  const bool fused = nbA <= 4096 && nbj <= 4096;
+  double* partA = c->partials;
+  double* partB = c->partials + nbA;
   int it = 0;
   while (!hs.done && it < maxit) {
     const int chunk = std::min(check, maxit - it);
     for (int j = 0; j < chunk; ++j, ++it) {
       const int par = it & 1;
+      if (fused) {
+        HIP_TRY(c, apply_any(c, DG_F64, o->transpose, 1, c->p64, c->q64, nullptr, 0, &st->done, s, partA));
+        HIP_TRY(c, (launch_bj_apply<double, double>(c->n, c->E, c->bjQ64, c->bjL64, c->r64, c->z64, partB, nullptr, s,
+                                                    c->q64, st, par, partA, nbA)));
+        HIP_TRY(c, (launch_cg_pupdate_fused<double, double, double, double>(n, x, c->z64, c->p64, nullptr, par, st,
+                                                                            partB, s, nbj)));
+        continue;
+      }
       HIP_TRY(c, apply_any(c, DG_F64, o->transpose, 1, c->p64, c->q64, st, par, &st->done, s));
       // r -= lambda q and z = P r in one element pass, then FIN_UPDATE on {<z, r>, <r, r>}
       HIP_TRY(c, (launch_bj_apply<double, double>(c->n, c->E, c->bjQ64, c->bjL64, c->r64, c->z64, c->partials,
@@ -1053,6 +1067,7 @@ int pcg_inner(dg_ctx* c, const dg_cg_opts* o, int prec, bool fresh, double inner
   // few block partials: the update kernels sum them themselves (no finish kernels)
   const int64_t nbA = apply_partials(c);
   const bool fused = !blk && nbA <= 4096 && 2 * vec_blocks(n) <= 8192;
+  const bool fused_blk = blk && nbA <= 4096 && nbj <= 4096;
   double* partA = c->partials;
   double* partB = c->partials + nbA;
   int it = 0;
@@ -1060,6 +1075,14 @@ int pcg_inner(dg_ctx* c, const dg_cg_opts* o, int prec, bool fresh, double inner
     const int chunk = std::min(check, maxit - it);
     for (int j = 0; j < chunk; ++j, ++it) {
       const int par = (par0 + it) & 1;
+      if (fused_blk) {  // as pcg64_block, on the FP32 inner vectors
+        HIP_TRY(c, apply_any(c, prec, o->transpose, 1, p, c->q32, nullptr, 0, &st->done, s, partA));
+        HIP_TRY(c, (launch_bj_apply<float, float>(c->n, c->E, c->bjQ32, c->bjL32, c->r32, c->z32, partB, nullptr, s,
+                                                  c->q32, st, par, partA, nbA)));
+        HIP_TRY(c, (launch_cg_pupdate_fused<float, float, TP, float>(n, c->d32, c->z32, p, nullptr, par, st, partB, s,
+                                                                     nbj)));
+        continue;
+      }
       if (blk) {  // as pcg64_block, on the FP32 inner vectors
         HIP_TRY(c, apply_any(c, prec, o->transpose, 1, p, c->q32, st, par, &st->done, s));
         HIP_TRY(c, (launch_bj_apply<float, float>(c->n, c->E, c->bjQ32, c->bjL32, c->r32, c->z32, c->partials,

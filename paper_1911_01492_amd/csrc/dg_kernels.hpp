@@ -55,10 +55,14 @@ hipError_t launch_apply_affine_multi(int n, int prec, int trans, int nrhs, const
 // q != nullptr: first r -= (rho[par] / pq) q from st (r rewritten), the CG update
 hipError_t launch_bj_setup(int n, const MeshArgs<double>& m, double* Q, double* lam, float* Q32, float* lam32,
                            hipStream_t s);
+// partA != nullptr (with q): the CG update sums the apply's nbA partials of
+// <p, q> itself (every block, in the same order) instead of reading st->pq
+// from a finish kernel, records pq and the pending x update in st, and stops
+// the solve on a breakdown (the counterpart of launch_cg_update_fused)
 template <typename TV, typename TQ>
 hipError_t launch_bj_apply(int n, int64_t E, const TQ* Q, const TQ* lam, TV* r, TV* z, double* partials,
-                           const int* skip, hipStream_t s, const TV* q = nullptr, const CgState* st = nullptr,
-                           int par = 0);
+                           const int* skip, hipStream_t s, const TV* q = nullptr, CgState* st = nullptr,
+                           int par = 0, const double* partA = nullptr, int64_t nbA = 0);
 // FIN_UPDATE on {<z, r>, <r, r>} partials (rho[par^1], rr, iteration count, convergence)
 hipError_t launch_update_finish(const double* partials, int64_t nb, CgState* st, int par, hipStream_t s);
 // st->rho[idx] = <z, r> from the block-Jacobi partials (nothing once the solve stopped)
@@ -126,9 +130,11 @@ hipError_t launch_cg2_update(int64_t n, double* x, double* r, double* z, double*
 template <typename TV, typename TD>
 hipError_t launch_cg_update_fused(int64_t n, TV* r, const TV* q, const TD* dinv, int par, CgState* st,
                                   const double* partA, int64_t nbA, double* partB, hipStream_t s);
+// nbB: number of {<z, r>, <r, r>} partial pairs in partB (< 0: those of
+// launch_cg_update_fused, one per vector block)
 template <typename TX, typename TV, typename TP, typename TD>
 hipError_t launch_cg_pupdate_fused(int64_t n, TX* x, const TV* r, TP* p, const TD* dinv, int par, CgState* st,
-                                   const double* partB, hipStream_t s);
+                                   const double* partB, hipStream_t s, int64_t nbB = -1);
 hipError_t launch_cg2_finish(const double* partA, int64_t nbA, const double* partB, int64_t nbB, CgState* st,
                              int mode, hipStream_t s);
 hipError_t launch_dc_replace(int64_t n, const double* b, const double* q, const float* dinv, float* r32,

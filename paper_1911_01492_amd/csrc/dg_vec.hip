@@ -600,14 +600,15 @@ hipError_t launch_cg_update_fused(int64_t n, TV* r, const TV* q, const TD* dinv,
 }
 template <typename TX, typename TV, typename TP, typename TD>
 hipError_t launch_cg_pupdate_fused(int64_t n, TX* x, const TV* r, TP* p, const TD* dinv, int par, CgState* st,
-                                   const double* partB, hipStream_t s) {
+                                   const double* partB, hipStream_t s, int64_t nbB) {
   const int64_t nb = vec_blocks(n);
+  if (nbB < 0) nbB = nb;
   if (seq_form<TV>(n))
     hipLaunchKernelGGL((k_cg_pupdate_fused<TX, TV, TP, TD, true>), dim3((unsigned)nb), dim3(kBlock), 0, s, n, x, r,
-                       p, dinv, par, st, partB, nb);
+                       p, dinv, par, st, partB, nbB);
   else
     hipLaunchKernelGGL((k_cg_pupdate_fused<TX, TV, TP, TD, false>), dim3((unsigned)nb), dim3(kBlock), 0, s, n, x,
-                       r, p, dinv, par, st, partB, nb);
+                       r, p, dinv, par, st, partB, nbB);
   return hipGetLastError();
 }
 template hipError_t launch_cg_update_fused<double, double>(int64_t, double*, const double*, const double*, int,
@@ -616,13 +617,13 @@ template hipError_t launch_cg_update_fused<float, float>(int64_t, float*, const 
                                                          const double*, int64_t, double*, hipStream_t);
 template hipError_t launch_cg_pupdate_fused<double, double, double, double>(int64_t, double*, const double*, double*,
                                                                             const double*, int, CgState*,
-                                                                            const double*, hipStream_t);
+                                                                            const double*, hipStream_t, int64_t);
 template hipError_t launch_cg_pupdate_fused<float, float, float, float>(int64_t, float*, const float*, float*,
                                                                        const float*, int, CgState*, const double*,
-                                                                       hipStream_t);
+                                                                       hipStream_t, int64_t);
 template hipError_t launch_cg_pupdate_fused<float, float, uint16_t, float>(int64_t, float*, const float*, uint16_t*,
                                                                           const float*, int, CgState*,
-                                                                          const double*, hipStream_t);
+                                                                          const double*, hipStream_t, int64_t);
 
 // explicit instantiations used by the host solvers
 template hipError_t launch_cg_init<double, double, double, double>(int64_t, const double*, const double*,
