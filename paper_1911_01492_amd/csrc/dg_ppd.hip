@@ -94,10 +94,20 @@ __global__ __launch_bounds__(apply_block(N)) void k_apply_ppd(MeshArgs<TC> m, co
   // padding lanes repeat the work of the brick's last element lane for lane
   // (same values to the same LDS words, in the same wavefront)
   static_assert(TE * NN == BLOCK || BLOCK - (TE - 1) * NN <= 64, "padding lanes and their twins share a wavefront");
+  // per element, lower and upper side each: x-face rows X, y-face jumps, z-face rows X, z-face jumps.
+  // The z-face rows live only inside the Z phase: where moving them into the
+  // element's face-scalar slot (free once the Z face scalars have been read,
+  // at the cost of one or two more barriers) lets one more workgroup fit in a
+  // CU's LDS, they go there (ZR_IN_F) and sP keeps six rows
+  constexpr size_t LDS_BASE = (3 * TE * PE + (F_IN_S2 ? 1 : TE * 4 * NN) + NN) * sizeof(TC) + BLOCK / 64 * 8;
+  constexpr size_t LDS_CU = 160 * 1024, MAX_WG = 32 / (BLOCK / 64);  // a CU holds at most 32 waves
+  constexpr size_t WG6 = LDS_CU / (LDS_BASE + TE * 6 * NN * sizeof(TC)), WG8 = LDS_CU / (LDS_BASE + TE * 8 * NN * sizeof(TC));
+  constexpr bool ZR_IN_F = (WG6 < MAX_WG ? WG6 : MAX_WG) > (WG8 < MAX_WG ? WG8 : MAX_WG);
+  constexpr int PR = ZR_IN_F ? 6 : 8;  // rows per element in sP
+  constexpr int JZ = ZR_IN_F ? 4 : 6;  // first z-face jump row
   __shared__ TC sS1[TE * PE], sS2[TE * PE], sS3[TE * PE];
   __shared__ TC sFx[F_IN_S2 ? 1 : TE * 4 * NN];
-  // per element, lower and upper side each: x-face rows X, y-face jumps, z-face rows X, z-face jumps
-  __shared__ TC sP[TE * 8 * NN];
+  __shared__ TC sP[TE * PR * NN];
   __shared__ TC sC[NN];  // C, row-major, for lane-indexed rows
   __shared__ double red[BLOCK / 64];
   if (skip != nullptr && *skip) return;
@@ -132,7 +142,8 @@ __global__ __launch_bounds__(apply_block(N)) void k_apply_ppd(MeshArgs<TC> m, co
   TC* S2 = sS2 + el * PE;
   TC* S3 = sS3 + el * PE;
   TC* Fe = F + el * FS;
-  TC* P = sP + el * 8 * NN;
+  TC* P = sP + el * PR * NN;
+  TC* ZR = ZR_IN_F ? Fe : P + 4 * NN;  // the element's z-face rows: lower side, then upper side
   if (tid < NN) sC[tid] = tabs().Cd[(tid / N) * kMaxN + tid % N];
   const int64_t e = c[0] + (int64_t)m.nx * (c[1] + (int64_t)m.ny * c[2]);
   const uint32_t eo = (uint32_t)e * (uint32_t)N3;  // the element's first entry (N_dof < 2^31)
@@ -219,10 +230,12 @@ __global__ __launch_bounds__(apply_block(N)) void k_apply_ppd(MeshArgs<TC> m, co
     mass_line<N, TC, false>(T, v, r);
     const TC Xlo = K * u[0] - TC(2) * GL * tr[0], Xhi = K * u[N - 1] - TC(2) * GH * tr[1];
     const TC jzl = GL * (u[0] - tr[0]), jzh = GH * (tr[1] - u[N - 1]);
-    P[4 * NN + t] = Xlo;  // z-face rows and jumps at (x, y) = (t1, t2)
-    P[5 * NN + t] = Xhi;
-    P[6 * NN + t] = jzl;
-    P[7 * NN + t] = jzh;
+    if constexpr (!ZR_IN_F) {  // z-face rows and jumps at (x, y) = (t1, t2)
+      ZR[t] = Xlo;
+      ZR[NN + t] = Xhi;
+    }
+    P[JZ * NN + t] = jzl;
+    P[(JZ + 1) * NN + t] = jzh;
     TC p[N];
     lds_get<N, 2>(S3, t1, t2, v);
     cd_line<N, TC>(T, v, p);  // P_yz = C_z c_y + ...
@@ -231,14 +244,21 @@ __global__ __launch_bounds__(apply_block(N)) void k_apply_ppd(MeshArgs<TC> m, co
     for (int i = 0; i < N; ++i) w[i] *= K2;
     w[N - 1] += Xhi;
     w[0] -= Xlo;
-    if (F_IN_S2) __syncthreads();  // the face scalars in S2 have been read; the z-face rows are published
+    // the face scalars (in S2 or in their own slots) have been read; the
+    // z-face rows are published
+    if (F_IN_S2 || ZR_IN_F) __syncthreads();
     else lds_sync<ELEM>();
+    if constexpr (ZR_IN_F) {  // into the face-scalar slot, free from here on
+      ZR[t] = Xlo;
+      ZR[NN + t] = Xhi;
+      lds_sync<ELEM>();
+    }
     TC sh = TC(0), sl = TC(0);  // z-face rows contracted along y, at y = t2
 #pragma unroll
     for (int j = 0; j < N; ++j) {
       const TC cj = sC[t2 * N + j];
-      sh += cj * P[5 * NN + t1 + N * j];
-      sl += cj * P[4 * NN + t1 + N * j];
+      sh += cj * ZR[NN + t1 + N * j];
+      sl += cj * ZR[t1 + N * j];
     }
     p[N - 1] += sh;
     p[0] -= sl;
@@ -249,6 +269,7 @@ __global__ __launch_bounds__(apply_block(N)) void k_apply_ppd(MeshArgs<TC> m, co
       p[N - 1] += P[2 * NN + t1 + N * (N - 1)] - jzh;
       p[0] -= P[2 * NN + t1] + jzl;
     }
+    if constexpr (ZR_IN_F && F_IN_S2) lds_sync<ELEM>();  // the rows in S2 have been read
     lds_put<N, 2>(S2, t1, t2, b);
     lds_put<N, 2>(S1, t1, t2, p);  // the thread's own z-lines of S1 and S3 were read above
     lds_put<N, 2>(S3, t1, t2, w);
@@ -273,11 +294,11 @@ __global__ __launch_bounds__(apply_block(N)) void k_apply_ppd(MeshArgs<TC> m, co
     p[N - 1] += sh;
     p[0] -= sl;
     if (t2 == N - 1) {  // edges of the (x, z) plane: own x-face jumps, z-face jumps at x = 0 / n-1
-      p[N - 1] += jxh + P[7 * NN + (N - 1) + N * t1];
-      p[0] += jxl - P[7 * NN + N * t1];
+      p[N - 1] += jxh + P[(JZ + 1) * NN + (N - 1) + N * t1];
+      p[0] += jxl - P[(JZ + 1) * NN + N * t1];
     } else if (t2 == 0) {
-      p[N - 1] += P[6 * NN + (N - 1) + N * t1] - jxh;
-      p[0] -= jxl + P[6 * NN + N * t1];
+      p[N - 1] += P[JZ * NN + (N - 1) + N * t1] - jxh;
+      p[0] -= jxl + P[JZ * NN + N * t1];
     }
 #pragma unroll
     for (int i = 0; i < N; ++i) w[i] += gxz * p[i];
