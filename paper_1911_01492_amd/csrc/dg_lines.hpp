@@ -40,35 +40,40 @@ __device__ __forceinline__ int64_t neighbour(const MeshArgs<T>& m, int ex, int e
 // one LDS pass (16 lanes for 8-byte words, 32 lanes for 4-byte words) should
 // hit distinct banks.  Offsets are affine, i1 + P2 i2 + P3 i3 (element stride
 // PE), so that every access is a per-thread base plus an immediate; the
-// paddings come from an exhaustive search over small values.
-template <int N, typename TC>
+// paddings come from an exhaustive search over small values.  V = 1 is a
+// denser variant for kernels whose occupancy the LDS limits (the
+// parallelepiped apply in FP64): n = 4 with element stride 74 (the same
+// modelled conflicts), n = 7 unpadded (slab stride 49, element stride 343;
+// 6% more).
+template <int N, typename TC, int V = 0>
 struct Lay {
   static constexpr bool f64 = sizeof(TC) == 8;
+  static constexpr bool dense = V == 1 && f64 && (N == 4 || N == 7);
   static constexpr int P2 = N == 6 ? (f64 ? 6 : 7) : N == 8 ? 9 : N;
-  static constexpr int P3 = N == 2 ? 5 : N == 4 ? 19 : N == 6 ? (f64 ? 39 : 42) : N == 7 ? (f64 ? 52 : 56) :
-                            N == 8 ? 72 : N * N;
-  static constexpr int PE = N == 2 ? 12 : N == 4 ? 76 : N == 6 ? (f64 ? 244 : 252) :
-                            N == 7 ? (f64 ? 369 : 401) : N == 8 ? 576 : N * N * N;
+  static constexpr int P3 = N == 2 ? 5 : N == 4 ? 19 : N == 6 ? (f64 ? 39 : 42) :
+                            N == 7 ? (dense ? 49 : f64 ? 52 : 56) : N == 8 ? 72 : N * N;
+  static constexpr int PE = N == 2 ? 12 : N == 4 ? (dense ? 74 : 76) : N == 6 ? (f64 ? 244 : 252) :
+                            N == 7 ? (dense ? 343 : f64 ? 369 : 401) : N == 8 ? 576 : N * N * N;
   __device__ static __forceinline__ int off(int i1, int i2, int i3) { return i1 + P2 * i2 + P3 * i3; }
 };
 
 // LDS offset of value i of the line along axis D at tangential (t1, t2)
-template <int N, int D, typename TC>
+template <int N, int D, typename TC, int V = 0>
 __device__ __forceinline__ int lds_idx(int t1, int t2, int i) {
-  if constexpr (D == 0) return Lay<N, TC>::off(i, t1, t2);
-  else if constexpr (D == 1) return Lay<N, TC>::off(t1, i, t2);
-  else return Lay<N, TC>::off(t1, t2, i);
+  if constexpr (D == 0) return Lay<N, TC, V>::off(i, t1, t2);
+  else if constexpr (D == 1) return Lay<N, TC, V>::off(t1, i, t2);
+  else return Lay<N, TC, V>::off(t1, t2, i);
 }
 
-template <int N, int D, typename TC>
+template <int N, int D, typename TC, int V = 0>
 __device__ __forceinline__ void lds_get(const TC* tile, int t1, int t2, TC (&v)[N]) {
 #pragma unroll
-  for (int i = 0; i < N; ++i) v[i] = tile[lds_idx<N, D, TC>(t1, t2, i)];
+  for (int i = 0; i < N; ++i) v[i] = tile[lds_idx<N, D, TC, V>(t1, t2, i)];
 }
-template <int N, int D, typename TC>
+template <int N, int D, typename TC, int V = 0>
 __device__ __forceinline__ void lds_put(TC* tile, int t1, int t2, const TC (&v)[N]) {
 #pragma unroll
-  for (int i = 0; i < N; ++i) tile[lds_idx<N, D, TC>(t1, t2, i)] = v[i];
+  for (int i = 0; i < N; ++i) tile[lds_idx<N, D, TC, V>(t1, t2, i)] = v[i];
 }
 // global line load; the element offset is a 32-bit index (the library limits
 // N_dof below 2^31), so the address is a scalar base plus a 32-bit offset.

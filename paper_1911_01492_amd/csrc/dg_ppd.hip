@@ -82,7 +82,8 @@ __global__ __launch_bounds__(apply_block(N)) void k_apply_ppd(MeshArgs<TC> m, co
                                                               const int* skip) {
   constexpr int NN = N * N, N3 = NN * N;
   constexpr int BX = tile_x(N), BY = tile_y(N), BZ = tile_z(N), TE = BX * BY * BZ;
-  constexpr int PE = Lay<N, TC>::PE;
+  constexpr int LV = 1;  // the denser tile layout: LDS bounds this kernel's occupancy
+  constexpr int PE = Lay<N, TC, LV>::PE;
   constexpr bool F_IN_S2 = 4 * NN <= PE;
   constexpr int FS = F_IN_S2 ? PE : 4 * NN;
   constexpr int BLOCK = apply_block(N);
@@ -158,7 +159,7 @@ __global__ __launch_bounds__(apply_block(N)) void k_apply_ppd(MeshArgs<TC> m, co
     const TC GL = gco(0), GH = gco(1);
     face_phase<N, 0, BX, BY, BZ, FS, TC, TIN, false, OFF32>(m, T, x, own, eo, c, o, Nd, t, t1, t2, F, Fe, K, GL, GH,
                                                             TC(0), b, u, tr);
-    lds_put<N, 0>(S1, t1, t2, b);
+    lds_put<N, 0, TC, LV>(S1, t1, t2, b);
     P[0 * NN + t] = K * u[0] - TC(2) * GL * tr[0];
     P[1 * NN + t] = K * u[N - 1] - TC(2) * GH * tr[1];
     jxl = GL * (u[0] - tr[0]);
@@ -171,7 +172,7 @@ __global__ __launch_bounds__(apply_block(N)) void k_apply_ppd(MeshArgs<TC> m, co
     const TC GL = gco(2), GH = gco(3);
     face_phase<N, 1, BX, BY, BZ, FS, TC, TIN, false, OFF32>(m, T, x, own, eo, c, o, Nd, t, t1, t2, F, Fe, K, GL, GH,
                                                             TC(0), b, u, tr);
-    lds_get<N, 1>(S1, t1, t2, v);
+    lds_get<N, 1, TC, LV>(S1, t1, t2, v);
     mass_line<N, TC, false>(T, v, w);
     cd_line<N, TC>(T, u, v);
 #pragma unroll
@@ -181,20 +182,20 @@ __global__ __launch_bounds__(apply_block(N)) void k_apply_ppd(MeshArgs<TC> m, co
     P[2 * NN + t] = GL * (u[0] - tr[0]);  // y-face jumps at (x, z) = (t1, t2)
     P[3 * NN + t] = GH * (tr[1] - u[N - 1]);
     if (F_IN_S2) __syncthreads();  // the face scalars in S2 have been read
-    lds_put<N, 1>(S2, t1, t2, b);
-    lds_put<N, 1>(S1, t1, t2, w);
-    lds_put<N, 1>(S3, t1, t2, v);
+    lds_put<N, 1, TC, LV>(S2, t1, t2, b);
+    lds_put<N, 1, TC, LV>(S1, t1, t2, w);
+    lds_put<N, 1, TC, LV>(S3, t1, t2, v);
   }
   lds_sync<ELEM>();
   // ---------------- X2: S1 <- S1 + M_x S2 + G_xy P_xy,  P_xy = C_x c_y + C_y (x-face rows) + corners
   {
     const Tables<TC>& T = tabs();
-    lds_get<N, 0>(S2, t1, t2, v);
-    lds_get<N, 0>(S1, t1, t2, w);
+    lds_get<N, 0, TC, LV>(S2, t1, t2, v);
+    lds_get<N, 0, TC, LV>(S1, t1, t2, w);
     mass_line<N, TC, false>(T, v, b);
 #pragma unroll
     for (int i = 0; i < N; ++i) w[i] += b[i];
-    lds_get<N, 0>(S3, t1, t2, v);
+    lds_get<N, 0, TC, LV>(S3, t1, t2, v);
     TC p[N];
     cd_line<N, TC>(T, v, p);
     TC sh = TC(0), sl = TC(0);  // x-face rows contracted along y, at y = t1
@@ -215,7 +216,7 @@ __global__ __launch_bounds__(apply_block(N)) void k_apply_ppd(MeshArgs<TC> m, co
     }
 #pragma unroll
     for (int i = 0; i < N; ++i) w[i] += gxy * p[i];
-    lds_put<N, 0>(S1, t1, t2, w);
+    lds_put<N, 0, TC, LV>(S1, t1, t2, w);
   }
   lds_sync<ELEM>();
   // ---------------- Z: b_z -> S2, r = M_z S1, P_yz -> S1, c_z -> S3, z-face rows and jumps
@@ -226,7 +227,7 @@ __global__ __launch_bounds__(apply_block(N)) void k_apply_ppd(MeshArgs<TC> m, co
     const TC cr = m.R ? m.R[e] * m.vol : TC(0);
     face_phase<N, 2, BX, BY, BZ, FS, TC, TIN, false, OFF32>(m, T, x, own, eo, c, o, Nd, t, t1, t2, F, Fe, K, GL, GH,
                                                             cr, b, u, tr);
-    lds_get<N, 2>(S1, t1, t2, v);
+    lds_get<N, 2, TC, LV>(S1, t1, t2, v);
     mass_line<N, TC, false>(T, v, r);
     const TC Xlo = K * u[0] - TC(2) * GL * tr[0], Xhi = K * u[N - 1] - TC(2) * GH * tr[1];
     const TC jzl = GL * (u[0] - tr[0]), jzh = GH * (tr[1] - u[N - 1]);
@@ -237,7 +238,7 @@ __global__ __launch_bounds__(apply_block(N)) void k_apply_ppd(MeshArgs<TC> m, co
     P[JZ * NN + t] = jzl;
     P[(JZ + 1) * NN + t] = jzh;
     TC p[N];
-    lds_get<N, 2>(S3, t1, t2, v);
+    lds_get<N, 2, TC, LV>(S3, t1, t2, v);
     cd_line<N, TC>(T, v, p);  // P_yz = C_z c_y + ...
     cd_line<N, TC>(T, u, w);  // c_z
 #pragma unroll
@@ -270,18 +271,18 @@ __global__ __launch_bounds__(apply_block(N)) void k_apply_ppd(MeshArgs<TC> m, co
       p[0] -= P[2 * NN + t1] + jzl;
     }
     if constexpr (ZR_IN_F && F_IN_S2) lds_sync<ELEM>();  // the rows in S2 have been read
-    lds_put<N, 2>(S2, t1, t2, b);
-    lds_put<N, 2>(S1, t1, t2, p);  // the thread's own z-lines of S1 and S3 were read above
-    lds_put<N, 2>(S3, t1, t2, w);
+    lds_put<N, 2, TC, LV>(S2, t1, t2, b);
+    lds_put<N, 2, TC, LV>(S1, t1, t2, p);  // the thread's own z-lines of S1 and S3 were read above
+    lds_put<N, 2, TC, LV>(S3, t1, t2, w);
   }
   lds_sync<ELEM>();
   // ---------------- X3: S2 <- M_x S2 + G_xz P_xz (P_xz = C_x c_z + C_z (x-face rows) + corners),
   //                      S1 <- G_yz M_x S1
   {
     const Tables<TC>& T = tabs();
-    lds_get<N, 0>(S2, t1, t2, v);
+    lds_get<N, 0, TC, LV>(S2, t1, t2, v);
     mass_line<N, TC, false>(T, v, w);
-    lds_get<N, 0>(S3, t1, t2, v);
+    lds_get<N, 0, TC, LV>(S3, t1, t2, v);
     TC p[N];
     cd_line<N, TC>(T, v, p);
     TC sh = TC(0), sl = TC(0);  // x-face rows contracted along z, at z = t2
@@ -302,26 +303,26 @@ __global__ __launch_bounds__(apply_block(N)) void k_apply_ppd(MeshArgs<TC> m, co
     }
 #pragma unroll
     for (int i = 0; i < N; ++i) w[i] += gxz * p[i];
-    lds_put<N, 0>(S2, t1, t2, w);
-    lds_get<N, 0>(S1, t1, t2, v);
+    lds_put<N, 0, TC, LV>(S2, t1, t2, w);
+    lds_get<N, 0, TC, LV>(S1, t1, t2, v);
     mass_line<N, TC, false>(T, v, w);
 #pragma unroll
     for (int i = 0; i < N; ++i) w[i] *= gyz;
-    lds_put<N, 0>(S1, t1, t2, w);
+    lds_put<N, 0, TC, LV>(S1, t1, t2, w);
   }
   lds_sync<ELEM>();
   // ---------------- Y3: S2 <- M_y S2
   {
     const Tables<TC>& T = tabs();
-    lds_get<N, 1>(S2, t1, t2, v);
+    lds_get<N, 1, TC, LV>(S2, t1, t2, v);
     mass_line<N, TC, false>(T, v, w);
-    lds_put<N, 1>(S2, t1, t2, w);
+    lds_put<N, 1, TC, LV>(S2, t1, t2, w);
   }
   lds_sync<ELEM>();
   // ---------------- Z2: y = r + S2 + S1
   double part = 0.0;
-  lds_get<N, 2>(S2, t1, t2, v);
-  lds_get<N, 2>(S1, t1, t2, w);
+  lds_get<N, 2, TC, LV>(S2, t1, t2, v);
+  lds_get<N, 2, TC, LV>(S1, t1, t2, w);
   if (act) {
     const uint32_t yb = (eo + (uint32_t)lidx<N, 2>(t1, t2, 0)) * (uint32_t)sizeof(TOUT);
     TOUT* py = y + e * N3;
