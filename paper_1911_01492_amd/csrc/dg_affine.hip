@@ -122,7 +122,10 @@ __global__ __launch_bounds__(apply_block(N), (N == 5 && sizeof(TC) == 8) ? 8 : 1
                                                          const int* skip) {
   constexpr int NN = N * N, N3 = NN * N;
   constexpr int BX = tile_x(N), BY = tile_y(N), BZ = tile_z(N), TE = BX * BY * BZ;
-  constexpr int PE = Lay<N, TC>::PE;
+  // in FP64 at n = 6 the LDS tiles bound the occupancy (five workgroups per
+  // CU): the denser layout (2% more modelled bank conflicts) fits a sixth
+  constexpr int LV = N == 6 ? 1 : 0;
+  constexpr int PE = Lay<N, TC, LV>::PE;
   constexpr bool F_IN_S2 = 4 * NN <= PE;
   constexpr int FS = F_IN_S2 ? PE : 4 * NN;  // element stride of the face-scalar slots
   constexpr int BLOCK = apply_block(N);
@@ -192,28 +195,28 @@ __global__ __launch_bounds__(apply_block(N), (N == 5 && sizeof(TC) == 8) ? 8 : 1
   TC b[N], v[N], w[N];
   // ---------------- X: b_x -> S1
   face_phase<N, 0, BX, BY, BZ, FS, TC, TIN, TRANS, OFF32>(m, tabs(), x, own, eo, c, o, Nd, t, t1, t2, F, Fe, K, gco(0), gco(1), TC(0), b);
-  lds_put<N, 0>(S1, t1, t2, b);
+  lds_put<N, 0, TC, LV>(S1, t1, t2, b);
   lds_sync<XROW>();  // F (read by the x-neighbours) is rewritten by the next phase
   // ---------------- Y: b_y -> S2, M_y b_x -> S1
   face_phase<N, 1, BX, BY, BZ, FS, TC, TIN, TRANS, OFF32>(m, tabs(), x, own, eo, c, o, Nd, t, t1, t2, F, Fe, K, gco(2), gco(3), TC(0), b);
   {
-    lds_get<N, 1>(S1, t1, t2, v);
+    lds_get<N, 1, TC, LV>(S1, t1, t2, v);
     mass_line<N, TC, TRANS>(tabs(), v, w);
   }
   if (F_IN_S2) __syncthreads();  // the face scalars in S2 have been read
   {
-    lds_put<N, 1>(S2, t1, t2, b);
-    lds_put<N, 1>(S1, t1, t2, w);
+    lds_put<N, 1, TC, LV>(S2, t1, t2, b);
+    lds_put<N, 1, TC, LV>(S1, t1, t2, w);
   }
   lds_sync<ELEM>();
   // ---------------- X2: M_y b_x + M_x b_y -> S1
   {
-    lds_get<N, 0>(S2, t1, t2, v);
-    lds_get<N, 0>(S1, t1, t2, w);
+    lds_get<N, 0, TC, LV>(S2, t1, t2, v);
+    lds_get<N, 0, TC, LV>(S1, t1, t2, w);
     mass_line<N, TC, TRANS>(tabs(), v, b);
 #pragma unroll
     for (int i = 0; i < N; ++i) w[i] += b[i];
-    lds_put<N, 0>(S1, t1, t2, w);
+    lds_put<N, 0, TC, LV>(S1, t1, t2, w);
   }
   lds_sync<ELEM>();
   // ---------------- Z: b_z -> S2, r = M_z S1
@@ -222,28 +225,28 @@ __global__ __launch_bounds__(apply_block(N), (N == 5 && sizeof(TC) == 8) ? 8 : 1
   face_phase<N, 2, BX, BY, BZ, FS, TC, TIN, TRANS, OFF32>(m, tabs(), x, own, eo, c, o, Nd, t, t1, t2, F, Fe, K, gco(4), gco(5), cr, b,
                                                DOT ? xz : nullptr);
   {
-    lds_get<N, 2>(S1, t1, t2, v);
+    lds_get<N, 2, TC, LV>(S1, t1, t2, v);
     mass_line<N, TC, TRANS>(tabs(), v, r);
   }
   if (F_IN_S2) __syncthreads();
-  lds_put<N, 2>(S2, t1, t2, b);
+  lds_put<N, 2, TC, LV>(S2, t1, t2, b);
   lds_sync<ELEM>();
   // ---------------- X3, Y3: S2 <- M_y M_x S2
   {
-    lds_get<N, 0>(S2, t1, t2, v);
+    lds_get<N, 0, TC, LV>(S2, t1, t2, v);
     mass_line<N, TC, TRANS>(tabs(), v, w);
-    lds_put<N, 0>(S2, t1, t2, w);
+    lds_put<N, 0, TC, LV>(S2, t1, t2, w);
   }
   lds_sync<ELEM>();
   {
-    lds_get<N, 1>(S2, t1, t2, v);
+    lds_get<N, 1, TC, LV>(S2, t1, t2, v);
     mass_line<N, TC, TRANS>(tabs(), v, w);
-    lds_put<N, 1>(S2, t1, t2, w);
+    lds_put<N, 1, TC, LV>(S2, t1, t2, w);
   }
   lds_sync<ELEM>();
   // ---------------- Z2: y = r + S2
   double part = 0.0;
-  lds_get<N, 2>(S2, t1, t2, v);
+  lds_get<N, 2, TC, LV>(S2, t1, t2, v);
   if (act) {
     // y is written once and not read back here: nontemporal stores keep it
     // from displacing in L2 the x lines that neighbouring bricks still read
