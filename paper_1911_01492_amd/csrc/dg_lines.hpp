@@ -46,7 +46,9 @@ __device__ __forceinline__ int64_t neighbour(const MeshArgs<T>& m, int ex, int e
 // conflicts), n = 6 and 7 unpadded (slab strides 36 and 49, element strides
 // 216 and 343; 2% and 6% more), and n = 3 with element stride 36, so that
 // the face-scalar slot (4 n^2) fits in a tile and needs no area of its own
-// (34% more).
+// (34% more).  V = 2, n = 4 in FP64: element stride 80 (no more modelled
+// conflicts), so that two tiles hold an element's 10 n^2 face rows (the
+// trilinear apply).
 template <int N, typename TC, int V = 0>
 struct Lay {
   static constexpr bool f64 = sizeof(TC) == 8;
@@ -54,7 +56,8 @@ struct Lay {
   static constexpr int P2 = N == 6 ? (f64 ? 6 : 7) : N == 8 ? 9 : N;
   static constexpr int P3 = N == 2 ? 5 : N == 4 ? 19 : N == 6 ? (dense ? 36 : f64 ? 39 : 42) :
                             N == 7 ? (dense ? 49 : f64 ? 52 : 56) : N == 8 ? 72 : N * N;
-  static constexpr int PE = N == 2 ? 12 : N == 3 ? (dense ? 36 : 27) : N == 4 ? (dense ? 74 : 76) : N == 6 ? (dense ? 216 : f64 ? 244 : 252) :
+  static constexpr bool roomy = V == 2 && f64 && N == 4;
+  static constexpr int PE = N == 2 ? 12 : N == 3 ? (dense ? 36 : 27) : N == 4 ? (dense ? 74 : roomy ? 80 : 76) : N == 6 ? (dense ? 216 : f64 ? 244 : 252) :
                             N == 7 ? (dense ? 343 : f64 ? 369 : 401) : N == 8 ? 576 : N * N * N;
   __device__ static __forceinline__ int off(int i1, int i2, int i3) { return i1 + P2 * i2 + P3 * i3; }
 };

@@ -64,7 +64,7 @@ __device__ __forceinline__ void corner_of(const MeshArgs<TC>& m, int64_t e, int 
 // lower face it is) is projected as well and its two line scalars per face
 // node go to m.fb for the second pass.  All threads of the block call this
 // (it synchronises); act marks threads owning an element.
-template <int N, int D, typename TC, typename TIN, bool UNIT = false, bool AFF = false, bool PAIR = false>
+template <int N, int D, typename TC, typename TIN, bool UNIT = false, bool AFF = false, bool PAIR = false, int LV = 0>
 __device__ void face_term(const MeshArgs<TC>& m, const Tables<TC>& T, const TIN* __restrict__ x, int64_t e,
                           int ex, int ey, int ez, const TC (&X)[8][3], TC (&Xn)[8][3], TC K, int t1, int t2,
                           TC* Y, TC (*F)[N * N], bool act, int s, const TC* Gc = nullptr) {
@@ -301,11 +301,11 @@ __device__ void face_term(const MeshArgs<TC>& m, const Tables<TC>& T, const TIN*
       }
     }
     TC yl[N];
-    lds_get<N, D>(Y, t1, t2, yl);
+    lds_get<N, D, TC, LV>(Y, t1, t2, yl);
 #pragma unroll
     for (int i = 0; i < N; ++i) yl[i] += dS[i] * z;
     yl[s ? N - 1 : 0] += out;
-    lds_put<N, D>(Y, t1, t2, yl);
+    lds_put<N, D, TC, LV>(Y, t1, t2, yl);
     if (PAIR && nb >= 0) {  // the neighbour's line (t1, t2) along D, added by its second pass
       TC* fbn = m.fb + ((int64_t)nb * 3 + D) * 2 * NN;
       // read once, by the second pass: stored nontemporal
@@ -320,7 +320,7 @@ __device__ void face_term(const MeshArgs<TC>& m, const Tables<TC>& T, const TIN*
 // the input x (see the file header), with coefficient K (and the reaction
 // coefficients of m, if any).  Xs: the element's corner slot in LDS (filled
 // here).  All threads of the block call this (it synchronises).
-template <int N, typename TC, typename TIN, bool AFF = false>
+template <int N, typename TC, typename TIN, bool AFF = false, int LV = 0>
 __device__ void tri_volume(const MeshArgs<TC>& m, const Tables<TC>& T, const TIN* __restrict__ x, int64_t e,
                            bool act, int t, int t1, int t2, TC K, TC (&Xs)[8][3], TC* A, TC* B, TC* C) {
   constexpr int NN = N * N;
@@ -330,39 +330,39 @@ __device__ void tri_volume(const MeshArgs<TC>& m, const Tables<TC>& T, const TIN
     glb_get<N, 2, TC, TIN>(x, e, t1, t2, uz);
     TC a[N];
     contract_eo<N, TC, 1>(T.eB, uz, a);  // phase Z: interpolate along z
-    lds_put<N, 2>(A, t1, t2, a);
+    lds_put<N, 2, TC, LV>(A, t1, t2, a);
   }
   elem_sync<N>();
   const TC (&X)[8][3] = Xs;
   if (act) {  // phase Y
     TC a[N], b[N];
-    lds_get<N, 1>(A, t1, t2, a);
+    lds_get<N, 1, TC, LV>(A, t1, t2, a);
     contract_eo<N, TC, 1>(T.eB, a, b);
-    lds_put<N, 1>(B, t1, t2, b);
+    lds_put<N, 1, TC, LV>(B, t1, t2, b);
   }
   elem_sync<N>();
   if (act) {  // phase X: v and d/dxi_0
     TC a[N], v[N], d1[N];
-    lds_get<N, 0>(B, t1, t2, a);
+    lds_get<N, 0, TC, LV>(B, t1, t2, a);
     contract_eo<N, TC, 1>(T.eB, a, v);
     contract_eo<N, TC, -1>(T.eDg, v, d1);
-    lds_put<N, 0>(A, t1, t2, v);
-    lds_put<N, 0>(C, t1, t2, d1);
+    lds_put<N, 0, TC, LV>(A, t1, t2, v);
+    lds_put<N, 0, TC, LV>(C, t1, t2, d1);
   }
   elem_sync<N>();
   if (act) {  // phase Y': d/dxi_1
     TC v[N], d2[N];
-    lds_get<N, 1>(A, t1, t2, v);
+    lds_get<N, 1, TC, LV>(A, t1, t2, v);
     contract_eo<N, TC, -1>(T.eDg, v, d2);
-    lds_put<N, 1>(B, t1, t2, d2);
+    lds_put<N, 1, TC, LV>(B, t1, t2, d2);
   }
   elem_sync<N>();
   if (act) {  // phase Z': d/dxi_2, geometry, g = G gr, Dg_z^T g_2
     TC d1[N], d2[N], d3[N], wz[N], v[N];
-    lds_get<N, 2>(A, t1, t2, v);
+    lds_get<N, 2, TC, LV>(A, t1, t2, v);
     contract_eo<N, TC, -1>(T.eDg, v, d3);
-    lds_get<N, 2>(C, t1, t2, d1);
-    lds_get<N, 2>(B, t1, t2, d2);
+    lds_get<N, 2, TC, LV>(C, t1, t2, d1);
+    lds_get<N, 2, TC, LV>(B, t1, t2, d2);
     const TC wq12 = T.gw[t1] * T.gw[t2] * K;
     const TC cw12 = m.R ? m.R[e] * T.gw[t1] * T.gw[t2] : TC(0);  // reaction weight
     TC G0[3][3], dJ0 = TC(1);
@@ -416,44 +416,44 @@ __device__ void tri_volume(const MeshArgs<TC>& m, const Tables<TC>& T, const TIN
     contract_eo<N, TC, -1>(T.eDgt, d3, wz);
 #pragma unroll
     for (int q = 0; q < N; ++q) wz[q] += v[q];
-    lds_put<N, 2>(A, t1, t2, wz);
-    lds_put<N, 2>(C, t1, t2, d1);
-    lds_put<N, 2>(B, t1, t2, d2);
+    lds_put<N, 2, TC, LV>(A, t1, t2, wz);
+    lds_put<N, 2, TC, LV>(C, t1, t2, d1);
+    lds_put<N, 2, TC, LV>(B, t1, t2, d2);
   }
   elem_sync<N>();
   if (act) {  // phase Y'': += Dg_y^T g_1
     TC g2[N], w[N], r[N];
-    lds_get<N, 1>(B, t1, t2, g2);
-    lds_get<N, 1>(A, t1, t2, w);
+    lds_get<N, 1, TC, LV>(B, t1, t2, g2);
+    lds_get<N, 1, TC, LV>(A, t1, t2, w);
     contract_eo<N, TC, -1>(T.eDgt, g2, r);
 #pragma unroll
     for (int i = 0; i < N; ++i) w[i] += r[i];
-    lds_put<N, 1>(A, t1, t2, w);
+    lds_put<N, 1, TC, LV>(A, t1, t2, w);
   }
   elem_sync<N>();
   if (act) {  // phase X'': += Dg_x^T g_0, then B_x^T
     TC g1[N], w[N], r[N], o[N];
-    lds_get<N, 0>(C, t1, t2, g1);
-    lds_get<N, 0>(A, t1, t2, w);
+    lds_get<N, 0, TC, LV>(C, t1, t2, g1);
+    lds_get<N, 0, TC, LV>(A, t1, t2, w);
     contract_eo<N, TC, -1>(T.eDgt, g1, r);
 #pragma unroll
     for (int i = 0; i < N; ++i) w[i] += r[i];
     contract_eo<N, TC, 1>(T.eBt, w, o);
-    lds_put<N, 0>(A, t1, t2, o);
+    lds_put<N, 0, TC, LV>(A, t1, t2, o);
   }
   elem_sync<N>();
   if (act) {  // phase Y''': B_y^T
     TC w[N], o[N];
-    lds_get<N, 1>(A, t1, t2, w);
+    lds_get<N, 1, TC, LV>(A, t1, t2, w);
     contract_eo<N, TC, 1>(T.eBt, w, o);
-    lds_put<N, 1>(A, t1, t2, o);
+    lds_put<N, 1, TC, LV>(A, t1, t2, o);
   }
   elem_sync<N>();
   if (act) {  // phase Z''': B_z^T -> accumulator C
     TC w[N], o[N];
-    lds_get<N, 2>(A, t1, t2, w);
+    lds_get<N, 2, TC, LV>(A, t1, t2, w);
     contract_eo<N, TC, 1>(T.eBt, w, o);
-    lds_put<N, 2>(C, t1, t2, o);
+    lds_put<N, 2, TC, LV>(C, t1, t2, o);
   }
 }
 
@@ -492,7 +492,11 @@ __host__ __device__ constexpr int tri_min_waves(int n, int bytes) {
 template <int N, typename TIN, typename TOUT, typename TC, bool AFF>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(tri_min_waves(N, sizeof(TC))))) void k_apply_trilinear(MeshArgs<TC> m, const TIN* __restrict__ x,
                                                             TOUT* __restrict__ y, const int* skip) {
-  constexpr int NN = N * N, N3 = NN * N, EPB = elems_per_block(N), PE = Lay<N, TC>::PE;
+  // FP64 at n = 4: tiles of stride 80 (no more modelled bank conflicts) hold
+  // the face rows, which then need no LDS area of their own (55.8 -> 36.9 KB
+  // per workgroup: three workgroups per CU instead of two)
+  constexpr int LV = (N == 4 && sizeof(TC) == 8) ? 2 : 0;
+  constexpr int NN = N * N, N3 = NN * N, EPB = elems_per_block(N), PE = Lay<N, TC, LV>::PE;
   // the face rows (10 n^2 per element) live in the volume scratch tiles A, B
   // once the volume term is done, when they fit there (n >= 5)
   constexpr bool F_IN_AB = 10 * NN <= 2 * PE;
@@ -518,7 +522,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(tri_min_
     ez = (int)(e / ((int64_t)m.nx * m.ny));
     K = m.K[e];
   }
-  tri_volume<N, TC, TIN, AFF>(m, T, x, e, act, t, t1, t2, K, sX[le], A, B, C);
+  tri_volume<N, TC, TIN, AFF, LV>(m, T, x, e, act, t, t1, t2, K, sX[le], A, B, C);
   // F_IN_AB: the face rows of an element overlap other elements' scratch tiles
   if (F_IN_AB) __syncthreads();
   const TC (&X)[8][3] = sX[le];
@@ -542,18 +546,18 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(tri_min_
   const bool bx0 = act && neighbour<0>(m, ex, ey, ez, 0) < 0;
   const bool by0 = act && neighbour<1>(m, ex, ey, ez, 0) < 0;
   const bool bz0 = act && neighbour<2>(m, ex, ey, ez, 0) < 0;
-  face_term<N, 0, TC, TIN, false, AFF, true>(m, T, x, e, ex, ey, ez, X, sXn[le], K, t1, t2, C, F, act, 1, Gc);
-  face_term<N, 0, TC, TIN, false, AFF>(m, T, x, e, ex, ey, ez, X, sXn[le], K, t1, t2, C, F, bx0, 0, Gc);
+  face_term<N, 0, TC, TIN, false, AFF, true, LV>(m, T, x, e, ex, ey, ez, X, sXn[le], K, t1, t2, C, F, act, 1, Gc);
+  face_term<N, 0, TC, TIN, false, AFF, false, LV>(m, T, x, e, ex, ey, ez, X, sXn[le], K, t1, t2, C, F, bx0, 0, Gc);
   elem_sync<N>();
-  face_term<N, 1, TC, TIN, false, AFF, true>(m, T, x, e, ex, ey, ez, X, sXn[le], K, t1, t2, C, F, act, 1, Gc);
-  face_term<N, 1, TC, TIN, false, AFF>(m, T, x, e, ex, ey, ez, X, sXn[le], K, t1, t2, C, F, by0, 0, Gc);
+  face_term<N, 1, TC, TIN, false, AFF, true, LV>(m, T, x, e, ex, ey, ez, X, sXn[le], K, t1, t2, C, F, act, 1, Gc);
+  face_term<N, 1, TC, TIN, false, AFF, false, LV>(m, T, x, e, ex, ey, ez, X, sXn[le], K, t1, t2, C, F, by0, 0, Gc);
   elem_sync<N>();
-  face_term<N, 2, TC, TIN, false, AFF, true>(m, T, x, e, ex, ey, ez, X, sXn[le], K, t1, t2, C, F, act, 1, Gc);
-  face_term<N, 2, TC, TIN, false, AFF>(m, T, x, e, ex, ey, ez, X, sXn[le], K, t1, t2, C, F, bz0, 0, Gc);
+  face_term<N, 2, TC, TIN, false, AFF, true, LV>(m, T, x, e, ex, ey, ez, X, sXn[le], K, t1, t2, C, F, act, 1, Gc);
+  face_term<N, 2, TC, TIN, false, AFF, false, LV>(m, T, x, e, ex, ey, ez, X, sXn[le], K, t1, t2, C, F, bz0, 0, Gc);
   elem_sync<N>();
   if (act) {
     TC o[N];
-    lds_get<N, 2>(C, t1, t2, o);
+    lds_get<N, 2, TC, LV>(C, t1, t2, o);
     TOUT* py = y + e * N3;
 #pragma unroll
     // y and the face buffer are not read again in this pass: nontemporal
