@@ -76,6 +76,8 @@ __device__ __forceinline__ void cd_line(const Tables<TC>& T, const TC (&a)[N], T
   }
 }
 
+__host__ __device__ constexpr size_t lds_units(size_t bytes) { return (bytes + 1023) / 1024 * 1024; }
+
 template <int N, typename TIN, typename TOUT, typename TC, bool DOT, bool OFF32>
 __global__ __launch_bounds__(apply_block(N)) void k_apply_ppd(MeshArgs<TC> m, const TIN* __restrict__ x,
                                                               TOUT* __restrict__ y, double* partials,
@@ -101,8 +103,11 @@ __global__ __launch_bounds__(apply_block(N)) void k_apply_ppd(MeshArgs<TC> m, co
   // at the cost of one or two more barriers) lets one more workgroup fit in a
   // CU's LDS, they go there (ZR_IN_F) and sP keeps six rows
   constexpr size_t LDS_BASE = (3 * TE * PE + (F_IN_S2 ? 1 : TE * 4 * NN) + NN) * sizeof(TC) + BLOCK / 64 * 8;
-  constexpr size_t LDS_CU = 160 * 1024, MAX_WG = 32 / (BLOCK / 64);  // a CU holds at most 32 waves
-  constexpr size_t WG6 = LDS_CU / (LDS_BASE + TE * 6 * NN * sizeof(TC)), WG8 = LDS_CU / (LDS_BASE + TE * 8 * NN * sizeof(TC));
+  // (a CU holds at most 32 waves and 160 KB of LDS, granted in 1 KB units as
+  // measured: 54.1 KB per workgroup left room for two at n = 7, 53.3 KB for three)
+  constexpr size_t LDS_CU = 160 * 1024, MAX_WG = 32 / (BLOCK / 64);
+  constexpr size_t WG6 = LDS_CU / lds_units(LDS_BASE + TE * 6 * NN * sizeof(TC));
+  constexpr size_t WG8 = LDS_CU / lds_units(LDS_BASE + TE * 8 * NN * sizeof(TC));
   constexpr bool ZR_IN_F = (WG6 < MAX_WG ? WG6 : MAX_WG) > (WG8 < MAX_WG ? WG8 : MAX_WG);
   constexpr int PR = ZR_IN_F ? 6 : 8;  // rows per element in sP
   constexpr int JZ = ZR_IN_F ? 4 : 6;  // first z-face jump row
