@@ -123,15 +123,19 @@ def time_apply(op, x, prec, steps, warmup, torch):
 
 
 def cold_apply(op, x, prec, reps, torch):
-    """Per-launch time with the 256 MB last-level cache flushed between launches."""
+    """Per-launch time with the 256 MB last-level cache flushed between launches.
+    The flush (a 1 GiB read-modify-write) is still running when the events and
+    the apply are enqueued, so the start event is written when the flush ends
+    and the apply follows at once: the interval holds the apply, not the host's
+    launch latency (as it would after an idle GPU)."""
     flush = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
     y = op.apply(x, prec=prec)
     ts = []
     for _ in range(reps):
-        flush.add_(1.0)
         torch.cuda.synchronize()
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
+        flush.add_(1.0)
         e0.record()
         op.apply(x, prec=prec, out=y)
         e1.record()
