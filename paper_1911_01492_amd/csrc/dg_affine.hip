@@ -194,11 +194,11 @@ __global__ __launch_bounds__(apply_block(N), (N == 5 && sizeof(TC) == 8) ? 8 : 1
   auto gco = [&](int f) { return OFF32 ? m.G[(uint32_t)(6 * e + f)] : m.G[6 * e + f]; };
   TC b[N], v[N], w[N];
   // ---------------- X: b_x -> S1
-  face_phase<N, 0, BX, BY, BZ, FS, TC, TIN, TRANS, OFF32>(m, tabs(), x, own, eo, c, o, Nd, t, t1, t2, F, Fe, K, gco(0), gco(1), TC(0), b);
+  face_phase<N, 0, BX, BY, BZ, FS, TC, TIN, TRANS, OFF32>(m, tabs(), x, own, eo, c, o, Nd, t, t1, t2, Fe, K, gco(0), gco(1), TC(0), b);
   lds_put<N, 0, TC, LV>(S1, t1, t2, b);
   lds_sync<XROW>();  // F (read by the x-neighbours) is rewritten by the next phase
   // ---------------- Y: b_y -> S2, M_y b_x -> S1
-  face_phase<N, 1, BX, BY, BZ, FS, TC, TIN, TRANS, OFF32>(m, tabs(), x, own, eo, c, o, Nd, t, t1, t2, F, Fe, K, gco(2), gco(3), TC(0), b);
+  face_phase<N, 1, BX, BY, BZ, FS, TC, TIN, TRANS, OFF32>(m, tabs(), x, own, eo, c, o, Nd, t, t1, t2, Fe, K, gco(2), gco(3), TC(0), b);
   {
     lds_get<N, 1, TC, LV>(S1, t1, t2, v);
     mass_line<N, TC, TRANS>(tabs(), v, w);
@@ -222,7 +222,7 @@ __global__ __launch_bounds__(apply_block(N), (N == 5 && sizeof(TC) == 8) ? 8 : 1
   // ---------------- Z: b_z -> S2, r = M_z S1
   TC r[N], xz[N];  // xz: the thread's z-line of x, for the fused <x, y>
   const TC cr = m.R ? m.R[e] * m.vol : TC(0);
-  face_phase<N, 2, BX, BY, BZ, FS, TC, TIN, TRANS, OFF32>(m, tabs(), x, own, eo, c, o, Nd, t, t1, t2, F, Fe, K, gco(4), gco(5), cr, b,
+  face_phase<N, 2, BX, BY, BZ, FS, TC, TIN, TRANS, OFF32>(m, tabs(), x, own, eo, c, o, Nd, t, t1, t2, Fe, K, gco(4), gco(5), cr, b,
                                                DOT ? xz : nullptr);
   {
     lds_get<N, 2, TC, LV>(S1, t1, t2, v);

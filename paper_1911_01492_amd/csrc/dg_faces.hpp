@@ -100,14 +100,14 @@ __device__ __forceinline__ void lds_sync() {
 
 // One face-aware direction of the affine apply: b = L_D u on this thread's
 // line along axis D (own line from HBM, neighbour face scalars from the
-// brick's exchange area F or from HBM).  Contains one barrier; every thread
-// of the block calls it.  act == false: the lane's element overhangs the
-// mesh (it computes on a clamped element, sees no neighbours, and its result
-// is discarded).
+// brick's exchange area or from HBM; Fe: the element's own slot in that
+// area).  Contains one barrier; every thread of the block calls it.
+// act == false: the lane's element overhangs the mesh (it computes on a
+// clamped element, sees no neighbours, and its result is discarded).
 template <int N, int D, int BX, int BY, int BZ, int FS, typename TC, typename TIN, bool TRANS, bool OFF32>
 __device__ __forceinline__ void face_phase(const MeshArgs<TC>& m, const Tables<TC>& T, const TIN* __restrict__ x,
                                            bool act, uint32_t eo, const int (&c)[3], const int (&o)[3],
-                                           const int (&Nd)[3], int t, int t1, int t2, TC* F, TC* Fe, TC K, TC GL,
+                                           const int (&Nd)[3], int t, int t1, int t2, TC* Fe, TC K, TC GL,
                                            TC GH, TC cr, TC (&b)[N], TC* own = nullptr, TC* nbt = nullptr) {
   constexpr int NN = N * N;
   AxisNeighbours<N, D, BX, BY, BZ, TC, TIN, OFF32> nb;

@@ -162,7 +162,7 @@ __global__ __launch_bounds__(apply_block(N)) void k_apply_ppd(MeshArgs<TC> m, co
   {
     const Tables<TC>& T = tabs();
     const TC GL = gco(0), GH = gco(1);
-    face_phase<N, 0, BX, BY, BZ, FS, TC, TIN, false, OFF32>(m, T, x, own, eo, c, o, Nd, t, t1, t2, F, Fe, K, GL, GH,
+    face_phase<N, 0, BX, BY, BZ, FS, TC, TIN, false, OFF32>(m, T, x, own, eo, c, o, Nd, t, t1, t2, Fe, K, GL, GH,
                                                             TC(0), b, u, tr);
     lds_put<N, 0, TC, LV>(S1, t1, t2, b);
     P[0 * NN + t] = K * u[0] - TC(2) * GL * tr[0];
@@ -175,7 +175,7 @@ __global__ __launch_bounds__(apply_block(N)) void k_apply_ppd(MeshArgs<TC> m, co
   {
     const Tables<TC>& T = tabs();
     const TC GL = gco(2), GH = gco(3);
-    face_phase<N, 1, BX, BY, BZ, FS, TC, TIN, false, OFF32>(m, T, x, own, eo, c, o, Nd, t, t1, t2, F, Fe, K, GL, GH,
+    face_phase<N, 1, BX, BY, BZ, FS, TC, TIN, false, OFF32>(m, T, x, own, eo, c, o, Nd, t, t1, t2, Fe, K, GL, GH,
                                                             TC(0), b, u, tr);
     lds_get<N, 1, TC, LV>(S1, t1, t2, v);
     mass_line<N, TC, false>(T, v, w);
@@ -230,7 +230,7 @@ __global__ __launch_bounds__(apply_block(N)) void k_apply_ppd(MeshArgs<TC> m, co
     const Tables<TC>& T = tabs();
     const TC GL = gco(4), GH = gco(5);
     const TC cr = m.R ? m.R[e] * m.vol : TC(0);
-    face_phase<N, 2, BX, BY, BZ, FS, TC, TIN, false, OFF32>(m, T, x, own, eo, c, o, Nd, t, t1, t2, F, Fe, K, GL, GH,
+    face_phase<N, 2, BX, BY, BZ, FS, TC, TIN, false, OFF32>(m, T, x, own, eo, c, o, Nd, t, t1, t2, Fe, K, GL, GH,
                                                             cr, b, u, tr);
     lds_get<N, 2, TC, LV>(S1, t1, t2, v);
     mass_line<N, TC, false>(T, v, r);
