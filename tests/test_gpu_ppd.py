@@ -93,6 +93,24 @@ def test_transpose_low_precision_and_diagonal():
     assert rel_l2(host(op.diagonal()), A.diagonal()) <= 1e-13
 
 
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 6])
+def test_low_precision_degrees(k):
+    """FP32 and BF16-in applies against the oracle at the degrees whose LDS
+    layout or row placement differs between precisions (the z-face rows in
+    the face-scalar slot at FP32 n = 2, 4, 5 and FP64 n = 2, 3, 4, 7)."""
+    shape = (4, 3, 3) if k <= 4 else (3, 2, 2)
+    banner(f"parallelepiped fp32 / bf16 {shape} k={k}")
+    m, op, x = _case(shape, k, "dirichlet", affine_vertices(*shape), seed=40 + k, reaction=True)
+    A = O.assemble(m)
+    assert rel_l2(host(op.apply(dev(x))), A @ x) <= 1e-12
+    x32 = I.to_f32(x).astype(np.float64)
+    y32 = host(op.apply(dev(I.to_f32(x), torch.float32), prec="f32").double())
+    assert rel_l2(y32, A @ x32) <= 2e-5
+    bits = I.to_bf16_bits(x)
+    yb = host(op.apply(bf16_dev(bits), prec="bf16").double())
+    assert rel_l2(yb, A @ I.bf16_bits_to_f64(bits)) <= 2e-5
+
+
 def test_layered_shear_takes_the_general_kernel():
     """Parallelepipeds that differ from layer to layer are not one affine image
     of the grid: setup keeps the trilinear kernel, still exact."""
