@@ -47,10 +47,11 @@ __device__ __forceinline__ void elem_sync() {
   }
 }
 
+// coordinate a of corner c (bit 0: +x, bit 1: +y, bit 2: +z) of the element
+// at grid position (cx, cy, cz) (the callers know it: no index division)
 template <typename TC>
-__device__ __forceinline__ void corner_of(const MeshArgs<TC>& m, int64_t e, int c, int a, TC& out) {
-  const int ex = (int)(e % m.nx), ey = (int)((e / m.nx) % m.ny), ez = (int)(e / ((int64_t)m.nx * m.ny));
-  const int vx = ex + (c & 1), vy = ey + ((c >> 1) & 1), vz = ez + ((c >> 2) & 1);
+__device__ __forceinline__ void corner_at(const MeshArgs<TC>& m, int cx, int cy, int cz, int c, int a, TC& out) {
+  const int vx = cx + (c & 1), vy = cy + ((c >> 1) & 1), vz = cz + ((c >> 2) & 1);
   const int64_t v = vx + (int64_t)(m.nx + 1) * (vy + (int64_t)(m.ny + 1) * vz);
   out = m.vert[3 * v + a];
 }
@@ -79,8 +80,11 @@ __device__ void face_term(const MeshArgs<TC>& m, const Tables<TC>& T, const TIN*
   if (act) {
     nb = neighbour<D>(m, ex, ey, ez, s);
     // the neighbour's corners, staged once per element (read after the barriers below)
-    if (nb >= 0)
-      for (int q = t; q < 24; q += NN) corner_of(m, nb, q / 3, q % 3, Xn[q / 3][q % 3]);
+    if (nb >= 0) {
+      int g[3] = {ex, ey, ez};
+      g[D] = nb_coord(g[D], s, D == 0 ? m.nx : (D == 1 ? m.ny : m.nz), m.periodic);
+      for (int q = t; q < 24; q += NN) corner_at(m, g[0], g[1], g[2], q / 3, q % 3, Xn[q / 3][q % 3]);
+    }
     TC own[N];
     glb_get<N, D, TC, TIN>(x, e, t1, t2, own);
     Uo = own[s ? N - 1 : 0];
@@ -318,15 +322,17 @@ __device__ void face_term(const MeshArgs<TC>& m, const Tables<TC>& T, const TIN*
 // Volume part of the trilinear apply for the thread's element: the element
 // tile C receives (B^T (x) B^T (x) B^T)(sum_d Dg_d^T g_d + c w |det J| v) of
 // the input x (see the file header), with coefficient K (and the reaction
-// coefficients of m, if any).  Xs: the element's corner slot in LDS (filled
-// here).  All threads of the block call this (it synchronises).
+// coefficients of m, if any); (ex, ey, ez): the element's grid position.
+// Xs: the element's corner slot in LDS (filled here).  All threads of the
+// block call this (it synchronises).
 template <int N, typename TC, typename TIN, bool AFF = false, int LV = 0>
 __device__ void tri_volume(const MeshArgs<TC>& m, const Tables<TC>& T, const TIN* __restrict__ x, int64_t e,
-                           bool act, int t, int t1, int t2, TC K, TC (&Xs)[8][3], TC* A, TC* B, TC* C) {
+                           int ex, int ey, int ez, bool act, int t, int t1, int t2, TC K, TC (&Xs)[8][3], TC* A,
+                           TC* B, TC* C) {
   constexpr int NN = N * N;
   if (act) {
     TC uz[N];
-    for (int q = t; q < 24; q += NN) corner_of(m, e, q / 3, q % 3, Xs[q / 3][q % 3]);
+    for (int q = t; q < 24; q += NN) corner_at(m, ex, ey, ez, q / 3, q % 3, Xs[q / 3][q % 3]);
     glb_get<N, 2, TC, TIN>(x, e, t1, t2, uz);
     TC a[N];
     contract_eo<N, TC, 1>(T.eB, uz, a);  // phase Z: interpolate along z
@@ -522,7 +528,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(tri_min_
     ez = (int)(e / ((int64_t)m.nx * m.ny));
     K = m.K[e];
   }
-  tri_volume<N, TC, TIN, AFF, LV>(m, T, x, e, act, t, t1, t2, K, sX[le], A, B, C);
+  tri_volume<N, TC, TIN, AFF, LV>(m, T, x, e, ex, ey, ez, act, t, t1, t2, K, sX[le], A, B, C);
   // F_IN_AB: the face rows of an element overlap other elements' scratch tiles
   if (F_IN_AB) __syncthreads();
   const TC (&X)[8][3] = sX[le];
@@ -650,7 +656,7 @@ __global__ __launch_bounds__(kBlock) void k_dA_parts_trilinear(MeshArgs<double> 
   }
   MeshArgs<double> m1 = m;
   m1.R = nullptr;
-  tri_volume<N, double, double>(m1, T, v, e, act, t, t1, t2, 1.0, sX[le], A, B, C);
+  tri_volume<N, double, double>(m1, T, v, e, ex, ey, ez, act, t, t1, t2, 1.0, sX[le], A, B, C);
   const double (&X)[8][3] = sX[le];
   double uz[N];
   if (act) glb_get<N, 2, double, double>(u, e, t1, t2, uz);
